@@ -1,0 +1,195 @@
+"""CPU oracle of the sparse scene-flow matching stage (SceneFlowFields,
+arXiv 1710.10096, Section 3.1) -- TEST INFRASTRUCTURE.
+
+A plain C implementation (``sff_oracle.c``) of what the GPU path computes,
+wrapped for NumPy arrays.  Only the tests, the smoke check and the bench's
+CPU-baseline leg use it; the GPU library never imports, links or calls it, and
+it shares no code with that library.
+
+Each wrapper names the passage its C function follows:
+
+* ``philox4x32_10``  -- Philox4x32-10 counter-based generator (Salmon et al.,
+  SC'11), used for the random search.
+* ``lanczos_q14``, ``smooth`` -- scale simulation, Section 3.1
+  "Multi-Scale Propagation" (area downsampling, Lanczos upsampling).
+* ``wht``, ``features`` -- WHT feature vectors, Section 3.1 "Initialization".
+* ``cost`` -- matching cost, eq. (1).
+* ``init_nn`` -- initialisation by nearest neighbours, Section 3.1.
+* ``match_level`` -- propagation and random search, Section 3.1.
+* ``consistency`` -- consistency check, Section 3.1 and tau_c of Section 5.
+* ``match_pair`` -- the whole stage for one pair, Section 3 overview.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i32 = ctypes.c_int
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_lanczos_q14.argtypes = [i32, P]
+        L.orc_smooth.argtypes = [P, i32, i32, i32, i32, P]
+        L.orc_wht.argtypes = [P, i32, i32, i32, i32, P]
+        L.orc_features.argtypes = [P, i32, i32, i32, i32, P]
+        L.orc_cost.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, i32, P]
+        L.orc_cost.restype = ctypes.c_uint32
+        L.orc_init_nn.argtypes = [P, P, P, P] + [i32] * 8 + [P, P]
+        L.orc_match_level.argtypes = ([P, P, P, P] + [i32] * 5 + [ctypes.c_uint64]
+                                      + [i32] * 5 + [P, i32, i32, P, P])
+        L.orc_consistency.argtypes = [P, P, i32, i32, i32, P, P]
+        L.orc_match_pair.argtypes = ([P] + [i32] * 10 + [ctypes.c_uint64, i32] + [P] * 4)
+        L.orc_max_threads.restype = i32
+        L.orc_rs_candidate.argtypes = ([ctypes.c_uint64] + [i32] * 10 + [P, P])
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = _c(ctr, np.uint32)
+    k = _c(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def rs_candidate(seed: int, level: int, s: int, i: int, j: int, Wk: int, it: int, t: int,
+                 rs_r0: int, fmax: int, dmax: int, centre) -> np.ndarray:
+    """Random-search sample t of grid pixel (i, j) in iteration it (Section 3.1)."""
+    c = _c(centre, np.int16)
+    out = np.zeros(4, np.int16)
+    lib().orc_rs_candidate(seed, level, s, i, j, Wk, it, t, rs_r0, fmax, dmax, _p(c), _p(out))
+    return out
+
+
+def lanczos_q14(n: int) -> np.ndarray:
+    t = np.zeros((n, 6), np.int32)
+    lib().orc_lanczos_q14(n, _p(t))
+    return t
+
+
+def smooth(img: np.ndarray, n: int) -> np.ndarray:
+    img = _c(img, np.uint8)
+    H, W, C = img.shape
+    out = np.zeros_like(img)
+    assert lib().orc_smooth(_p(img), H, W, C, n, _p(out)) == 0
+    return out
+
+
+def wht(S: np.ndarray, n: int) -> np.ndarray:
+    S = _c(S, np.uint8)
+    H, W, C = S.shape
+    out = np.zeros((H, W, C, 16), np.int16)
+    assert lib().orc_wht(_p(S), H, W, C, n, _p(out)) == 0
+    return out
+
+
+def features(img: np.ndarray, level: int) -> np.ndarray:
+    img = _c(img, np.uint8)
+    H, W, C = img.shape
+    out = np.zeros((H, W, C, 16), np.int16)
+    assert lib().orc_features(_p(img), H, W, C, level, _p(out)) == 0
+    return out
+
+
+def _descs(descs):
+    ds = [_c(d, np.int16) for d in descs]
+    H, W, C, _ = ds[0].shape
+    return ds, H, W, C
+
+
+def cost(descs, s: int, x: int, y: int, h) -> int:
+    ds, H, W, C = _descs(descs)
+    hh = _c(h, np.int16)
+    return int(lib().orc_cost(*[_p(d) for d in ds], H, W, C, s, x, y, _p(hh)))
+
+
+def grid_shape(H: int, W: int, level: int):
+    n = 1 << level
+    return (H + n - 1) // n, (W + n - 1) // n
+
+
+def init_nn(descs, level: int, s: int, fmax: int, dmax: int, nthreads: int = 0):
+    ds, H, W, C = _descs(descs)
+    Hk, Wk = grid_shape(H, W, level)
+    hyp = np.zeros((Hk, Wk, 4), np.int16)
+    cst = np.zeros((Hk, Wk), np.uint32)
+    assert lib().orc_init_nn(*[_p(d) for d in ds], H, W, C, level, s, fmax, dmax, nthreads,
+                             _p(hyp), _p(cst)) == 0
+    return hyp, cst
+
+
+def match_level(descs, level: int, s: int, seed: int, iters: int, rs_r0: int, rs_samples: int,
+                fmax: int, dmax: int, hyp, cost=None, hyp_coarse=None, order: int = 0,
+                nthreads: int = 0):
+    """Run one level.  With ``hyp_coarse`` the level starts from the hand-off of
+    the coarser field (``hyp``/``cost`` are then outputs only); otherwise it
+    starts from ``hyp``/``cost``.  Returns new (hyp, cost) arrays."""
+    ds, H, W, C = _descs(descs)
+    Hk, Wk = grid_shape(H, W, level)
+    h = np.array(hyp, dtype=np.int16, copy=True, order="C") if hyp is not None else \
+        np.zeros((Hk, Wk, 4), np.int16)
+    c = np.array(cost, dtype=np.uint32, copy=True, order="C") if cost is not None else \
+        np.zeros((Hk, Wk), np.uint32)
+    assert h.shape == (Hk, Wk, 4) and c.shape == (Hk, Wk)
+    hc = None
+    if hyp_coarse is not None:
+        hc = _c(hyp_coarse, np.int16)
+        assert hc.shape[:2] == grid_shape(H, W, level + 1)
+    assert lib().orc_match_level(*[_p(d) for d in ds], H, W, C, level, s, seed, iters, rs_r0,
+                                 rs_samples, fmax, dmax,
+                                 _p(hc) if hc is not None else None, order, nthreads,
+                                 _p(h), _p(c)) == 0
+    return h, c
+
+
+def consistency(hyp_fwd, hyp_inv, tau: int):
+    hf = _c(hyp_fwd, np.int16)
+    hi = _c(hyp_inv, np.int16)
+    H, W, _ = hf.shape
+    valid = np.zeros((H, W), np.uint8)
+    err = np.zeros((H, W), np.uint32)
+    assert lib().orc_consistency(_p(hf), _p(hi), H, W, tau, _p(valid), _p(err)) == 0
+    return valid, err
+
+
+def match_pair(imgs, params: dict, seed: int, nthreads: int = 0):
+    """Whole stage on one pair.  imgs: uint8 [4][H][W][C] (l0, l1, r0, r1).
+    Returns dict with hyp [2][H][W][4] (forward, inverse), cost [2][H][W],
+    valid [H][W], err [H][W]."""
+    im = _c(imgs, np.uint8)
+    _, H, W, C = im.shape
+    hyp = np.zeros((2, H, W, 4), np.int16)
+    cst = np.zeros((2, H, W), np.uint32)
+    valid = np.zeros((H, W), np.uint8)
+    err = np.zeros((H, W), np.uint32)
+    p = params
+    assert lib().orc_match_pair(_p(im), H, W, C, p["levels"], p["iters"], p["rs_r0"],
+                                p["rs_samples"], p["fmax"], p["dmax"], p["tau"], seed, nthreads,
+                                _p(hyp), _p(cst), _p(valid), _p(err)) == 0
+    return dict(hyp=hyp, cost=cst, valid=valid, err=err)

@@ -1,0 +1,149 @@
+"""Independent NumPy routes used to pin the oracle (test code only).
+
+Nothing here re-types the oracle's loops.  The WHT is taken from
+``scipy.linalg.hadamard`` reordered to sequency order.  Descriptor distances go
+through Parseval: the four lowest-sequency length-8 Walsh functions are constant
+on pixel pairs and equal the length-4 sequency-ordered Walsh functions, so the
+4x4 coefficient block of a patch is W4 B W4^T with B the 4x4 matrix of 2x2-bin
+sums, and since W4 W4^T = 4 I the squared distance of two 16-coefficient
+descriptors is 16 times the squared distance of their bin sums.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.linalg import hadamard
+
+
+def sequency_walsh(N: int) -> np.ndarray:
+    """Rows of the Sylvester Hadamard matrix sorted by number of sign changes."""
+    Hm = hadamard(N)
+    changes = (np.diff(Hm, axis=1) != 0).sum(axis=1)
+    return Hm[np.argsort(changes, kind="stable")].astype(np.int64)
+
+
+def patch_indices(H, W, y, x, n):
+    ys = np.clip(y + n * (np.arange(8) - 3), 0, H - 1)
+    xs = np.clip(x + n * (np.arange(8) - 3), 0, W - 1)
+    return ys, xs
+
+
+def patch(img, y, x, c, n):
+    H, W = img.shape[:2]
+    ys, xs = patch_indices(H, W, y, x, n)
+    return img[np.ix_(ys, xs)][:, :, c].astype(np.int64)
+
+
+def wht_block(P: np.ndarray) -> np.ndarray:
+    """4x4 lowest-sequency block of the full 8x8 2-D WHT (a rows, b columns)."""
+    W8 = sequency_walsh(8)
+    return (W8 @ P @ W8.T)[:4, :4]
+
+
+def bin_sums(img, n):
+    """B[y][x][c][4][4]: 2x2-bin sums of the stride-n 8x8 patch at every pixel."""
+    img = np.asarray(img)
+    H, W, C = img.shape
+    ys = np.clip(np.arange(H)[:, None] + n * (np.arange(8)[None, :] - 3), 0, H - 1)  # H x 8
+    xs = np.clip(np.arange(W)[:, None] + n * (np.arange(8)[None, :] - 3), 0, W - 1)  # W x 8
+    P = img.astype(np.int64)[ys[:, None, :, None], xs[None, :, None, :], :]  # H W 8 8 C
+    P = np.moveaxis(P, -1, 2)  # H W C 8 8
+    B = P.reshape(H, W, C, 4, 2, 4, 2).sum(axis=(4, 6))
+    return B
+
+
+def views(imgs, s):
+    l0, l1, r0, r1 = imgs
+    return (l0, l1, r0, r1) if s > 0 else (r1, r0, l1, l0)
+
+
+def targets(x, y, h, s):
+    u, v, d0, d1 = (int(t) for t in h)
+    return [(x + u, y + v), (x - s * d0, y), (x + u - s * d1, y + v)]
+
+
+def cost_parseval(Bs, s, x, y, h):
+    """Eq. (1) cost via bin sums.  Bs: per-view bin-sum maps in (l0, l1, r0, r1)."""
+    R, T, S, X = views(Bs, s)
+    H, W = R.shape[:2]
+    total = 0
+    for img, (tx, ty) in zip((T, S, X), targets(x, y, h, s)):
+        tx = min(max(tx, 0), W - 1)
+        ty = min(max(ty, 0), H - 1)
+        total += 16 * int(((R[y, x] - img[ty, tx]) ** 2).sum())
+    return total
+
+
+def ssd_maps(Bq, Bmap):
+    """16 * sum (Bq - Bmap[y][x])^2 for every pixel of Bmap."""
+    return 16 * ((Bmap - Bq[None, None]) ** 2).sum(axis=(2, 3, 4))
+
+
+def brute_init(Bs, s, level, fmax, dmax):
+    """Exhaustive exact nearest neighbours per view (Section 3.1 initialisation
+    read as exact search), lowest linear target index on ties."""
+    n = 1 << level
+    R, T, S, X = views(Bs, s)
+    H, W = R.shape[:2]
+    Hk, Wk = (H + n - 1) // n, (W + n - 1) // n
+    hyp = np.zeros((Hk, Wk, 4), np.int64)
+    cst = np.zeros((Hk, Wk), np.int64)
+    gy = np.arange(0, H, n)
+    gx = np.arange(0, W, n)
+    for i in range(Hk):
+        for j in range(Wk):
+            x, y = n * j, n * i
+            q = R[y, x]
+            # temporal: grid targets within the box
+            cy = gy[np.abs(gy - y) <= fmax]
+            cx = gx[np.abs(gx - x) <= fmax]
+            e = 16 * ((T[np.ix_(cy, cx)] - q) ** 2).sum(axis=(2, 3, 4))
+            lin = cy[:, None] * W + cx[None, :]
+            k = np.lexsort((lin.ravel(), e.ravel()))[0]
+            ty, tx = cy[k // len(cx)], cx[k % len(cx)]
+            u, v = tx - x, ty - y
+            # stereo, same row
+            d = s * (x - gx)
+            cand = gx[(d >= 0) & (d <= dmax)]
+            e = 16 * ((S[y, cand] - q) ** 2).sum(axis=(1, 2, 3))
+            tx0 = cand[np.lexsort((cand, e))[0]]
+            d0 = s * (x - tx0)
+            # cross, row y + v
+            d = s * (x + u - gx)
+            cand = gx[(d >= 0) & (d <= dmax)]
+            e = 16 * ((X[y + v, cand] - q) ** 2).sum(axis=(1, 2, 3))
+            tx1 = cand[np.lexsort((cand, e))[0]]
+            d1 = s * (x + u - tx1)
+            hyp[i, j] = (u, v, d0, d1)
+            cst[i, j] = cost_parseval(Bs, s, x, y, hyp[i, j])
+    return hyp, cst
+
+
+def exhaustive_min(Bs, s, level, fmax, dmax):
+    """Minimum of eq. (1) over every integer hypothesis in the search bounds,
+    per grid pixel (tiny images only)."""
+    n = 1 << level
+    R, T, S, X = views(Bs, s)
+    H, W = R.shape[:2]
+    Hk, Wk = (H + n - 1) // n, (W + n - 1) // n
+    out = np.zeros((Hk, Wk), np.int64)
+    uu = np.arange(-fmax, fmax + 1)
+    dd = np.arange(0, dmax + 1)
+    for i in range(Hk):
+        for j in range(Wk):
+            x, y = n * j, n * i
+            q = R[y, x]
+            ty = np.clip(y + uu, 0, H - 1)
+            tx = np.clip(x + uu, 0, W - 1)
+            eT = 16 * ((T[np.ix_(ty, tx)] - q) ** 2).sum(axis=(2, 3, 4))  # [v][u]
+            sx = np.clip(x - s * dd, 0, W - 1)
+            eS = 16 * ((S[y, sx] - q) ** 2).sum(axis=(1, 2, 3))  # [d0]
+            best = None
+            for vi, v in enumerate(uu):
+                yy = min(max(y + v, 0), H - 1)
+                # cross: x + u - s d1 for every (u, d1)
+                xx = np.clip(x + uu[:, None] - s * dd[None, :], 0, W - 1)
+                eX = 16 * ((X[yy][xx] - q) ** 2).sum(axis=(2, 3, 4))  # [u][d1]
+                tot = (eT[vi][:, None] + eX).min() + eS.min()
+                best = tot if best is None else min(best, tot)
+            out[i, j] = best
+    return out
