@@ -1,0 +1,163 @@
+/*
+ * sff.h -- C ABI of libsff, the MI355X (gfx950) implementation of the sparse
+ * scene-flow matching stage of SceneFlowFields (Schuster, Wasenmueller,
+ * Kuschk, Bailer, Stricker; arXiv 1710.10096, Section 3.1 "Sparse
+ * Correspondences").
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Array pointers are DEVICE pointers (HIP global memory) unless the comment
+ *    says "host".  The caller allocates and owns every buffer; the library
+ *    neither allocates device memory, nor keeps pointers after the call
+ *    returns, nor synchronises.
+ *  - All work is enqueued on `stream` (a hipStream_t; NULL = the default
+ *    stream).  Results are ready when the stream reaches that point.
+ *  - Arguments are checked on the host before anything is enqueued.  On an
+ *    error the call returns a non-zero sff_status, enqueues nothing and leaves
+ *    every output untouched.  A launch failure reported by the runtime after
+ *    enqueueing returns SFF_ERR_HIP; faults inside kernels surface at the
+ *    caller's next synchronisation.
+ *  - The library is stateless and thread-safe.
+ *
+ * Data layouts (row-major, no padding)
+ *  - image  uint8  [n][H][W][C]                 C = 1..4 channels
+ *  - desc   int16  [n][H][W][C][16]             16 = 4x4 lowest-sequency WHT
+ *                                                coefficients, index a*4 + b
+ *                                                (a vertical, b horizontal)
+ *  - the four views of a pair are stored consecutively in the canonical order
+ *    (I_l^0, I_l^1, I_r^0, I_r^1); `batch` pairs make n = 4 * batch images.
+ *  - hyp    int16  [ndir][batch][Hk][Wk][4]     (u, v, d0, d1), full-res px
+ *  - cost   uint32 [ndir][batch][Hk][Wk]
+ *    with level k, n = 2^k, Hk = ceil(H / n), Wk = ceil(W / n); ndir = 2 when
+ *    dir = SFF_DIR_BOTH (forward field first), else 1.
+ */
+#ifndef SFF_H
+#define SFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SFF_OK = 0,
+    SFF_ERR_INVALID_ARG = 1, /* bad pointer, size or parameter            */
+    SFF_ERR_UNSUPPORTED = 2, /* valid but outside what this build handles */
+    SFF_ERR_HIP = 3,         /* the HIP runtime reported an error         */
+    SFF_ERR_WORKSPACE = 4    /* workspace missing or too small            */
+} sff_status;
+
+/* Direction of a field (Section 3.1, "Consistency Check"): the forward field
+ * has reference I_l^0; the inverse field has reference I_r^1, with temporal
+ * order and viewpoints swapped. */
+enum { SFF_DIR_FORWARD = 1, SFF_DIR_INVERSE = -1, SFF_DIR_BOTH = 0 };
+
+/* Matcher parameters.  Limits checked by every call:
+ *   1 <= H, W <= 16384; 1 <= C <= 4; 1 <= levels <= 5; 0 <= iters <= 64;
+ *   0 <= rs_samples <= 16; 1 <= rs_r0 <= 4096; 0 <= fmax, dmax <= 8192;
+ *   0 <= tau <= 8192.                                                        */
+typedef struct sff_params {
+    int32_t H, W, C;    /* full-resolution image size and channel count       */
+    int32_t levels;     /* pyramid levels K (k subscales + full resolution)   */
+    int32_t iters;      /* propagation + random-search iterations per level   */
+    int32_t rs_r0;      /* random-search radius of sample 0, in level pixels  */
+    int32_t rs_samples; /* random-search samples per pixel and half-step      */
+    int32_t fmax;       /* |u|, |v| <= fmax (full-res px)                     */
+    int32_t dmax;       /* 0 <= d0, d1 <= dmax (full-res px)                  */
+    int32_t tau;        /* consistency threshold tau_c in px (Section 5: 1)   */
+} sff_params;
+
+/* Human-readable text for a status code (static storage; never NULL). */
+const char* sff_status_string(int32_t status);
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int32_t sff_version(void);
+
+/* Host-only helper: the Q14 Lanczos-3 weights the smoothing uses for pyramid
+ * factor n (2 <= n <= 16), table[p * 6 + t] for phase p = x mod n and tap t
+ * at floor((x + 0.5) / n - 0.5) - 2 + t.  `table` is a HOST array of n * 6
+ * int32.  Returns SFF_ERR_INVALID_ARG for a bad n or NULL table. */
+sff_status sff_lanczos_q14(int32_t n, int32_t* table);
+
+/* Device workspace (bytes) that sff_wht_features needs for `nimg` images at
+ * `level`; 0 for level 0. */
+size_t sff_wht_workspace_bytes(const sff_params* p, int32_t nimg, int32_t level);
+
+/* WHT feature vectors at one pyramid level (Section 3.1, "Initialization" --
+ * WHT features; "Multi-Scale Propagation" -- scale simulation).
+ *   For level k >= 1 each image is first smoothed: area-based downsampling by
+ *   n = 2^k (rounded block mean, replicated border), then separable Lanczos-3
+ *   upsampling back to H x W with Q14 weights (sff_lanczos_q14), each pass
+ *   rounded, the second clamped to 0..255.  Level 0 uses the image itself.
+ *   Then, at EVERY full-resolution pixel q and channel c, the 8x8 patch sampled
+ *   every n-th pixel at offsets -3..+4 (replicated border) is transformed by
+ *   the unnormalised 2-D Walsh-Hadamard transform and the 16 coefficients of
+ *   vertical/horizontal sequency < 4 are stored (exact in int16).
+ * img:  [nimg][H][W][C] uint8, read only.
+ * desc: [nimg][H][W][C][16] int16, written.
+ * workspace: device buffer of at least sff_wht_workspace_bytes(p, nimg, level)
+ *   bytes (may be NULL at level 0); contents on entry are ignored.
+ * Errors: SFF_ERR_INVALID_ARG (NULL pointers, nimg < 1, level outside
+ *   0..levels-1, bad params), SFF_ERR_WORKSPACE (workspace too small). */
+sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_t level, const uint8_t* img,
+                            int16_t* desc, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Initialisation at the coarsest level k = levels - 1 (Section 3.1,
+ * "Initialization"), read as exact nearest neighbours in descriptor space:
+ * for every grid pixel p = (n j, n i), among grid targets (multiples of n)
+ * inside the image,
+ *   temporal partner: the box |u|, |v| <= fmax;
+ *   stereo partner:   the same row (epipolar), 0 <= d0 <= dmax;
+ *   cross partner:    row y + v*, 0 <= d1 <= dmax, target x + u* - s d1;
+ * each the exact argmin of the descriptor SSD with ties to the smallest target
+ * index y*W + x.  The combination is the hypothesis; its cost is eq. (1).
+ * desc: level-(levels-1) descriptors [batch][4][H][W][C][16].
+ * dir:  SFF_DIR_FORWARD, SFF_DIR_INVERSE or SFF_DIR_BOTH.
+ * hyp/cost: coarsest-level field, written.
+ * Errors: SFF_ERR_INVALID_ARG. */
+sff_status sff_init_nn(const sff_params* p, int32_t batch, int32_t dir, const int16_t* desc,
+                       int16_t* hyp, uint32_t* cost, void* stream);
+
+/* Propagation and random search at one level (Section 3.1, "Multi-Scale
+ * Propagation"), eq. (1) cost: sum over the temporal (x + u, y + v), stereo
+ * (x - s d0, y) and cross (x + u - s d1, y + v) partners of the squared
+ * distance of level-k descriptors, targets clamped to the image, uint32.
+ *   hand-off (hyp_coarse != NULL): every pixel starts from its parent's vector
+ *     hyp_coarse[i >> 1][j >> 1] with its cost recomputed at this level;
+ *     otherwise hyp/cost already hold the starting field (the initialisation).
+ *   iterations: red pixels ((i + j) even) then black ones; each takes the
+ *     cheapest of [own, left, up, right, down] under strict improvement, then
+ *     rs_samples random-search samples around that vector: sample t moves each
+ *     component by a uniform integer in [-r_t, r_t], r_t = max(1, rs_r0 >> t)
+ *     * n, clamped to |u|,|v| <= fmax, 0 <= d <= dmax; Philox4x32-10 with key
+ *     = seeds[b] and counter (i*Wk + j, it, (k << 16) | (t << 8) | (s < 0), 0),
+ *     offset = floor(x_c (2 r_t + 1) / 2^32) - r_t; kept on strict improvement.
+ * desc:  level-k descriptors [batch][4][H][W][C][16].
+ * seeds: [batch] uint64, device.
+ * hyp_coarse: level-(k+1) field [ndir][batch][H(k+1)][W(k+1)][4] or NULL;
+ *   must not overlap hyp.
+ * hyp/cost: level-k field, read and written in place.
+ * Errors: SFF_ERR_INVALID_ARG (also for level >= levels - 1 with a non-NULL
+ *   hyp_coarse, and for overlapping hyp/hyp_coarse). */
+sff_status sff_match_level(const sff_params* p, int32_t batch, int32_t dir, int32_t level,
+                           const int16_t* desc, const uint64_t* seeds, const int16_t* hyp_coarse,
+                           int16_t* hyp, uint32_t* cost, void* stream);
+
+/* Consistency check (Section 3.1, "Consistency Check"; tau_c, Section 5).
+ * For every pixel p with forward vector (u, v, d0, d1): if a forward target
+ * lies outside the image the match is invalid and err = UINT32_MAX; otherwise,
+ * with (u', v', d0', d1') the inverse field at q = (x + u - d1, y + v),
+ * e0 = d0 - d1', e1 = d1 - d0', ef = (u + u' + d1' - d0', v + v');
+ * valid = 1 iff e0^2, e1^2 and |ef|^2 are all <= tau^2; err = their maximum.
+ * hyp_fwd, hyp_inv: level-0 fields [batch][H][W][4].
+ * valid: [batch][H][W] uint8 (0/1), err: [batch][H][W] uint32, written.
+ * Errors: SFF_ERR_INVALID_ARG. */
+sff_status sff_consistency(const sff_params* p, int32_t batch, const int16_t* hyp_fwd,
+                           const int16_t* hyp_inv, uint8_t* valid, uint32_t* err, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFF_H */

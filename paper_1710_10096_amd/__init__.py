@@ -1,0 +1,11 @@
+"""MI355X (gfx950) implementation of the sparse scene-flow matching stage of
+SceneFlowFields (arXiv 1710.10096, Section 3.1): WHT descriptors, exact-NN
+initialisation, red-black propagation with Philox random search, and the
+forward/inverse consistency check, as HIP kernels behind the C ABI of
+include/sff.h.
+"""
+from ._native import SffParams, LIB_PATH, EXPORTS  # noqa: F401
+from .api import (DIR_BOTH, DIR_FORWARD, DIR_INVERSE,  # noqa: F401
+                  SffError, grid_shape, sff_consistency, sff_init_nn, sff_lanczos_q14,
+                  sff_match_level, sff_version, sff_wht_features, sff_wht_workspace_bytes)
+from .pipeline import PairMatcher, match_pairs  # noqa: F401

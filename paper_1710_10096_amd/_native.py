@@ -1,0 +1,63 @@
+"""ctypes loader for libsff.so (built in-tree by ``build.py``).
+
+There is no fallback: if the HIP library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsff.so")
+
+
+class SffParams(ctypes.Structure):
+    """Mirror of ``sff_params`` in include/sff.h."""
+
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("C", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("rs_r0", ctypes.c_int32), ("rs_samples", ctypes.c_int32),
+                ("fmax", ctypes.c_int32), ("dmax", ctypes.c_int32), ("tau", ctypes.c_int32)]
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "SffParams":
+        return cls(**{k: int(d[k]) for k, _ in cls._fields_})
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+EXPORTS = ("sff_status_string", "sff_version", "sff_lanczos_q14", "sff_wht_workspace_bytes",
+           "sff_wht_features", "sff_init_nn", "sff_match_level", "sff_consistency")
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1710_10096_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    PP = ctypes.POINTER(SffParams)
+    L.sff_status_string.argtypes = [i32]
+    L.sff_status_string.restype = ctypes.c_char_p
+    L.sff_version.argtypes = []
+    L.sff_version.restype = i32
+    L.sff_lanczos_q14.argtypes = [i32, P]
+    L.sff_lanczos_q14.restype = i32
+    L.sff_wht_workspace_bytes.argtypes = [PP, i32, i32]
+    L.sff_wht_workspace_bytes.restype = ctypes.c_size_t
+    L.sff_wht_features.argtypes = [PP, i32, i32, P, P, P, ctypes.c_size_t, P]
+    L.sff_wht_features.restype = i32
+    L.sff_init_nn.argtypes = [PP, i32, i32, P, P, P, P]
+    L.sff_init_nn.restype = i32
+    L.sff_match_level.argtypes = [PP, i32, i32, i32, P, P, P, P, P, P]
+    L.sff_match_level.restype = i32
+    L.sff_consistency.argtypes = [PP, i32, P, P, P, P, P]
+    L.sff_consistency.restype = i32
+    _lib = L
+    return L

@@ -1,0 +1,47 @@
+// Device-side descriptor helpers of libsff: loading C x 16 int16 WHT
+// coefficients and their exact squared distance with packed 16-bit subtracts
+// and 2-way int16 dot products (v_pk_sub_i16, v_dot2c_i32_i16).
+#pragma once
+
+#include "sff_internal.hpp"
+
+namespace sff {
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+
+// C channels x 16 coefficients = 8 C packed int16 pairs.
+template <int C>
+struct Desc {
+    uint32_t w[8 * C];
+};
+
+template <int C>
+__device__ __forceinline__ Desc<C> load_desc(const int16_t* __restrict__ map, size_t pix) {
+    const uint4* p = reinterpret_cast<const uint4*>(map + pix * (size_t)(16 * C));
+    Desc<C> d;
+#pragma unroll
+    for (int k = 0; k < 2 * C; ++k) {
+        const uint4 v = p[k];
+        d.w[4 * k + 0] = v.x;
+        d.w[4 * k + 1] = v.y;
+        d.w[4 * k + 2] = v.z;
+        d.w[4 * k + 3] = v.w;
+    }
+    return d;
+}
+
+// Squared distance of two descriptors.  Coefficients lie in [-16320, 16320],
+// so each difference fits int16; by Parseval one channel contributes at most
+// 64 * 64 * 255^2 < 2^28, four channels stay below 2^31.
+template <int C>
+__device__ __forceinline__ uint32_t desc_ssd(const Desc<C>& a, const Desc<C>& b) {
+    int acc = 0;
+#pragma unroll
+    for (int k = 0; k < 8 * C; ++k) {
+        const short2v d = __builtin_bit_cast(short2v, a.w[k]) - __builtin_bit_cast(short2v, b.w[k]);
+        acc = __builtin_amdgcn_sdot2(d, d, acc, false);
+    }
+    return (uint32_t)acc;
+}
+
+}  // namespace sff

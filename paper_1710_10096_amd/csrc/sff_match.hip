@@ -1,0 +1,233 @@
+// Multi-scale propagation and random search at one level (SceneFlowFields,
+// Section 3.1, "Multi-Scale Propagation"), with the eq. (1) matching cost on
+// WHT descriptors.
+//
+// Schedule: per iteration a red half-step (pixels with (i + j) even) then a
+// black one.  Pixels of one colour only read the other colour's vectors, so a
+// half-step is a race-free Jacobi sweep and its result does not depend on the
+// order in which threads run.  Each pixel: cheapest of [own, left, up, right,
+// down] under strict improvement, then rs_samples random-search samples around
+// that vector (Philox4x32-10), kept on strict improvement.
+//
+// The hand-off from the coarser level is fused into iteration 0: a pixel whose
+// level-k vector has not been written yet reads its parent's vector from the
+// coarse field and computes its cost at this level.
+#include "sff_device.hpp"
+
+namespace sff {
+namespace {
+
+struct MatchArgs {
+    const int16_t* desc;        // [batch][4][H][W][C][16]
+    const uint64_t* seeds;      // [batch]
+    const int16_t* hyp_coarse;  // [ndir][batch][Hc][Wc][4] or null
+    int16_t* hyp;               // [ndir][batch][Hk][Wk][4]
+    uint32_t* cost;             // [ndir][batch][Hk][Wk]
+    int H, W, n, level, Hk, Wk, Hc, Wc;
+    int rs_r0, rs_samples, fmax, dmax;
+    int batch, dir0, ndir;
+};
+
+struct Hyp {
+    int u, v, d0, d1;
+};
+
+__device__ __forceinline__ Hyp unpack(uint2 h) {
+    Hyp r;
+    r.u = (int)(int16_t)(h.x & 0xFFFFu);
+    r.v = (int)(int16_t)(h.x >> 16);
+    r.d0 = (int)(int16_t)(h.y & 0xFFFFu);
+    r.d1 = (int)(int16_t)(h.y >> 16);
+    return r;
+}
+
+__device__ __forceinline__ uint2 pack(const Hyp& h) {
+    uint2 r;
+    r.x = (uint32_t)(uint16_t)(int16_t)h.u | ((uint32_t)(uint16_t)(int16_t)h.v << 16);
+    r.y = (uint32_t)(uint16_t)(int16_t)h.d0 | ((uint32_t)(uint16_t)(int16_t)h.d1 << 16);
+    return r;
+}
+
+template <int C>
+struct Views {
+    const int16_t *T, *S, *X;
+    int H, W, s;
+
+    // eq. (1): temporal (x+u, y+v), stereo (x - s d0, y), cross (x+u - s d1, y+v),
+    // each target clamped to the image.
+    __device__ __forceinline__ uint32_t cost(const Desc<C>& ref, int x, int y, const Hyp& h) const {
+        const int ty = clampi(y + h.v, 0, H - 1);
+        const int txT = clampi(x + h.u, 0, W - 1);
+        const int txS = clampi(x - s * h.d0, 0, W - 1);
+        const int txX = clampi(x + h.u - s * h.d1, 0, W - 1);
+        const Desc<C> dT = load_desc<C>(T, (size_t)ty * W + txT);
+        const Desc<C> dS = load_desc<C>(S, (size_t)y * W + txS);
+        const Desc<C> dX = load_desc<C>(X, (size_t)ty * W + txX);
+        return desc_ssd<C>(ref, dT) + desc_ssd<C>(ref, dS) + desc_ssd<C>(ref, dX);
+    }
+};
+
+// mode: 0 = regular half-step; 1 = iteration-0 red half after a hand-off (own
+// and neighbours from the coarse field); 2 = iteration-0 black half after a
+// hand-off (own from the coarse field, neighbours already at this level);
+// 3 = hand-off only (no propagation or search), used when iters == 0.
+template <int C>
+__global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int colour, int mode) {
+    const int i = blockIdx.y * 4 + threadIdx.y;
+    const int jc = blockIdx.x * 64 + threadIdx.x;
+    const int z = blockIdx.z;
+    if (i >= a.Hk) return;
+    const int j = mode == 3 ? jc : 2 * jc + ((i + colour) & 1);
+    if (j >= a.Wk) return;
+    const int di = z / a.batch, b = z - di * a.batch;
+    const int s = (a.ndir == 2) ? (di == 0 ? 1 : -1) : a.dir0;
+    const size_t mapsz = (size_t)a.H * a.W * 16 * C;
+    const int16_t* base = a.desc + (size_t)b * 4 * mapsz;
+    Views<C> V;
+    V.T = base + (size_t)(s > 0 ? 1 : 2) * mapsz;
+    V.S = base + (size_t)(s > 0 ? 2 : 1) * mapsz;
+    V.X = base + (size_t)(s > 0 ? 3 : 0) * mapsz;
+    V.H = a.H;
+    V.W = a.W;
+    V.s = s;
+    const int16_t* R = base + (size_t)(s > 0 ? 0 : 3) * mapsz;
+    const int n = a.n;
+    const int x = n * j, y = n * i;
+    const Desc<C> ref = load_desc<C>(R, (size_t)y * a.W + x);
+
+    const uint2* field = reinterpret_cast<const uint2*>(a.hyp) + (size_t)z * a.Hk * a.Wk;
+    const uint2* coarse = reinterpret_cast<const uint2*>(a.hyp_coarse) + (size_t)z * a.Hc * a.Wc;
+    const size_t o = (size_t)i * a.Wk + j;
+
+    Hyp best;
+    uint32_t bestc;
+    if (mode == 0) {
+        best = unpack(field[o]);
+        bestc = a.cost[(size_t)z * a.Hk * a.Wk + o];
+    } else {
+        best = unpack(coarse[(size_t)(i >> 1) * a.Wc + (j >> 1)]);
+        bestc = V.cost(ref, x, y, best);
+    }
+    if (mode != 3) {
+        // propagation: left, up, right, down
+        const int ni[4] = {i, i - 1, i, i + 1};
+        const int nj[4] = {j - 1, j, j + 1, j};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (ni[q] < 0 || ni[q] >= a.Hk || nj[q] < 0 || nj[q] >= a.Wk) continue;
+            const Hyp h = unpack(mode == 1 ? coarse[(size_t)(ni[q] >> 1) * a.Wc + (nj[q] >> 1)]
+                                           : field[(size_t)ni[q] * a.Wk + nj[q]]);
+            const uint32_t c = V.cost(ref, x, y, h);
+            if (c < bestc) {
+                bestc = c;
+                best = h;
+            }
+        }
+        // random search around the propagated vector
+        const Hyp centre = best;
+        const uint64_t seed = a.seeds[b];
+        const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+        for (int t = 0; t < a.rs_samples; ++t) {
+            const int r = max(1, a.rs_r0 >> t) * n;
+            U4 ctr;
+            ctr.x = (uint32_t)(i * a.Wk + j);
+            ctr.y = (uint32_t)it;
+            ctr.z = ((uint32_t)a.level << 16) | ((uint32_t)t << 8) | (s < 0 ? 1u : 0u);
+            ctr.w = 0u;
+            const U4 rnd = philox4x32_10(ctr, k0, k1);
+            Hyp c;
+            c.u = clampi(centre.u + uniform_offset(rnd.x, r), -a.fmax, a.fmax);
+            c.v = clampi(centre.v + uniform_offset(rnd.y, r), -a.fmax, a.fmax);
+            c.d0 = clampi(centre.d0 + uniform_offset(rnd.z, r), 0, a.dmax);
+            c.d1 = clampi(centre.d1 + uniform_offset(rnd.w, r), 0, a.dmax);
+            const uint32_t cc = V.cost(ref, x, y, c);
+            if (cc < bestc) {
+                bestc = cc;
+                best = c;
+            }
+        }
+    }
+    reinterpret_cast<uint2*>(a.hyp)[(size_t)z * a.Hk * a.Wk + o] = pack(best);
+    a.cost[(size_t)z * a.Hk * a.Wk + o] = bestc;
+}
+
+template <int C>
+sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
+    const int half_w = (a.Wk + 1) / 2;
+    const dim3 grid_half((half_w + 63) / 64, (a.Hk + 3) / 4, a.ndir * a.batch);
+    const dim3 block(64, 4);
+    if (a.hyp_coarse && iters == 0) {
+        const dim3 grid_all((a.Wk + 63) / 64, (a.Hk + 3) / 4, a.ndir * a.batch);
+        hipLaunchKernelGGL(half_step_kernel<C>, grid_all, block, 0, st, a, 0, 0, 3);
+        return launch_status();
+    }
+    for (int it = 0; it < iters; ++it)
+        for (int colour = 0; colour < 2; ++colour) {
+            int mode = 0;
+            if (a.hyp_coarse && it == 0) mode = colour == 0 ? 1 : 2;
+            hipLaunchKernelGGL(half_step_kernel<C>, grid_half, block, 0, st, a, it, colour, mode);
+        }
+    return launch_status();
+}
+
+}  // namespace
+}  // namespace sff
+
+using namespace sff;
+
+extern "C" sff_status sff_match_level(const sff_params* p, int32_t batch, int32_t dir,
+                                      int32_t level, const int16_t* desc, const uint64_t* seeds,
+                                      const int16_t* hyp_coarse, int16_t* hyp, uint32_t* cost,
+                                      void* stream) {
+    if (!params_ok(p) || batch < 1 || batch > 32767 || (dir != 1 && dir != -1 && dir != 0) ||
+        level < 0 || level >= p->levels || !desc || !seeds || !hyp || !cost)
+        return SFF_ERR_INVALID_ARG;
+    if (hyp_coarse && level >= p->levels - 1) return SFF_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(desc) & 15) != 0 || (reinterpret_cast<uintptr_t>(hyp) & 7) != 0 ||
+        (reinterpret_cast<uintptr_t>(cost) & 3) != 0 ||
+        (reinterpret_cast<uintptr_t>(hyp_coarse) & 7) != 0)
+        return SFF_ERR_INVALID_ARG;
+    const LevelGeom g = level_geom(*p, level);
+    const int ndir = dir == 0 ? 2 : 1;
+    const size_t fine_bytes = (size_t)ndir * batch * g.Hk * g.Wk * 8;
+    if (hyp_coarse) {
+        const LevelGeom gc = level_geom(*p, level + 1);
+        const size_t coarse_bytes = (size_t)ndir * batch * gc.Hk * gc.Wk * 8;
+        const uintptr_t f0 = reinterpret_cast<uintptr_t>(hyp), f1 = f0 + fine_bytes;
+        const uintptr_t c0 = reinterpret_cast<uintptr_t>(hyp_coarse), c1 = c0 + coarse_bytes;
+        if (f0 < c1 && c0 < f1) return SFF_ERR_INVALID_ARG;
+    }
+    MatchArgs a;
+    a.desc = desc;
+    a.seeds = seeds;
+    a.hyp_coarse = hyp_coarse;
+    a.hyp = hyp;
+    a.cost = cost;
+    a.H = p->H;
+    a.W = p->W;
+    a.n = g.n;
+    a.level = level;
+    a.Hk = g.Hk;
+    a.Wk = g.Wk;
+    if (hyp_coarse) {
+        const LevelGeom gc = level_geom(*p, level + 1);
+        a.Hc = gc.Hk;
+        a.Wc = gc.Wk;
+    } else {
+        a.Hc = a.Wc = 0;
+    }
+    a.rs_r0 = p->rs_r0;
+    a.rs_samples = p->rs_samples;
+    a.fmax = p->fmax;
+    a.dmax = p->dmax;
+    a.batch = batch;
+    a.ndir = ndir;
+    a.dir0 = dir == 0 ? 1 : dir;
+    hipStream_t st = as_stream(stream);
+    switch (p->C) {
+        case 1: return run_level<1>(a, p->iters, st);
+        case 2: return run_level<2>(a, p->iters, st);
+        case 3: return run_level<3>(a, p->iters, st);
+        default: return run_level<4>(a, p->iters, st);
+    }
+}

@@ -1,0 +1,15 @@
+// Status strings and version of libsff.
+#include "sff.h"
+
+extern "C" const char* sff_status_string(int32_t status) {
+    switch (status) {
+        case SFF_OK: return "ok";
+        case SFF_ERR_INVALID_ARG: return "invalid argument";
+        case SFF_ERR_UNSUPPORTED: return "unsupported configuration";
+        case SFF_ERR_HIP: return "HIP runtime error";
+        case SFF_ERR_WORKSPACE: return "workspace missing or too small";
+        default: return "unknown status";
+    }
+}
+
+extern "C" int32_t sff_version(void) { return 100; }  // 0.1.0

@@ -1,0 +1,68 @@
+"""The matching stage for a batch of pairs (SceneFlowFields, Section 3
+overview, up to the consistency check), as a sequence of libsff calls on one
+stream: for levels K-1 .. 0, WHT features of the four views, exact-NN
+initialisation at the coarsest level, propagation + random search with the
+hand-off from the coarser level; then the consistency check at level 0.
+Forward and inverse fields run together (SFF_DIR_BOTH).
+
+Buffers are allocated once per shape; a call only enqueues kernels.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import api
+from ._native import SffParams
+
+
+class PairMatcher:
+    def __init__(self, params, batch: int = 1, device: str | torch.device = "cuda"):
+        self.p = params if isinstance(params, SffParams) else SffParams.from_dict(params)
+        self.batch = int(batch)
+        p, B = self.p, self.batch
+        dev = torch.device(device)
+        self.desc = torch.empty((B, 4, p.H, p.W, p.C, 16), dtype=torch.int16, device=dev)
+        ws = max(api.sff_wht_workspace_bytes(p, 4 * B, k) for k in range(p.levels))
+        self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
+        self.hyp, self.cost = [], []
+        for k in range(p.levels):
+            Hk, Wk = api.grid_shape(p, k)
+            self.hyp.append(torch.empty((2, B, Hk, Wk, 4), dtype=torch.int16, device=dev))
+            self.cost.append(torch.empty((2, B, Hk, Wk), dtype=torch.int32, device=dev))
+        self.valid = torch.empty((B, p.H, p.W), dtype=torch.uint8, device=dev)
+        self.err = torch.empty((B, p.H, p.W), dtype=torch.int32, device=dev)
+
+    def run(self, imgs: torch.Tensor, seeds: torch.Tensor, stream=None, mark=None) -> dict:
+        """imgs uint8 [batch][4][H][W][C] (l0, l1, r0, r1); seeds int64 [batch].
+        ``mark(name)``, if given, is called before the first and after every
+        library call (timing hooks)."""
+        mk = mark if mark is not None else (lambda name: None)
+        p, B = self.p, self.batch
+        if tuple(imgs.shape) != (B, 4, p.H, p.W, p.C):
+            raise ValueError(f"imgs must be [{B}, 4, {p.H}, {p.W}, {p.C}]")
+        flat_img = imgs.view(4 * B, p.H, p.W, p.C)
+        flat_desc = self.desc.view(4 * B, p.H, p.W, p.C, 16)
+        top = p.levels - 1
+        mk("start")
+        for k in range(top, -1, -1):
+            api.sff_wht_features(p, flat_img, k, flat_desc, self.ws, stream)
+            mk(f"features:L{k}")
+            if k == top:
+                api.sff_init_nn(p, self.desc, api.DIR_BOTH, self.hyp[k], self.cost[k], stream)
+                mk(f"init:L{k}")
+                api.sff_match_level(p, self.desc, api.DIR_BOTH, k, seeds, self.hyp[k],
+                                    self.cost[k], None, stream)
+            else:
+                api.sff_match_level(p, self.desc, api.DIR_BOTH, k, seeds, self.hyp[k],
+                                    self.cost[k], self.hyp[k + 1], stream)
+            mk(f"match:L{k}")
+        api.sff_consistency(p, self.hyp[0][0], self.hyp[0][1], self.valid, self.err, stream)
+        mk("consistency:L0")
+        return dict(hyp=self.hyp[0], cost=self.cost[0], valid=self.valid, err=self.err)
+
+
+def match_pairs(params, imgs: torch.Tensor, seeds: torch.Tensor) -> dict:
+    """One-shot convenience wrapper around PairMatcher (returns copies)."""
+    m = PairMatcher(params, imgs.shape[0], imgs.device)
+    out = m.run(imgs, seeds)
+    return {k: v.clone() for k, v in out.items()}

@@ -1,0 +1,134 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol include/sff.h declares, and rejects bad arguments on the host before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1710_10096_amd import _native
+from paper_1710_10096_amd._native import SffParams
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _gpu_visible():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+# The argument checks below pass fake device addresses that validation must
+# reject; they are host-logic tests and never run where a GPU is visible.
+host_only = pytest.mark.skipif(_gpu_visible(), reason="host-only validation test (fake pointers)")
+
+
+def declared_symbols():
+    names = []
+    for f in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            # declarations: lines outside comment blocks naming sff_* before "("
+            names += re.findall(r"^(?!\s*(?:/\*|\*))[^\n;(]*?\b(sff_[a-z0-9_]+)\s*\(", txt,
+                                re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _native.lib()
+    decl = declared_symbols()
+    assert len(decl) >= 8
+    for name in decl:
+        assert hasattr(L, name), name
+    assert set(_native.EXPORTS) <= set(decl)
+
+
+def test_params_struct_matches_header():
+    txt = open(os.path.join(ROOT, "include", "sff.h")).read()
+    body = txt[txt.index("typedef struct sff_params"):txt.index("} sff_params;")]
+    fields = re.findall(r"(\w+)(?=[,;])", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
+    fields = [f for f in fields if f not in ("int32_t",)]
+    assert fields == [n for n, _ in SffParams._fields_]
+    assert ctypes.sizeof(SffParams) == 40
+
+
+def test_status_strings_and_version():
+    L = _native.lib()
+    assert L.sff_status_string(0) == b"ok"
+    assert L.sff_status_string(1) == b"invalid argument"
+    assert L.sff_status_string(99) == b"unknown status"
+    assert L.sff_version() >= 100
+
+
+def _good():
+    return SffParams(H=96, W=160, C=1, levels=1, iters=4, rs_r0=32, rs_samples=6, fmax=32, dmax=32,
+                     tau=1)
+
+
+BAD = [dict(H=0), dict(W=-1), dict(C=0), dict(C=5), dict(levels=0), dict(levels=6),
+       dict(iters=-1), dict(rs_samples=17), dict(rs_r0=0), dict(fmax=9000), dict(dmax=-1),
+       dict(tau=-2), dict(H=20000)]
+
+
+@host_only
+@pytest.mark.parametrize("bad", BAD)
+def test_invalid_params_rejected_without_launch(bad):
+    L = _native.lib()
+    p = _good()
+    for k, v in bad.items():
+        setattr(p, k, v)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert L.sff_wht_features(ctypes.byref(p), 1, 0, fake, fake, None, 0, None) == 1
+    assert L.sff_init_nn(ctypes.byref(p), 1, 0, fake, fake, fake, None) == 1
+    assert L.sff_match_level(ctypes.byref(p), 1, 0, 0, fake, fake, None, fake, fake, None) == 1
+    assert L.sff_consistency(ctypes.byref(p), 1, fake, fake, fake, fake, None) == 1
+    assert L.sff_wht_workspace_bytes(ctypes.byref(p), 4, 0) == 0
+
+
+@host_only
+def test_invalid_arguments_rejected():
+    L = _native.lib()
+    p = _good()
+    P = ctypes.byref(p)
+    f = ctypes.c_void_p(0x1000)
+    # null pointers
+    assert L.sff_wht_features(P, 1, 0, None, f, None, 0, None) == 1
+    assert L.sff_init_nn(P, 1, 0, f, None, f, None) == 1
+    assert L.sff_match_level(P, 1, 0, 0, f, None, None, f, f, None) == 1
+    assert L.sff_consistency(P, 1, f, f, None, f, None) == 1
+    # bad batch / direction / level
+    assert L.sff_init_nn(P, 0, 0, f, f, f, None) == 1
+    assert L.sff_init_nn(P, 1, 2, f, f, f, None) == 1
+    assert L.sff_match_level(P, 1, 0, 1, f, f, None, f, f, None) == 1      # level >= levels
+    assert L.sff_match_level(P, 1, 0, 0, f, f, f, f, f, None) == 1         # hand-off at top
+    assert L.sff_wht_features(P, 1, 1, f, f, None, 0, None) == 1          # level >= levels
+    # misaligned descriptor pointer
+    assert L.sff_init_nn(P, 1, 0, ctypes.c_void_p(0x1002), f, f, None) == 1
+    # workspace missing at level >= 1
+    p2 = _good()
+    p2.levels = 3
+    need = L.sff_wht_workspace_bytes(ctypes.byref(p2), 4, 1)
+    assert need > 0
+    assert L.sff_wht_workspace_bytes(ctypes.byref(p2), 4, 0) == 0
+    assert L.sff_wht_features(ctypes.byref(p2), 4, 1, f, f, None, 0, None) == 4
+    assert L.sff_wht_features(ctypes.byref(p2), 4, 1, f, f, f, need - 1, None) == 4
+    # overlapping hand-off buffers
+    p3 = _good()
+    p3.levels = 2
+    base = 0x100000
+    assert L.sff_match_level(ctypes.byref(p3), 1, 0, 0, f, f, ctypes.c_void_p(base + 64),
+                             ctypes.c_void_p(base), f, None) == 1
+
+
+def test_lanczos_table_identical_to_oracle():
+    import oracle
+    from paper_1710_10096_amd import sff_lanczos_q14
+    for n in (2, 4, 8, 16):
+        assert sff_lanczos_q14(n) == oracle.lanczos_q14(n).tolist()
+    L = _native.lib()
+    buf = (ctypes.c_int32 * 6)()
+    assert L.sff_lanczos_q14(1, ctypes.cast(buf, ctypes.c_void_p)) == 1
+    assert L.sff_lanczos_q14(32, ctypes.cast(buf, ctypes.c_void_p)) == 1

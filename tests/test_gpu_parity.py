@@ -1,0 +1,271 @@
+"""GPU parity: every libsff entry point against the CPU oracle, bit-exact
+(integer path: descriptors, vectors, costs, argmin tie-breaks, masks, errors).
+
+Inputs are seeded synthetic scenes; expected values come only from ``oracle``.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from sff_inputs import (make_scene, small_spec, tiny_spec, tiny_params, kitti_spec,
+                        kitti_params, params_dict)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sff():
+    import torch
+    import paper_1710_10096_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t, u32=False):
+    a = t.cpu().numpy()
+    return a.view(np.uint32) if u32 else a
+
+
+def _imgs_stack(scenes):
+    return np.stack([sc.stack() for sc in scenes], axis=0)  # [B][4][H][W][C]
+
+
+def _oracle_descs(imgs_b, level):
+    """imgs_b [4][H][W][C] -> 4 oracle descriptor maps."""
+    return [oracle.features(imgs_b[m], level) for m in range(4)]
+
+
+# ------------------------------------------------------------- features ----
+FEATURE_CASES = [
+    ("tiny_l0", 96, 160, 1, 1, [0]),
+    ("ragged_c3", 37, 53, 3, 3, [0, 1, 2]),
+    ("ragged_c2_l4", 29, 71, 2, 4, [0, 3]),
+    ("c4", 20, 24, 4, 2, [0, 1]),
+    ("one_pixel", 1, 1, 1, 2, [0, 1]),
+    ("thin_row", 1, 40, 3, 3, [2]),
+]
+
+
+@pytest.mark.parametrize("case", FEATURE_CASES, ids=[c[0] for c in FEATURE_CASES])
+def test_wht_features_parity(sff, case):
+    name, H, W, C, levels, lvls = case
+    rng = np.random.default_rng(abs(hash(name)) % 2 ** 32)
+    imgs = rng.integers(0, 256, (4, H, W, C), dtype=np.uint8)
+    p = params_dict(H, W, C, levels=levels, iters=1)
+    for lv in lvls:
+        _say("features", name, "level", lv)
+        d = host(sff.sff_wht_features(p, dev(imgs), lv))
+        for m in range(4):
+            assert np.array_equal(d[m], oracle.features(imgs[m], lv)), (name, lv, m)
+
+
+def test_wht_features_kitti_full(sff):
+    sc = make_scene(kitti_spec())
+    p = kitti_params()
+    imgs = sc.stack()
+    g = dev(imgs)
+    for lv in range(3):
+        _say("features kitti level", lv)
+        d = host(sff.sff_wht_features(p, g, lv))
+        for m in range(4):
+            assert np.array_equal(d[m], oracle.features(imgs[m], lv)), (lv, m)
+
+
+# ----------------------------------------------------------------- init ----
+INIT_CASES = [
+    # name, H, W, C, levels, fmax, dmax, seed
+    ("tiny", 96, 160, 1, 1, 32, 32, 1),
+    ("ragged_l2", 45, 77, 3, 2, 12, 10, 3),
+    ("ragged_l3_c2", 50, 83, 2, 3, 20, 17, 4),
+    ("c4_l1", 24, 40, 4, 1, 7, 9, 5),
+    ("fmax0", 20, 30, 1, 1, 0, 0, 6),
+]
+
+
+@pytest.mark.parametrize("case", INIT_CASES, ids=[c[0] for c in INIT_CASES])
+def test_init_nn_parity(sff, case):
+    name, H, W, C, levels, fmax, dmax, seed = case
+    sc = make_scene(small_spec(H, W, C, seed, flow_max=min(fmax, 10), d_range=(0, min(dmax, 10))))
+    p = params_dict(H, W, C, levels=levels, iters=1, fmax=fmax, dmax=dmax)
+    top = levels - 1
+    imgs = sc.stack()
+    desc = sff.sff_wht_features(p, dev(imgs), top).view(1, 4, H, W, C, 16)
+    D = _oracle_descs(imgs, top)
+    _say("init", name, "both directions")
+    hyp, cost = sff.sff_init_nn(p, desc, sff.DIR_BOTH)
+    h, c = host(hyp), host(cost, u32=True)
+    for di, s in enumerate((1, -1)):
+        oh, oc = oracle.init_nn(D, top, s, fmax, dmax)
+        assert np.array_equal(h[di, 0], oh), (name, s)
+        assert np.array_equal(c[di, 0], oc), (name, s)
+    _say("init", name, "single directions")
+    for s in (1, -1):
+        hyp1, cost1 = sff.sff_init_nn(p, desc, s)
+        assert np.array_equal(host(hyp1)[0, 0], h[0 if s > 0 else 1, 0])
+        assert np.array_equal(host(cost1, u32=True)[0, 0], c[0 if s > 0 else 1, 0])
+
+
+def test_init_nn_kitti_full(sff):
+    sc = make_scene(kitti_spec())
+    p = kitti_params()
+    imgs = sc.stack()
+    top = p["levels"] - 1
+    desc = sff.sff_wht_features(p, dev(imgs), top).view(1, 4, p["H"], p["W"], p["C"], 16)
+    _say("init kitti")
+    hyp, cost = sff.sff_init_nn(p, desc, sff.DIR_BOTH)
+    D = _oracle_descs(imgs, top)
+    for di, s in enumerate((1, -1)):
+        oh, oc = oracle.init_nn(D, top, s, p["fmax"], p["dmax"])
+        assert np.array_equal(host(hyp)[di, 0], oh)
+        assert np.array_equal(host(cost, u32=True)[di, 0], oc)
+
+
+# ---------------------------------------------------------- match level ----
+LEVEL_CASES = [
+    # name, H, W, C, levels, level, iters, rs_samples, batch
+    ("top_tiny", 96, 160, 1, 1, 0, 4, 6, 1),
+    ("top_ragged_l2", 45, 77, 3, 3, 2, 3, 6, 2),
+    ("handoff_l1", 45, 77, 3, 3, 1, 2, 6, 2),
+    ("handoff_l0_c2", 38, 61, 2, 2, 0, 3, 4, 1),
+    ("handoff_only", 38, 61, 1, 2, 0, 0, 6, 1),
+    ("no_search", 30, 50, 1, 1, 0, 3, 0, 3),
+    ("odd_sizes", 17, 9, 2, 2, 1, 5, 6, 1),
+]
+
+
+@pytest.mark.parametrize("case", LEVEL_CASES, ids=[c[0] for c in LEVEL_CASES])
+def test_match_level_parity(sff, case):
+    import torch
+    name, H, W, C, levels, level, iters, rs, B = case
+    fmax, dmax = 16, 12
+    p = params_dict(H, W, C, levels=levels, iters=iters, rs_samples=rs, fmax=fmax, dmax=dmax)
+    scenes = [make_scene(small_spec(H, W, C, 100 + 7 * b, flow_max=8, d_range=(0, 10)))
+              for b in range(B)]
+    imgs = _imgs_stack(scenes)
+    seeds = np.array([11 + 1000003 * b for b in range(B)], np.int64)
+    flat = dev(imgs.reshape(4 * B, H, W, C))
+    desc_l = sff.sff_wht_features(p, flat, level).view(B, 4, H, W, C, 16)
+    Dl = [_oracle_descs(imgs[b], level) for b in range(B)]
+    if level < levels - 1:
+        # a coarse field: oracle init at the next level (both sides get the same input)
+        Dc = [_oracle_descs(imgs[b], level + 1) for b in range(B)]
+        coarse = np.stack([np.stack([oracle.init_nn(Dc[b], level + 1, s, fmax, dmax)[0]
+                                     for b in range(B)]) for s in (1, -1)])
+        _say("match_level", name, "hand-off")
+        hyp, cost = sff.sff_match_level(p, desc_l, sff.DIR_BOTH, level, dev(seeds),
+                                        hyp_coarse=dev(coarse))
+        for di, s in enumerate((1, -1)):
+            for b in range(B):
+                oh, oc = oracle.match_level(Dl[b], level, s, int(seeds[b]), iters, 32, rs, fmax,
+                                            dmax, None, None, hyp_coarse=coarse[di, b])
+                assert np.array_equal(host(hyp)[di, b], oh), (name, s, b)
+                assert np.array_equal(host(cost, u32=True)[di, b], oc), (name, s, b)
+    else:
+        start = np.stack([np.stack([oracle.init_nn(Dl[b], level, s, fmax, dmax)[0]
+                                    for b in range(B)]) for s in (1, -1)])
+        startc = np.stack([np.stack([oracle.init_nn(Dl[b], level, s, fmax, dmax)[1]
+                                     for b in range(B)]) for s in (1, -1)])
+        _say("match_level", name, "from init")
+        hyp = dev(start)
+        cost = dev(startc.view(np.int32))
+        sff.sff_match_level(p, desc_l, sff.DIR_BOTH, level, dev(seeds), hyp, cost)
+        for di, s in enumerate((1, -1)):
+            for b in range(B):
+                oh, oc = oracle.match_level(Dl[b], level, s, int(seeds[b]), iters, 32, rs, fmax,
+                                            dmax, start[di, b], startc[di, b])
+                assert np.array_equal(host(hyp)[di, b], oh), (name, s, b)
+                assert np.array_equal(host(cost, u32=True)[di, b], oc), (name, s, b)
+        # one direction at a time gives the same fields
+        for di, s in enumerate((1, -1)):
+            h1 = dev(start[di:di + 1])
+            c1 = dev(startc[di:di + 1].view(np.int32))
+            sff.sff_match_level(p, desc_l, s, level, dev(seeds), h1, c1)
+            assert np.array_equal(host(h1)[0], host(hyp)[di])
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------- consistency ----
+def test_consistency_parity(sff):
+    rng = np.random.default_rng(12)
+    H, W, B = 41, 67, 3
+    p = params_dict(H, W, 1, levels=1, iters=1, fmax=20, dmax=15, tau=1)
+    fwd = np.empty((B, H, W, 4), np.int16)
+    inv = np.empty((B, H, W, 4), np.int16)
+    for arr in (fwd, inv):
+        arr[..., :2] = rng.integers(-20, 21, (B, H, W, 2))
+        arr[..., 2:] = rng.integers(0, 16, (B, H, W, 2))
+    # make a share of pixels exactly or nearly consistent
+    sc = make_scene(small_spec(H, W, 1, 77, flow_max=6, d_range=(0, 8), delta_max=2))
+    fwd[0] = sc.gt_fwd
+    inv[0] = np.where(sc.inv_mask[..., None], sc.gt_inv, inv[0])
+    for tau in (0, 1, 3):
+        p["tau"] = tau
+        _say("consistency tau", tau)
+        valid, err = sff.sff_consistency(p, dev(fwd), dev(inv))
+        for b in range(B):
+            ov, oe = oracle.consistency(fwd[b], inv[b], tau)
+            assert np.array_equal(host(valid)[b], ov)
+            assert np.array_equal(host(err, u32=True)[b], oe)
+    assert host(valid)[0].mean() > 0.3
+
+
+# ---------------------------------------------------------- whole stage ----
+def _check_pipeline(sff, scenes, p, seeds, stream=None):
+    import torch
+    B = len(scenes)
+    imgs = _imgs_stack(scenes)
+    m = sff.PairMatcher(p, B)
+    out = m.run(dev(imgs), dev(np.array(seeds, np.int64)), stream)
+    if stream is not None:
+        stream.synchronize()
+    torch.cuda.synchronize()
+    hyp, cost = host(out["hyp"]), host(out["cost"], u32=True)
+    valid, err = host(out["valid"]), host(out["err"], u32=True)
+    for b in range(B):
+        ref = oracle.match_pair(imgs[b], p, int(seeds[b]))
+        assert np.array_equal(hyp[:, b], ref["hyp"]), b
+        assert np.array_equal(cost[:, b], ref["cost"]), b
+        assert np.array_equal(valid[b], ref["valid"]), b
+        assert np.array_equal(err[b], ref["err"]), b
+    return out
+
+
+def test_pipeline_tiny(sff):
+    _say("pipeline tiny")
+    _check_pipeline(sff, [make_scene(tiny_spec())], tiny_params(), [1])
+
+
+def test_pipeline_ragged_batch_on_side_stream(sff):
+    import torch
+    p = params_dict(53, 91, 3, levels=3, iters=3, fmax=24, dmax=20)
+    scenes = [make_scene(small_spec(53, 91, 3, 300 + b, flow_max=12, d_range=(0, 16)))
+              for b in range(3)]
+    st = torch.cuda.Stream()
+    _say("pipeline ragged batch 3 on side stream")
+    with torch.cuda.stream(st):
+        _check_pipeline(sff, scenes, p, [5, 6, 7], stream=st)
+
+
+def test_pipeline_kitti_full(sff):
+    _say("pipeline kitti 1242x375")
+    _check_pipeline(sff, [make_scene(kitti_spec())], kitti_params(), [2])
+
+
+def test_invalid_batch_raises(sff):
+    import torch
+    p = tiny_params()
+    img = torch.zeros((0, 96, 160, 1), dtype=torch.uint8, device="cuda")
+    with pytest.raises(sff.SffError):
+        sff.sff_wht_features(p, img, 0, torch.zeros((1, 96, 160, 1, 16), dtype=torch.int16,
+                                                   device="cuda"))
