@@ -104,6 +104,9 @@ size_t sff_wht_workspace_bytes(const sff_params* p, int32_t nimg, int32_t level)
 sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_t level, const uint8_t* img,
                             int16_t* desc, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Device workspace (bytes) that sff_init_nn needs for `batch` pairs. */
+size_t sff_init_workspace_bytes(const sff_params* p, int32_t batch);
+
 /* Initialisation at the coarsest level k = levels - 1 (Section 3.1,
  * "Initialization"), read as exact nearest neighbours in descriptor space:
  * for every grid pixel p = (n j, n i), among grid targets (multiples of n)
@@ -116,9 +119,13 @@ sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_t level, co
  * desc: level-(levels-1) descriptors [batch][4][H][W][C][16].
  * dir:  SFF_DIR_FORWARD, SFF_DIR_INVERSE or SFF_DIR_BOTH.
  * hyp/cost: coarsest-level field, written.
- * Errors: SFF_ERR_INVALID_ARG. */
+ * workspace: device buffer, 256-byte aligned, of at least
+ *   sff_init_workspace_bytes(p, batch) bytes; contents on entry are ignored.
+ * Errors: SFF_ERR_INVALID_ARG; SFF_ERR_WORKSPACE (missing, misaligned or too
+ *   small workspace). */
 sff_status sff_init_nn(const sff_params* p, int32_t batch, int32_t dir, const int16_t* desc,
-                       int16_t* hyp, uint32_t* cost, void* stream);
+                       int16_t* hyp, uint32_t* cost, void* workspace, size_t workspace_bytes,
+                       void* stream);
 
 /* Propagation and random search at one level (Section 3.1, "Multi-Scale
  * Propagation"), eq. (1) cost: sum over the temporal (x + u, y + v), stereo

@@ -6,6 +6,6 @@ include/sff.h.
 """
 from ._native import SffParams, LIB_PATH, EXPORTS  # noqa: F401
 from .api import (DIR_BOTH, DIR_FORWARD, DIR_INVERSE,  # noqa: F401
-                  SffError, grid_shape, sff_consistency, sff_init_nn, sff_lanczos_q14,
+                  SffError, grid_shape, sff_consistency, sff_init_nn, sff_init_workspace_bytes, sff_lanczos_q14,
                   sff_match_level, sff_version, sff_wht_features, sff_wht_workspace_bytes)
 from .pipeline import PairMatcher, match_pairs  # noqa: F401

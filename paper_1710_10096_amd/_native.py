@@ -28,7 +28,8 @@ class SffParams(ctypes.Structure):
 
 
 EXPORTS = ("sff_status_string", "sff_version", "sff_lanczos_q14", "sff_wht_workspace_bytes",
-           "sff_wht_features", "sff_init_nn", "sff_match_level", "sff_consistency")
+           "sff_wht_features", "sff_init_workspace_bytes", "sff_init_nn", "sff_match_level",
+           "sff_consistency")
 
 _lib = None
 
@@ -53,7 +54,9 @@ def lib() -> ctypes.CDLL:
     L.sff_wht_workspace_bytes.restype = ctypes.c_size_t
     L.sff_wht_features.argtypes = [PP, i32, i32, P, P, P, ctypes.c_size_t, P]
     L.sff_wht_features.restype = i32
-    L.sff_init_nn.argtypes = [PP, i32, i32, P, P, P, P]
+    L.sff_init_workspace_bytes.argtypes = [PP, i32]
+    L.sff_init_workspace_bytes.restype = ctypes.c_size_t
+    L.sff_init_nn.argtypes = [PP, i32, i32, P, P, P, P, ctypes.c_size_t, P]
     L.sff_init_nn.restype = i32
     L.sff_match_level.argtypes = [PP, i32, i32, i32, P, P, P, P, P, P]
     L.sff_match_level.restype = i32

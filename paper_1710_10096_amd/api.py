@@ -99,15 +99,26 @@ def _field(p, batch, ndir, level, device, hyp=None, cost=None):
     return hyp, cost
 
 
-def sff_init_nn(p, desc: torch.Tensor, dir: int = DIR_BOTH, hyp=None, cost=None, stream=None):
+def sff_init_workspace_bytes(p, batch: int) -> int:
+    pp = _params(p)
+    return int(lib().sff_init_workspace_bytes(ctypes.byref(pp), batch))
+
+
+def sff_init_nn(p, desc: torch.Tensor, dir: int = DIR_BOTH, hyp=None, cost=None,
+                workspace: torch.Tensor | None = None, stream=None):
     """desc int16 [batch][4][H][W][C][16] at the coarsest level -> (hyp, cost)."""
     pp = _params(p)
     batch = desc.shape[0]
     ndir = 2 if dir == DIR_BOTH else 1
     hyp, cost = _field(pp, batch, ndir, pp.levels - 1, desc.device, hyp, cost)
+    if workspace is None:
+        workspace = torch.empty(sff_init_workspace_bytes(pp, batch), dtype=torch.uint8,
+                                device=desc.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
     _check(lib().sff_init_nn(ctypes.byref(pp), batch, dir, _ptr(desc, torch.int16, "desc"),
                              _ptr(hyp, torch.int16, "hyp"), _ptr(cost, torch.int32, "cost"),
-                             _stream(stream)), "sff_init_nn")
+                             _ptr(workspace, None, "workspace"), ws_bytes, _stream(stream)),
+           "sff_init_nn")
     return hyp, cost
 
 

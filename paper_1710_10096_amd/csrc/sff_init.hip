@@ -5,9 +5,14 @@
 // (row y + v*, 0 <= d1 <= dmax), ties to the smallest target index; the
 // combination's eq. (1) cost is stored with it.
 //
-// One thread per reference grid pixel.  A wave covers a 16 x 4 tile of grid
-// pixels, so at every step of the box scan its lanes read 4 runs of 16
-// consecutive candidate descriptors.
+// The temporal search is a dense contraction: for a query descriptor a and a
+// candidate b, |a - b|^2 = |a|^2 + |b|^2 - 2 a.b.  It runs on int8 MFMA with
+// every int16 coefficient split exactly into a = 256 a_h + a_l (a_l in
+// [-128, 127], a_h in [-64, 64]):
+//   a.b = 65536 (a_h.b_h) + 256 (a_h.b_l + a_l.b_h) + a_l.b_l,
+// each partial an exact int32 MFMA accumulation.  The true squared distance of
+// up to 4 channels is below 2^32, so evaluating the identity modulo 2^32 in
+// uint32 arithmetic yields it exactly.
 #include "sff_device.hpp"
 
 namespace sff {
@@ -21,81 +26,235 @@ struct InitArgs {
     int batch, dir0, ndir;
 };
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kQRows = 4;    // query rows per block (one 16-query MFMA tile each)
+constexpr int kWaves = 4;    // waves per block, splitting the candidate rows
+constexpr int kKBytes = 64;  // MFMA K: 16 C int8 values, zero padded (C <= 4)
+
+// Split planes of the coarsest-level grid of all four views:
+//   hi[z][p][64], lo[z][p][64] int8 and sq[z][p] = |desc|^2 mod 2^32,
+// z = pair * 4 + view, p = i * Wk + j.
+struct SplitPlanes {
+    int8_t* hi;
+    int8_t* lo;
+    uint32_t* sq;
+};
+
 template <int C>
-__global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a) {
-    const int j = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
+__global__ void __launch_bounds__(256) split_kernel(const int16_t* __restrict__ desc, SplitPlanes P,
+                                                    int H, int W, int n, int Hk, int Wk, int nz) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int z = blockIdx.y;
+    if (p >= Hk * Wk || z >= nz) return;
+    const int i = p / Wk, j = p - i * Wk;
+    const size_t mapsz = (size_t)H * W * 16 * C;
+    const int16_t* d = desc + (size_t)z * mapsz + ((size_t)(n * i) * W + n * j) * 16 * C;
+    uint32_t hw[kKBytes / 4], lw[kKBytes / 4];
+    uint32_t sq = 0;
+#pragma unroll
+    for (int w = 0; w < kKBytes / 4; ++w) {
+        hw[w] = 0;
+        lw[w] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16 * C; ++k) {
+        const int a = d[k];
+        const int lo = ((a + 128) & 255) - 128;
+        const int hi = (a - lo) >> 8;
+        sq += (uint32_t)(a * a);
+        hw[k >> 2] |= (uint32_t)(uint8_t)(int8_t)hi << (8 * (k & 3));
+        lw[k >> 2] |= (uint32_t)(uint8_t)(int8_t)lo << (8 * (k & 3));
+    }
+    const size_t o = (size_t)z * Hk * Wk + p;
+    uint4* ho = reinterpret_cast<uint4*>(P.hi + o * kKBytes);
+    uint4* lo4 = reinterpret_cast<uint4*>(P.lo + o * kKBytes);
+#pragma unroll
+    for (int q = 0; q < kKBytes / 16; ++q) {
+        ho[q] = make_uint4(hw[4 * q], hw[4 * q + 1], hw[4 * q + 2], hw[4 * q + 3]);
+        lo4[q] = make_uint4(lw[4 * q], lw[4 * q + 1], lw[4 * q + 2], lw[4 * q + 3]);
+    }
+    P.sq[o] = sq;
+}
+
+__device__ __forceinline__ v4i load16(const int8_t* p) {
+    return __builtin_bit_cast(v4i, *reinterpret_cast<const uint4*>(p));
+}
+
+// One block: kQRows rows x 16 consecutive columns of reference grid pixels of
+// one field.  Wave w scans the candidate rows r = rlo + w (mod kWaves) of the
+// union of the queries' boxes, 16 candidates per MFMA tile.
+//
+// v_mfma_i32_16x16x64_i8 operands: A (16 x 64) holds candidates, lane l giving
+// candidate l % 16; B (64 x 16) holds queries, lane l giving query l % 16; both
+// with the same K bytes for lane group l / 16, so each product sums over all 64
+// K values.  Lane l receives C[4 (l / 16) + e][l % 16], e = 0..3: candidates
+// 4 g + e of the tile against its own query.
+template <int C>
+__global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P) {
+    __shared__ unsigned long long red[kWaves * 4][kQRows][16];
+    __shared__ int res_u[kQRows][16], res_v[kQRows][16];
+    __shared__ uint32_t res_t[kQRows][16];
+    __shared__ unsigned long long red2[4][kQRows][16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nq = lane & 15, g = lane >> 4;
+    const int j0 = blockIdx.x * 16, i0 = blockIdx.y * kQRows;
     const int z = blockIdx.z;  // dir_index * batch + b
     const int di = z / a.batch, b = z - di * a.batch;
-    if (i >= a.Hk || j >= a.Wk) return;
     const int s = (a.ndir == 2) ? (di == 0 ? 1 : -1) : a.dir0;
-    const size_t plane = (size_t)a.H * a.W;
-    const size_t mapsz = plane * 16 * C;
-    const int16_t* base = a.desc + (size_t)b * 4 * mapsz;
-    // canonical order l0, l1, r0, r1; the inverse field permutes to r1, r0, l1, l0
-    const int16_t* R = base + (size_t)(s > 0 ? 0 : 3) * mapsz;
-    const int16_t* T = base + (size_t)(s > 0 ? 1 : 2) * mapsz;
-    const int16_t* S = base + (size_t)(s > 0 ? 2 : 1) * mapsz;
-    const int16_t* X = base + (size_t)(s > 0 ? 3 : 0) * mapsz;
-    const int n = a.n, W = a.W, H = a.H;
-    const int x = n * j, y = n * i;
-    const Desc<C> q = load_desc<C>(R, (size_t)y * W + x);
+    const int Hk = a.Hk, Wk = a.Wk, n = a.n;
+    const int F = a.fm / n;
+    const int vR = s > 0 ? 0 : 3, vT = s > 0 ? 1 : 2, vS = s > 0 ? 2 : 1, vX = s > 0 ? 3 : 0;
+    const size_t Nk = (size_t)Hk * Wk;
+    const size_t zR = ((size_t)b * 4 + vR) * Nk, zT = ((size_t)b * 4 + vT) * Nk;
 
-    // temporal partner: box scan in increasing target index, strict improvement
-    const int vlo = -min(a.fm, y), vhi = min(a.fm, ((H - 1 - y) / n) * n);
-    const int ulo = -min(a.fm, x), uhi = min(a.fm, ((W - 1 - x) / n) * n);
-    uint32_t bestT = 0xFFFFFFFFu;
-    int bu = 0, bv = 0;
-    for (int v = vlo; v <= vhi; v += n) {
-        const size_t row = (size_t)(y + v) * W;
-        for (int u = ulo; u <= uhi; u += n) {
-            const uint32_t e = desc_ssd<C>(q, load_desc<C>(T, row + x + u));
-            if (e < bestT) {
-                bestT = e;
-                bu = u;
-                bv = v;
+    // queries (B operands), one 16-column tile per query row
+    v4i qh[kQRows], ql[kQRows];
+    uint32_t asq[kQRows], best[kQRows], bidx[kQRows];
+    const int jq = min(j0 + nq, Wk - 1);
+#pragma unroll
+    for (int t = 0; t < kQRows; ++t) {
+        const size_t o = zR + (size_t)min(i0 + t, Hk - 1) * Wk + jq;
+        qh[t] = load16(P.hi + o * kKBytes + 16 * g);
+        ql[t] = load16(P.lo + o * kKBytes + 16 * g);
+        asq[t] = P.sq[o];
+        best[t] = 0xFFFFFFFFu;
+        bidx[t] = 0;
+    }
+    const int rlo = max(0, i0 - F), rhi = min(Hk - 1, i0 + kQRows - 1 + F);
+    const int nct = (16 + 2 * F + 15) / 16;
+    const v4i zero = {0, 0, 0, 0};
+    for (int r = rlo + w; r <= rhi; r += kWaves) {
+        const size_t rowT = zT + (size_t)r * Wk;
+        for (int ct = 0; ct < nct; ++ct) {
+            const int c0 = j0 - F + 16 * ct;
+            if (c0 + 15 < 0 || c0 >= Wk) continue;
+            const size_t oa = rowT + clampi(c0 + nq, 0, Wk - 1);
+            const v4i ah = load16(P.hi + oa * kKBytes + 16 * g);
+            const v4i al = load16(P.lo + oa * kKBytes + 16 * g);
+            uint32_t bsq[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bsq[e] = P.sq[rowT + clampi(c0 + 4 * g + e, 0, Wk - 1)];
+            // every candidate of the tile inside the image and in every query's box
+            const bool full = c0 >= 0 && c0 + 15 < Wk && c0 >= j0 + 15 - F && c0 + 15 <= j0 + F;
+#pragma unroll
+            for (int t = 0; t < kQRows; ++t) {
+                const int iq = i0 + t;
+                if (iq >= Hk || r < iq - F || r > iq + F) continue;
+                const v4i hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, qh[t], zero, 0, 0, 0);
+                v4i cr = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, ql[t], zero, 0, 0, 0);
+                cr = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, qh[t], cr, 0, 0, 0);
+                const v4i ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, ql[t], zero, 0, 0, 0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int jc = c0 + 4 * g + e;
+                    // 2 a.b mod 2^32 = 2 (256 (256 hh + cr) + ll)
+                    const uint32_t ab = ((((uint32_t)hh[e] << 8) + (uint32_t)cr[e]) << 8) + (uint32_t)ll[e];
+                    uint32_t ssd = asq[t] + bsq[e] - (ab << 1);
+                    if (!full) {
+                        const bool ok = (unsigned)(jc - (j0 + nq) + F) <= (unsigned)(2 * F) &&
+                                        (unsigned)jc < (unsigned)Wk;
+                        ssd = ok ? ssd : 0xFFFFFFFFu;
+                    }
+                    if (ssd < best[t]) {
+                        best[t] = ssd;
+                        bidx[t] = (uint32_t)(r * Wk + jc);
+                    }
+                }
             }
         }
     }
-    // stereo partner on row y: target tx = x - s d0, scanned by increasing tx
-    uint32_t bestS = 0xFFFFFFFFu;
-    int bd0 = 0;
-    {
-        const int dlim_l = min(a.dm, x);                         // towards smaller x
-        const int dlim_r = min(a.dm, ((W - 1 - x) / n) * n);     // towards larger x
-        const int txlo = s > 0 ? x - dlim_l : x;
-        const int txhi = s > 0 ? x : x + dlim_r;
-        for (int tx = txlo; tx <= txhi; tx += n) {
-            const uint32_t e = desc_ssd<C>(q, load_desc<C>(S, (size_t)y * W + tx));
-            if (e < bestS) {
-                bestS = e;
-                bd0 = s * (x - tx);
-            }
+#pragma unroll
+    for (int t = 0; t < kQRows; ++t)
+        red[w * 4 + g][t][nq] = ((unsigned long long)best[t] << 32) | bidx[t];
+    __syncthreads();
+    // combine the 16 partial minima (waves x lane groups) of each query
+    if (threadIdx.x < kQRows * 16) {
+        const int t = threadIdx.x >> 4, q = threadIdx.x & 15;
+        unsigned long long m = red[0][t][q];
+#pragma unroll
+        for (int k = 1; k < kWaves * 4; ++k) m = red[k][t][q] < m ? red[k][t][q] : m;
+        const uint32_t idx = (uint32_t)m;
+        const int ri = (int)(idx / (uint32_t)Wk), rj = (int)(idx % (uint32_t)Wk);
+        res_v[t][q] = n * (ri - (i0 + t));
+        res_u[t][q] = n * (rj - min(j0 + q, Wk - 1));
+        res_t[t][q] = (uint32_t)(m >> 32);
+    }
+    __syncthreads();
+
+    // epipolar searches: 4 threads per query, candidates interleaved
+    const int q = threadIdx.x & 15, t = (threadIdx.x >> 4) & 3, part = threadIdx.x >> 6;
+    const int iq = i0 + t, jqq = j0 + q;
+    const bool live = iq < Hk && jqq < Wk;
+    const int x = n * min(jqq, Wk - 1), y = n * min(iq, Hk - 1);
+    const int W = a.W;
+    const size_t mapsz = (size_t)a.H * W * 16 * C;
+    const int16_t* base = a.desc + (size_t)b * 4 * mapsz;
+    const Desc<C> qd = load_desc<C>(base + (size_t)vR * mapsz, (size_t)y * W + x);
+    const int16_t* Sm = base + (size_t)vS * mapsz;
+    const int16_t* Xm = base + (size_t)vX * mapsz;
+    // stereo partner on row y: target tx = x - s d0, increasing tx
+    unsigned long long kS = ~0ull;
+    if (live) {
+        const int txlo = s > 0 ? x - min(a.dm, x) : x;
+        const int txhi = s > 0 ? x : x + min(a.dm, ((W - 1 - x) / n) * n);
+        for (int tx = txlo + n * part; tx <= txhi; tx += 4 * n) {
+            const uint32_t e = desc_ssd<C>(qd, load_desc<C>(Sm, (size_t)y * W + tx));
+            const unsigned long long k = ((unsigned long long)e << 32) | (uint32_t)tx;
+            kS = k < kS ? k : kS;
         }
     }
-    // cross partner on row y + v*: target tx = x + u* - s d1
-    uint32_t bestX = 0xFFFFFFFFu;
-    int bd1 = 0;
-    {
+    red2[part][t][q] = kS;
+    __syncthreads();
+    unsigned long long mS = red2[0][t][q];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) mS = red2[k][t][q] < mS ? red2[k][t][q] : mS;
+    __syncthreads();
+    // cross partner on row y + v*: target tx = x + u* - s d1, increasing tx
+    const int bu = live ? res_u[t][q] : 0, bv = live ? res_v[t][q] : 0;
+    unsigned long long kX = ~0ull;
+    if (live) {
         const int xc = x + bu, yc = y + bv;
-        const int dlim_l = min(a.dm, xc);
-        const int dlim_r = min(a.dm, ((W - 1 - xc) / n) * n);
-        const int txlo = s > 0 ? xc - dlim_l : xc;
-        const int txhi = s > 0 ? xc : xc + dlim_r;
-        for (int tx = txlo; tx <= txhi; tx += n) {
-            const uint32_t e = desc_ssd<C>(q, load_desc<C>(X, (size_t)yc * W + tx));
-            if (e < bestX) {
-                bestX = e;
-                bd1 = s * (xc - tx);
-            }
+        const int txlo = s > 0 ? xc - min(a.dm, xc) : xc;
+        const int txhi = s > 0 ? xc : xc + min(a.dm, ((W - 1 - xc) / n) * n);
+        for (int tx = txlo + n * part; tx <= txhi; tx += 4 * n) {
+            const uint32_t e = desc_ssd<C>(qd, load_desc<C>(Xm, (size_t)yc * W + tx));
+            const unsigned long long k = ((unsigned long long)e << 32) | (uint32_t)tx;
+            kX = k < kX ? k : kX;
         }
     }
-    const size_t o = ((size_t)z * a.Hk + i) * a.Wk + j;
+    red2[part][t][q] = kX;
+    __syncthreads();
+    if (part != 0 || !live) return;
+    unsigned long long mX = red2[0][t][q];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) mX = red2[k][t][q] < mX ? red2[k][t][q] : mX;
+    const int bd0 = s * (x - (int)(uint32_t)mS);
+    const int bd1 = s * (x + bu - (int)(uint32_t)mX);
+    const size_t o = ((size_t)z * Hk + iq) * Wk + jqq;
     uint2 hv;
     hv.x = (uint32_t)(uint16_t)(int16_t)bu | ((uint32_t)(uint16_t)(int16_t)bv << 16);
     hv.y = (uint32_t)(uint16_t)(int16_t)bd0 | ((uint32_t)(uint16_t)(int16_t)bd1 << 16);
     reinterpret_cast<uint2*>(a.hyp)[o] = hv;
-    a.cost[o] = bestT + bestS + bestX;  // all three targets lie inside the image
+    // all three targets lie inside the image, so no clamping enters the cost
+    a.cost[o] = res_t[t][q] + (uint32_t)(mS >> 32) + (uint32_t)(mX >> 32);
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct InitWs {
+    size_t hi, lo, sq, total;
+};
+
+InitWs init_ws(const sff_params& p, int batch) {
+    const LevelGeom g = level_geom(p, p.levels - 1);
+    const size_t cnt = (size_t)batch * 4 * g.Hk * g.Wk;
+    InitWs L;
+    L.hi = 0;
+    L.lo = align256(cnt * kKBytes);
+    L.sq = L.lo + align256(cnt * kKBytes);
+    L.total = L.sq + align256(cnt * sizeof(uint32_t));
+    return L;
 }
 
 }  // namespace
@@ -103,15 +262,23 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a) {
 
 using namespace sff;
 
+extern "C" size_t sff_init_workspace_bytes(const sff_params* p, int32_t batch) {
+    if (!params_ok(p) || batch < 1 || batch > 32767) return 0;
+    return init_ws(*p, batch).total;
+}
+
 extern "C" sff_status sff_init_nn(const sff_params* p, int32_t batch, int32_t dir,
                                   const int16_t* desc, int16_t* hyp, uint32_t* cost,
-                                  void* stream) {
+                                  void* workspace, size_t workspace_bytes, void* stream) {
     if (!params_ok(p) || batch < 1 || batch > 32767 || (dir != 1 && dir != -1 && dir != 0) ||
         !desc || !hyp || !cost)
         return SFF_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(desc) & 15) != 0 || (reinterpret_cast<uintptr_t>(hyp) & 7) != 0 ||
         (reinterpret_cast<uintptr_t>(cost) & 3) != 0)
         return SFF_ERR_INVALID_ARG;
+    const InitWs L = init_ws(*p, batch);
+    if (!workspace || workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return SFF_ERR_WORKSPACE;
     const int level = p->levels - 1;
     const LevelGeom g = level_geom(*p, level);
     InitArgs a;
@@ -128,13 +295,32 @@ extern "C" sff_status sff_init_nn(const sff_params* p, int32_t batch, int32_t di
     a.batch = batch;
     a.ndir = dir == 0 ? 2 : 1;
     a.dir0 = dir == 0 ? 1 : dir;
-    const dim3 grid((g.Wk + 15) / 16, (g.Hk + 15) / 16, a.ndir * batch);
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    SplitPlanes P;
+    P.hi = reinterpret_cast<int8_t*>(ws + L.hi);
+    P.lo = reinterpret_cast<int8_t*>(ws + L.lo);
+    P.sq = reinterpret_cast<uint32_t*>(ws + L.sq);
+    const int nz4 = 4 * batch;
+    const dim3 sgrid((g.Hk * g.Wk + 255) / 256, nz4);
+    const dim3 grid((g.Wk + 15) / 16, (g.Hk + kQRows - 1) / kQRows, a.ndir * batch);
     hipStream_t st = as_stream(stream);
     switch (p->C) {
-        case 1: hipLaunchKernelGGL(init_nn_kernel<1>, grid, dim3(256), 0, st, a); break;
-        case 2: hipLaunchKernelGGL(init_nn_kernel<2>, grid, dim3(256), 0, st, a); break;
-        case 3: hipLaunchKernelGGL(init_nn_kernel<3>, grid, dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL(init_nn_kernel<4>, grid, dim3(256), 0, st, a); break;
+        case 1:
+            hipLaunchKernelGGL(split_kernel<1>, sgrid, dim3(256), 0, st, desc, P, a.H, a.W, a.n, a.Hk, a.Wk, nz4);
+            hipLaunchKernelGGL(init_nn_kernel<1>, grid, dim3(256), 0, st, a, P);
+            break;
+        case 2:
+            hipLaunchKernelGGL(split_kernel<2>, sgrid, dim3(256), 0, st, desc, P, a.H, a.W, a.n, a.Hk, a.Wk, nz4);
+            hipLaunchKernelGGL(init_nn_kernel<2>, grid, dim3(256), 0, st, a, P);
+            break;
+        case 3:
+            hipLaunchKernelGGL(split_kernel<3>, sgrid, dim3(256), 0, st, desc, P, a.H, a.W, a.n, a.Hk, a.Wk, nz4);
+            hipLaunchKernelGGL(init_nn_kernel<3>, grid, dim3(256), 0, st, a, P);
+            break;
+        default:
+            hipLaunchKernelGGL(split_kernel<4>, sgrid, dim3(256), 0, st, desc, P, a.H, a.W, a.n, a.Hk, a.Wk, nz4);
+            hipLaunchKernelGGL(init_nn_kernel<4>, grid, dim3(256), 0, st, a, P);
+            break;
     }
     return launch_status();
 }

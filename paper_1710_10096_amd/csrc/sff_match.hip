@@ -48,34 +48,59 @@ __device__ __forceinline__ uint2 pack(const Hyp& h) {
     return r;
 }
 
+__device__ __forceinline__ bool same(const Hyp& a, const Hyp& b) {
+    return a.u == b.u && a.v == b.v && a.d0 == b.d0 && a.d1 == b.d1;
+}
+
 template <int C>
 struct Views {
     const int16_t *T, *S, *X;
     int H, W, s;
 
     // eq. (1): temporal (x+u, y+v), stereo (x - s d0, y), cross (x+u - s d1, y+v),
-    // each target clamped to the image.
-    __device__ __forceinline__ uint32_t cost(const Desc<C>& ref, int x, int y, const Hyp& h) const {
+    // each target clamped to the image.  The three squared distances are
+    // non-negative, so once a partial sum reaches `bound` the candidate cannot
+    // be strictly cheaper than `bound`; the remaining gathers are skipped and a
+    // value >= bound is returned.  Below `bound` the exact cost is returned.
+    __device__ __forceinline__ uint32_t cost_below(const Desc<C>& ref, int x, int y, const Hyp& h,
+                                                   uint32_t bound) const {
         const int ty = clampi(y + h.v, 0, H - 1);
         const int txT = clampi(x + h.u, 0, W - 1);
+        uint32_t c = desc_ssd<C>(ref, load_desc<C>(T, (size_t)ty * W + txT));
+        if (c >= bound) return c;
         const int txS = clampi(x - s * h.d0, 0, W - 1);
+        c += desc_ssd<C>(ref, load_desc<C>(S, (size_t)y * W + txS));
+        if (c >= bound) return c;
         const int txX = clampi(x + h.u - s * h.d1, 0, W - 1);
-        const Desc<C> dT = load_desc<C>(T, (size_t)ty * W + txT);
-        const Desc<C> dS = load_desc<C>(S, (size_t)y * W + txS);
-        const Desc<C> dX = load_desc<C>(X, (size_t)ty * W + txX);
-        return desc_ssd<C>(ref, dT) + desc_ssd<C>(ref, dS) + desc_ssd<C>(ref, dX);
+        c += desc_ssd<C>(ref, load_desc<C>(X, (size_t)ty * W + txX));
+        return c;
     }
 };
+
+// Blocks are dealt to the 8 XCDs round-robin (block id mod 8).  Renumber them
+// so that each XCD receives one contiguous run of tiles (a band of rows of one
+// field), which keeps the descriptor rows an XCD gathers in its own L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+    const int xcd = bid & 7, k = bid >> 3;
+    const int q = nb >> 3, rem = nb & 7;
+    return xcd * q + min(xcd, rem) + k;
+}
 
 // mode: 0 = regular half-step; 1 = iteration-0 red half after a hand-off (own
 // and neighbours from the coarse field); 2 = iteration-0 black half after a
 // hand-off (own from the coarse field, neighbours already at this level);
 // 3 = hand-off only (no propagation or search), used when iters == 0.
 template <int C>
-__global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int colour, int mode) {
-    const int i = blockIdx.y * 4 + threadIdx.y;
-    const int jc = blockIdx.x * 64 + threadIdx.x;
-    const int z = blockIdx.z;
+__global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int colour, int mode,
+                                                        int tiles_x, int tiles_y) {
+    // tile = 4 grid rows x 64 pixels of the half-step's colour (all pixels for mode 3)
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int per_field = tiles_x * tiles_y;
+    const int z = tile / per_field;
+    const int tr = tile - z * per_field;
+    const int ty = tr / tiles_x, tx = tr - ty * tiles_x;
+    const int i = ty * 4 + (threadIdx.x >> 6);
+    const int jc = tx * 64 + (threadIdx.x & 63);
     if (i >= a.Hk) return;
     const int j = mode == 3 ? jc : 2 * jc + ((i + colour) & 1);
     if (j >= a.Wk) return;
@@ -95,32 +120,48 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
     const int x = n * j, y = n * i;
     const Desc<C> ref = load_desc<C>(R, (size_t)y * a.W + x);
 
-    const uint2* field = reinterpret_cast<const uint2*>(a.hyp) + (size_t)z * a.Hk * a.Wk;
-    const uint2* coarse = reinterpret_cast<const uint2*>(a.hyp_coarse) + (size_t)z * a.Hc * a.Wc;
+    const size_t field_off = (size_t)z * a.Hk * a.Wk;
+    const uint2* field = reinterpret_cast<const uint2*>(a.hyp) + field_off;
+    const uint2* coarse = mode == 0 ? nullptr
+                                    : reinterpret_cast<const uint2*>(a.hyp_coarse) +
+                                          (size_t)z * a.Hc * a.Wc;
     const size_t o = (size_t)i * a.Wk + j;
 
     Hyp best;
     uint32_t bestc;
     if (mode == 0) {
         best = unpack(field[o]);
-        bestc = a.cost[(size_t)z * a.Hk * a.Wk + o];
+        bestc = a.cost[field_off + o];
     } else {
         best = unpack(coarse[(size_t)(i >> 1) * a.Wc + (j >> 1)]);
-        bestc = V.cost(ref, x, y, best);
+        bestc = V.cost_below(ref, x, y, best, 0xFFFFFFFFu);
     }
     if (mode != 3) {
-        // propagation: left, up, right, down
+        // propagation: left, up, right, down.  A vector equal to one already
+        // scored has the same cost and cannot be a strict improvement.
         const int ni[4] = {i, i - 1, i, i + 1};
         const int nj[4] = {j - 1, j, j + 1, j};
+        Hyp nh[4];
+        bool in[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (ni[q] < 0 || ni[q] >= a.Hk || nj[q] < 0 || nj[q] >= a.Wk) continue;
-            const Hyp h = unpack(mode == 1 ? coarse[(size_t)(ni[q] >> 1) * a.Wc + (nj[q] >> 1)]
-                                           : field[(size_t)ni[q] * a.Wk + nj[q]]);
-            const uint32_t c = V.cost(ref, x, y, h);
+            in[q] = ni[q] >= 0 && ni[q] < a.Hk && nj[q] >= 0 && nj[q] < a.Wk;
+            if (in[q])
+                nh[q] = unpack(mode == 1 ? coarse[(size_t)(ni[q] >> 1) * a.Wc + (nj[q] >> 1)]
+                                         : field[(size_t)ni[q] * a.Wk + nj[q]]);
+        }
+        const Hyp own = best;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!in[q]) continue;
+            bool dup = same(nh[q], own);
+#pragma unroll
+            for (int p = 0; p < q; ++p) dup = dup || (in[p] && same(nh[q], nh[p]));
+            if (dup) continue;
+            const uint32_t c = V.cost_below(ref, x, y, nh[q], bestc);
             if (c < bestc) {
                 bestc = c;
-                best = h;
+                best = nh[q];
             }
         }
         // random search around the propagated vector
@@ -140,32 +181,36 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
             c.v = clampi(centre.v + uniform_offset(rnd.y, r), -a.fmax, a.fmax);
             c.d0 = clampi(centre.d0 + uniform_offset(rnd.z, r), 0, a.dmax);
             c.d1 = clampi(centre.d1 + uniform_offset(rnd.w, r), 0, a.dmax);
-            const uint32_t cc = V.cost(ref, x, y, c);
+            if (same(c, centre)) continue;
+            const uint32_t cc = V.cost_below(ref, x, y, c, bestc);
             if (cc < bestc) {
                 bestc = cc;
                 best = c;
             }
         }
     }
-    reinterpret_cast<uint2*>(a.hyp)[(size_t)z * a.Hk * a.Wk + o] = pack(best);
-    a.cost[(size_t)z * a.Hk * a.Wk + o] = bestc;
+    reinterpret_cast<uint2*>(a.hyp)[field_off + o] = pack(best);
+    a.cost[field_off + o] = bestc;
 }
 
 template <int C>
 sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
-    const int half_w = (a.Wk + 1) / 2;
-    const dim3 grid_half((half_w + 63) / 64, (a.Hk + 3) / 4, a.ndir * a.batch);
-    const dim3 block(64, 4);
+    const int nz = a.ndir * a.batch;
+    const int tiles_y = (a.Hk + 3) / 4;
+    const dim3 block(256);
     if (a.hyp_coarse && iters == 0) {
-        const dim3 grid_all((a.Wk + 63) / 64, (a.Hk + 3) / 4, a.ndir * a.batch);
-        hipLaunchKernelGGL(half_step_kernel<C>, grid_all, block, 0, st, a, 0, 0, 3);
+        const int tiles_x = (a.Wk + 63) / 64;
+        hipLaunchKernelGGL(half_step_kernel<C>, dim3(tiles_x * tiles_y * nz), block, 0, st, a, 0, 0,
+                           3, tiles_x, tiles_y);
         return launch_status();
     }
+    const int tiles_x = ((a.Wk + 1) / 2 + 63) / 64;
     for (int it = 0; it < iters; ++it)
         for (int colour = 0; colour < 2; ++colour) {
             int mode = 0;
             if (a.hyp_coarse && it == 0) mode = colour == 0 ? 1 : 2;
-            hipLaunchKernelGGL(half_step_kernel<C>, grid_half, block, 0, st, a, it, colour, mode);
+            hipLaunchKernelGGL(half_step_kernel<C>, dim3(tiles_x * tiles_y * nz), block, 0, st, a,
+                               it, colour, mode, tiles_x, tiles_y);
         }
     return launch_status();
 }

@@ -23,6 +23,7 @@ class PairMatcher:
         dev = torch.device(device)
         self.desc = torch.empty((B, 4, p.H, p.W, p.C, 16), dtype=torch.int16, device=dev)
         ws = max(api.sff_wht_workspace_bytes(p, 4 * B, k) for k in range(p.levels))
+        ws = max(ws, api.sff_init_workspace_bytes(p, B))
         self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
         self.hyp, self.cost = [], []
         for k in range(p.levels):
@@ -48,7 +49,8 @@ class PairMatcher:
             api.sff_wht_features(p, flat_img, k, flat_desc, self.ws, stream)
             mk(f"features:L{k}")
             if k == top:
-                api.sff_init_nn(p, self.desc, api.DIR_BOTH, self.hyp[k], self.cost[k], stream)
+                api.sff_init_nn(p, self.desc, api.DIR_BOTH, self.hyp[k], self.cost[k], self.ws,
+                                stream)
                 mk(f"init:L{k}")
                 api.sff_match_level(p, self.desc, api.DIR_BOTH, k, seeds, self.hyp[k],
                                     self.cost[k], None, stream)

@@ -82,7 +82,8 @@ def test_invalid_params_rejected_without_launch(bad):
         setattr(p, k, v)
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
     assert L.sff_wht_features(ctypes.byref(p), 1, 0, fake, fake, None, 0, None) == 1
-    assert L.sff_init_nn(ctypes.byref(p), 1, 0, fake, fake, fake, None) == 1
+    assert L.sff_init_nn(ctypes.byref(p), 1, 0, fake, fake, fake, fake, 1 << 30, None) == 1
+    assert L.sff_init_workspace_bytes(ctypes.byref(p), 1) == 0
     assert L.sff_match_level(ctypes.byref(p), 1, 0, 0, fake, fake, None, fake, fake, None) == 1
     assert L.sff_consistency(ctypes.byref(p), 1, fake, fake, fake, fake, None) == 1
     assert L.sff_wht_workspace_bytes(ctypes.byref(p), 4, 0) == 0
@@ -96,17 +97,23 @@ def test_invalid_arguments_rejected():
     f = ctypes.c_void_p(0x1000)
     # null pointers
     assert L.sff_wht_features(P, 1, 0, None, f, None, 0, None) == 1
-    assert L.sff_init_nn(P, 1, 0, f, None, f, None) == 1
+    assert L.sff_init_nn(P, 1, 0, f, None, f, f, 1 << 30, None) == 1
     assert L.sff_match_level(P, 1, 0, 0, f, None, None, f, f, None) == 1
     assert L.sff_consistency(P, 1, f, f, None, f, None) == 1
     # bad batch / direction / level
-    assert L.sff_init_nn(P, 0, 0, f, f, f, None) == 1
-    assert L.sff_init_nn(P, 1, 2, f, f, f, None) == 1
+    assert L.sff_init_nn(P, 0, 0, f, f, f, f, 1 << 30, None) == 1
+    assert L.sff_init_nn(P, 1, 2, f, f, f, f, 1 << 30, None) == 1
     assert L.sff_match_level(P, 1, 0, 1, f, f, None, f, f, None) == 1      # level >= levels
     assert L.sff_match_level(P, 1, 0, 0, f, f, f, f, f, None) == 1         # hand-off at top
     assert L.sff_wht_features(P, 1, 1, f, f, None, 0, None) == 1          # level >= levels
     # misaligned descriptor pointer
-    assert L.sff_init_nn(P, 1, 0, ctypes.c_void_p(0x1002), f, f, None) == 1
+    assert L.sff_init_nn(P, 1, 0, ctypes.c_void_p(0x1002), f, f, f, 1 << 30, None) == 1
+    # init workspace missing, too small or misaligned
+    need = L.sff_init_workspace_bytes(P, 1)
+    assert need > 0
+    assert L.sff_init_nn(P, 1, 0, f, f, f, None, need, None) == 4
+    assert L.sff_init_nn(P, 1, 0, f, f, f, f, need - 1, None) == 4
+    assert L.sff_init_nn(P, 1, 0, f, f, f, ctypes.c_void_p(0x1010), need, None) == 4
     # workspace missing at level >= 1
     p2 = _good()
     p2.levels = 3
