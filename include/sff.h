@@ -164,6 +164,102 @@ sff_status sff_match_level(const sff_params* p, int32_t batch, int32_t dir, int3
 sff_status sff_consistency(const sff_params* p, int32_t batch, const int16_t* hyp_fwd,
                            const int16_t* hyp_inv, uint8_t* valid, uint32_t* err, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Window form of the matching cost on real-valued feature maps (eq. (1),
+ * Section 3.1: feature distances summed over a window around the pixel for the
+ * temporal, stereo and cross correspondences, replicated borders), FP32:
+ *   cost(p) = sum_corr sum_{w in {-3..4}^2} sum_c
+ *             (F_R(clamp(p + w), c) - F_corr(clamp(t_corr(p) + w), c))^2,
+ *   t_corr(p) = clamp(p + o_corr), o_T = (u, v), o_S = (-s d0, 0),
+ *   o_X = (u - s d1, v), s = dir.
+ * feat: [batch][4][H][W][cf] float32, views in the canonical order, 16-byte
+ *   aligned; cf in {4, 8, 16, 32, 64}.
+ * hyp:  [batch][H][W][4] int16 full-resolution vectors (held fixed).
+ * dir:  SFF_DIR_FORWARD or SFF_DIR_INVERSE.
+ * Errors: SFF_ERR_INVALID_ARG (shapes, alignment, dir, batch*H*W >= 2^31). */
+sff_status sff_cost_f32_fwd(int32_t batch, int32_t H, int32_t W, int32_t cf, int32_t dir,
+                            const float* feat, const int16_t* hyp, float* cost_px, void* stream);
+
+/* Device workspace (bytes) that sff_cost_f32_bwd needs. */
+size_t sff_cost_f32_bwd_workspace_bytes(int32_t batch, int32_t H, int32_t W);
+
+/* Gradient of L = sum_p grad_cost[p] * cost(p) with respect to all four
+ * feature maps (chain rule: each term with difference delta contributes
+ * +2 g delta to its reference entry and -2 g delta to its target entry).
+ * grad_cost: [batch][H][W] float32.  grad_feat: [batch][4][H][W][cf] float32,
+ * fully overwritten.  Deterministic: the same inputs give the same bits.
+ * workspace: device buffer, 256-byte aligned, at least
+ *   sff_cost_f32_bwd_workspace_bytes(batch, H, W) bytes.
+ * Errors: SFF_ERR_INVALID_ARG, SFF_ERR_WORKSPACE. */
+sff_status sff_cost_f32_bwd(int32_t batch, int32_t H, int32_t W, int32_t cf, int32_t dir,
+                            const float* feat, const int16_t* hyp, const float* grad_cost,
+                            float* grad_feat, void* workspace, size_t workspace_bytes,
+                            void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned features in place of the WHT features of the matching cost
+ * (Section 3.1): 3x3 convolutions, BF16 NHWC tensors (raw bfloat16 bits as
+ * uint16_t), FP32 accumulation on the matrix cores, zero padding, dilation
+ * `dil` (1..16).  Weights [cout][3][3][cin] BF16, tap (ky, kx) reading offset
+ * ((ky - 1) dil, (kx - 1) dil); bias [cout] FP32.  Supported: cin in {3, 32},
+ * cout = 32.  Results are rounded to BF16 (nearest even) on store.
+ *   y = act(bias + sum_tap W_tap x_shifted), act = ReLU if relu != 0.
+ * Errors: SFF_ERR_INVALID_ARG (shapes, NULL pointers, y not 8-byte aligned). */
+sff_status sff_conv3x3_bf16_fwd(int32_t n, int32_t H, int32_t W, int32_t cin, int32_t cout,
+                                int32_t dil, int32_t relu, const uint16_t* x, const uint16_t* w,
+                                const float* bias, uint16_t* y, void* stream);
+
+/* Device workspace (bytes) for sff_conv3x3_bf16_dgrad / _wgrad. */
+size_t sff_conv3x3_bf16_bwd_workspace_bytes(int32_t n, int32_t H, int32_t W, int32_t cin,
+                                            int32_t cout);
+
+/* Input gradient (cin = 32): dx = sum over the outputs that read each input of
+ * W times dz, with dz = dy * (relu_out > 0) when relu_out (the layer's ReLU
+ * output) is given, dz = dy when it is NULL.  dy [n][H][W][cout], dx
+ * [n][H][W][cin], BF16.  Errors: SFF_ERR_INVALID_ARG, SFF_ERR_WORKSPACE. */
+sff_status sff_conv3x3_bf16_dgrad(int32_t n, int32_t H, int32_t W, int32_t cin, int32_t cout,
+                                  int32_t dil, const uint16_t* dy, const uint16_t* relu_out,
+                                  const uint16_t* w, uint16_t* dx, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+
+/* Weight and bias gradients: dw [cout][3][3][cin] = sum_p dz[p] x[p + tap]^T,
+ * db [cout] = sum_p dz[p], FP32, dz as for dgrad.  Per-block partial sums are
+ * reduced in a fixed order (deterministic).  Errors: SFF_ERR_INVALID_ARG,
+ * SFF_ERR_WORKSPACE. */
+sff_status sff_conv3x3_bf16_wgrad(int32_t n, int32_t H, int32_t W, int32_t cin, int32_t cout,
+                                  int32_t dil, const uint16_t* x, const uint16_t* dy,
+                                  const uint16_t* relu_out, float* dw, float* db, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+
+/* The level-k image of the scale simulation alone (Section 3.1, "Multi-Scale
+ * Propagation"; the smoothing step of sff_wht_features): img [nimg][H][W][C]
+ * -> out [nimg][H][W][C] uint8 (a copy at level 0).  workspace as for
+ * sff_wht_features.  Used to feed learned features per level.
+ * Errors: SFF_ERR_INVALID_ARG, SFF_ERR_WORKSPACE. */
+sff_status sff_smooth_level(const sff_params* p, int32_t nimg, int32_t level, const uint8_t* img,
+                            uint8_t* out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Learned descriptors: per-pixel L2 normalisation of 32-channel BF16 features
+ * feat [n][H][W][32], scaled and rounded to int16: desc = rint(scale f / |f|)
+ * (0 < scale <= 8192).  desc [n][H][W][32] is a C = 2 descriptor map for
+ * sff_init_nn / sff_match_level (squared distances stay far below 2^31 per
+ * map).  Errors: SFF_ERR_INVALID_ARG. */
+sff_status sff_quantise_features(int32_t n, int32_t H, int32_t W, const uint16_t* feat, float scale,
+                                 int16_t* desc, void* stream);
+
+/* Triplet loss on normalised 32-channel BF16 features feat [npx][32]: for
+ * triple t = (a, p, n) of pixel indices (triplets [ntrip][3] int32, device),
+ * loss[t] = max(0, margin + |a^ - p^|^2 - |a^ - n^|^2); weight * dloss/dfeat
+ * is ADDED to grad [npx][32] FP32 (atomic adds: summation order may vary).
+ * Triples with an index outside [0, npx) give loss 0 and no gradient.
+ * Errors: SFF_ERR_INVALID_ARG. */
+sff_status sff_triplet_loss(int32_t npx, const uint16_t* feat, int32_t ntrip,
+                            const int32_t* triplets, float margin, float weight, float* loss,
+                            float* grad, void* stream);
+
+/* out[i] = bf16(grad[i]) (nearest even), then grad[i] = 0, for i < n. */
+sff_status sff_take_grad_bf16(size_t n, float* grad, uint16_t* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

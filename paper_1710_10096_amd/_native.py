@@ -29,7 +29,10 @@ class SffParams(ctypes.Structure):
 
 EXPORTS = ("sff_status_string", "sff_version", "sff_lanczos_q14", "sff_wht_workspace_bytes",
            "sff_wht_features", "sff_init_workspace_bytes", "sff_init_nn", "sff_match_level",
-           "sff_consistency")
+           "sff_consistency", "sff_cost_f32_fwd", "sff_cost_f32_bwd_workspace_bytes",
+           "sff_cost_f32_bwd", "sff_conv3x3_bf16_fwd", "sff_conv3x3_bf16_bwd_workspace_bytes",
+           "sff_conv3x3_bf16_dgrad", "sff_conv3x3_bf16_wgrad", "sff_smooth_level",
+           "sff_quantise_features", "sff_triplet_loss", "sff_take_grad_bf16")
 
 _lib = None
 
@@ -62,5 +65,27 @@ def lib() -> ctypes.CDLL:
     L.sff_match_level.restype = i32
     L.sff_consistency.argtypes = [PP, i32, P, P, P, P, P]
     L.sff_consistency.restype = i32
+    L.sff_cost_f32_fwd.argtypes = [i32] * 5 + [P, P, P, P]
+    L.sff_cost_f32_fwd.restype = i32
+    L.sff_cost_f32_bwd_workspace_bytes.argtypes = [i32] * 3
+    L.sff_cost_f32_bwd_workspace_bytes.restype = ctypes.c_size_t
+    L.sff_cost_f32_bwd.argtypes = [i32] * 5 + [P, P, P, P, P, ctypes.c_size_t, P]
+    L.sff_cost_f32_bwd.restype = i32
+    L.sff_conv3x3_bf16_fwd.argtypes = [i32] * 7 + [P, P, P, P, P]
+    L.sff_conv3x3_bf16_fwd.restype = i32
+    L.sff_conv3x3_bf16_bwd_workspace_bytes.argtypes = [i32] * 5
+    L.sff_conv3x3_bf16_bwd_workspace_bytes.restype = ctypes.c_size_t
+    L.sff_conv3x3_bf16_dgrad.argtypes = [i32] * 6 + [P, P, P, P, P, ctypes.c_size_t, P]
+    L.sff_conv3x3_bf16_dgrad.restype = i32
+    L.sff_conv3x3_bf16_wgrad.argtypes = [i32] * 6 + [P, P, P, P, P, P, ctypes.c_size_t, P]
+    L.sff_conv3x3_bf16_wgrad.restype = i32
+    L.sff_smooth_level.argtypes = [PP, i32, i32, P, P, P, ctypes.c_size_t, P]
+    L.sff_smooth_level.restype = i32
+    L.sff_quantise_features.argtypes = [i32, i32, i32, P, ctypes.c_float, P, P]
+    L.sff_quantise_features.restype = i32
+    L.sff_triplet_loss.argtypes = [i32, P, i32, P, ctypes.c_float, ctypes.c_float, P, P, P]
+    L.sff_triplet_loss.restype = i32
+    L.sff_take_grad_bf16.argtypes = [ctypes.c_size_t, P, P, P]
+    L.sff_take_grad_bf16.restype = i32
     _lib = L
     return L

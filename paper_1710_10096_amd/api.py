@@ -155,3 +155,169 @@ def sff_consistency(p, hyp_fwd: torch.Tensor, hyp_inv: torch.Tensor, valid=None,
                                  _ptr(valid, torch.uint8, "valid"), _ptr(err, torch.int32, "err"),
                                  _stream(stream)), "sff_consistency")
     return valid, err
+
+
+def sff_cost_f32_fwd(feat: torch.Tensor, hyp: torch.Tensor, dir: int, cost=None, stream=None):
+    """feat float32 [batch][4][H][W][cf], hyp int16 [batch][H][W][4] -> cost [batch][H][W]."""
+    B, four, H, W, cf = feat.shape
+    if four != 4 or tuple(hyp.shape) != (B, H, W, 4):
+        raise ValueError("feat must be [batch][4][H][W][cf] and hyp [batch][H][W][4]")
+    if cost is None:
+        cost = torch.empty((B, H, W), dtype=torch.float32, device=feat.device)
+    _check(lib().sff_cost_f32_fwd(B, H, W, cf, dir, _ptr(feat, torch.float32, "feat"),
+                                  _ptr(hyp, torch.int16, "hyp"), _ptr(cost, torch.float32, "cost"),
+                                  _stream(stream)), "sff_cost_f32_fwd")
+    return cost
+
+
+def sff_cost_f32_bwd_workspace_bytes(batch: int, H: int, W: int) -> int:
+    return int(lib().sff_cost_f32_bwd_workspace_bytes(batch, H, W))
+
+
+def sff_cost_f32_bwd(feat: torch.Tensor, hyp: torch.Tensor, dir: int, grad_cost: torch.Tensor,
+                     grad_feat=None, workspace=None, stream=None):
+    """Gradient of sum(grad_cost * cost) w.r.t. feat (all four maps)."""
+    B, four, H, W, cf = feat.shape
+    if grad_feat is None:
+        grad_feat = torch.empty_like(feat)
+    if workspace is None:
+        workspace = torch.empty(sff_cost_f32_bwd_workspace_bytes(B, H, W), dtype=torch.uint8,
+                                device=feat.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(lib().sff_cost_f32_bwd(B, H, W, cf, dir, _ptr(feat, torch.float32, "feat"),
+                                  _ptr(hyp, torch.int16, "hyp"),
+                                  _ptr(grad_cost, torch.float32, "grad_cost"),
+                                  _ptr(grad_feat, torch.float32, "grad_feat"),
+                                  _ptr(workspace, None, "workspace"), ws_bytes, _stream(stream)),
+           "sff_cost_f32_bwd")
+    return grad_feat
+
+
+class MatchCost(torch.autograd.Function):
+    """Per-pixel window cost of eq. (1) at fixed vectors, differentiable with
+    respect to the four FP32 feature maps (forward and backward are libsff
+    kernels)."""
+
+    @staticmethod
+    def forward(ctx, feat: torch.Tensor, hyp: torch.Tensor, dir: int = DIR_FORWARD):
+        feat = feat.contiguous()
+        ctx.save_for_backward(feat, hyp)
+        ctx.dir = dir
+        return sff_cost_f32_fwd(feat, hyp, dir)
+
+    @staticmethod
+    def backward(ctx, grad_cost):
+        feat, hyp = ctx.saved_tensors
+        g = sff_cost_f32_bwd(feat, hyp, ctx.dir, grad_cost.contiguous().float())
+        return g, None, None
+
+
+def sff_conv3x3_bf16_fwd(x: torch.Tensor, w: torch.Tensor, bias: torch.Tensor | None, dil: int = 1,
+                         relu: bool = False, y=None, stream=None):
+    """x bf16 [n][H][W][cin], w bf16 [cout][3][3][cin], bias f32 [cout] -> y bf16."""
+    n, H, W, cin = x.shape
+    cout = w.shape[0]
+    if y is None:
+        y = torch.empty((n, H, W, cout), dtype=torch.bfloat16, device=x.device)
+    _check(lib().sff_conv3x3_bf16_fwd(n, H, W, cin, cout, dil, int(bool(relu)),
+                                      _ptr(x, torch.bfloat16, "x"), _ptr(w, torch.bfloat16, "w"),
+                                      _ptr(bias, torch.float32, "bias"),
+                                      _ptr(y, torch.bfloat16, "y"), _stream(stream)),
+           "sff_conv3x3_bf16_fwd")
+    return y
+
+
+def _conv_ws(n, H, W, cin, cout, device, workspace):
+    if workspace is not None:
+        return workspace
+    nb = int(lib().sff_conv3x3_bf16_bwd_workspace_bytes(n, H, W, cin, cout))
+    return torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
+
+
+def sff_conv3x3_bf16_dgrad(dy: torch.Tensor, w: torch.Tensor, dil: int = 1,
+                           relu_out: torch.Tensor | None = None, dx=None, workspace=None,
+                           stream=None):
+    n, H, W, cout = dy.shape
+    cin = w.shape[3]
+    if dx is None:
+        dx = torch.empty((n, H, W, cin), dtype=torch.bfloat16, device=dy.device)
+    ws = _conv_ws(n, H, W, cin, cout, dy.device, workspace)
+    _check(lib().sff_conv3x3_bf16_dgrad(n, H, W, cin, cout, dil, _ptr(dy, torch.bfloat16, "dy"),
+                                        _ptr(relu_out, torch.bfloat16, "relu_out"),
+                                        _ptr(w, torch.bfloat16, "w"), _ptr(dx, torch.bfloat16, "dx"),
+                                        _ptr(ws, None, "ws"), ws.numel(), _stream(stream)),
+           "sff_conv3x3_bf16_dgrad")
+    return dx
+
+
+def sff_conv3x3_bf16_wgrad(x: torch.Tensor, dy: torch.Tensor, dil: int = 1,
+                           relu_out: torch.Tensor | None = None, dw=None, db=None, workspace=None,
+                           stream=None):
+    n, H, W, cin = x.shape
+    cout = dy.shape[3]
+    if dw is None:
+        dw = torch.empty((cout, 3, 3, cin), dtype=torch.float32, device=x.device)
+    if db is None:
+        db = torch.empty((cout,), dtype=torch.float32, device=x.device)
+    ws = _conv_ws(n, H, W, cin, cout, x.device, workspace)
+    _check(lib().sff_conv3x3_bf16_wgrad(n, H, W, cin, cout, dil, _ptr(x, torch.bfloat16, "x"),
+                                        _ptr(dy, torch.bfloat16, "dy"),
+                                        _ptr(relu_out, torch.bfloat16, "relu_out"),
+                                        _ptr(dw, torch.float32, "dw"), _ptr(db, torch.float32, "db"),
+                                        _ptr(ws, None, "ws"), ws.numel(), _stream(stream)),
+           "sff_conv3x3_bf16_wgrad")
+    return dw, db
+
+
+def sff_smooth_level(p, img: torch.Tensor, level: int, out=None, workspace=None, stream=None):
+    """The level-k smoothed images, uint8 [n][H][W][C]."""
+    pp = _params(p)
+    nimg = img.shape[0]
+    if out is None:
+        out = torch.empty_like(img)
+    need = sff_wht_workspace_bytes(pp, nimg, level)
+    if workspace is None and need > 0:
+        workspace = torch.empty(need, dtype=torch.uint8, device=img.device)
+    ws_bytes = 0 if workspace is None else workspace.numel()
+    _check(lib().sff_smooth_level(ctypes.byref(pp), nimg, level, _ptr(img, torch.uint8, "img"),
+                                  _ptr(out, torch.uint8, "out"), _ptr(workspace, None, "ws"),
+                                  ws_bytes, _stream(stream)), "sff_smooth_level")
+    return out
+
+
+def sff_quantise_features(feat: torch.Tensor, scale: float = 4096.0, desc=None, stream=None):
+    """bf16 [n][H][W][32] -> int16 descriptors [n][H][W][2][16] (C = 2 records)."""
+    n, H, W, F = feat.shape
+    if F != 32:
+        raise ValueError("features must have 32 channels")
+    if desc is None:
+        desc = torch.empty((n, H, W, 2, 16), dtype=torch.int16, device=feat.device)
+    _check(lib().sff_quantise_features(n, H, W, _ptr(feat, torch.bfloat16, "feat"), float(scale),
+                                       _ptr(desc, torch.int16, "desc"), _stream(stream)),
+           "sff_quantise_features")
+    return desc
+
+
+def sff_triplet_loss(feat: torch.Tensor, triplets: torch.Tensor, margin: float, grad: torch.Tensor,
+                     weight: float = 1.0, loss=None, stream=None):
+    """feat bf16 [..][32] (pixels flattened), triplets int32 [T][3] -> loss [T]; adds
+    weight * dloss/dfeat into grad (float32, same pixel count)."""
+    npx = feat.numel() // 32
+    T = triplets.shape[0]
+    if loss is None:
+        loss = torch.empty((T,), dtype=torch.float32, device=feat.device)
+    _check(lib().sff_triplet_loss(npx, _ptr(feat, torch.bfloat16, "feat"), T,
+                                  _ptr(triplets, torch.int32, "triplets"), float(margin),
+                                  float(weight), _ptr(loss, torch.float32, "loss"),
+                                  _ptr(grad, torch.float32, "grad"), _stream(stream)),
+           "sff_triplet_loss")
+    return loss
+
+
+def sff_take_grad_bf16(grad: torch.Tensor, out=None, stream=None):
+    if out is None:
+        out = torch.empty(grad.shape, dtype=torch.bfloat16, device=grad.device)
+    _check(lib().sff_take_grad_bf16(grad.numel(), _ptr(grad, torch.float32, "grad"),
+                                    _ptr(out, torch.bfloat16, "out"), _stream(stream)),
+           "sff_take_grad_bf16")
+    return out

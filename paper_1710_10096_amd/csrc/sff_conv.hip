@@ -1,0 +1,330 @@
+// Learned feature extractor: 3x3 convolutions on BF16 NHWC tensors with FP32
+// accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16), used in place
+// of the WHT features of the matching cost (Section 3.1).  Zero padding,
+// dilation d; weights [Cout][3][3][Cin] (tap (ky, kx) reads offset
+// ((ky - 1) d, (kx - 1) d)), bias FP32.
+//
+//   forward:  y = act(b + sum_tap W_tap x_shift)            implicit GEMM, K = 9 Cin
+//   dgrad:    dx = conv(dz, W') with W'[i][ky][kx][o] = W[o][2-ky][2-kx][i],
+//             dz = dy * (relu_out > 0) when the layer had a ReLU
+//   wgrad:    dW_tap = sum_p dz[p] x[p + tap]^T,  db = sum_p dz[p]
+//
+// MFMA lane layout (16 x 16 x 32): lane l supplies row (A) / column (B) l % 16
+// and eight K values for lane group l / 16; it receives C[4 (l / 16) + e][l % 16].
+#include <hip/hip_bfloat16.h>
+
+#include "sff_internal.hpp"
+
+namespace sff {
+namespace {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef uint16_t bf16_t;  // raw bfloat16 bits in memory
+
+__device__ __forceinline__ float bf2f(bf16_t v) { return __uint_as_float((uint32_t)v << 16); }
+
+// round to nearest even
+__device__ __forceinline__ bf16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (bf16_t)((u >> 16) | ((u & 0xFFFF) ? 0x40 : 0));
+    return (bf16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+constexpr int kTilePx = 64;  // output pixels per block (one row segment)
+
+// ---------------------------------------------------------------- forward --
+// Block: 64 consecutive pixels of one row, 4 waves of 16 pixels, all COUT
+// channels.  LDS: weights [COUT][KP] and the im2col tile [64][KP] (KP = 9 CIN
+// rounded up to 32, zero padded).  `mask` (optional) multiplies each input
+// value by (mask > 0), which folds a ReLU derivative into the gradient path.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) conv_fwd_kernel(const bf16_t* __restrict__ x,
+                                                       const bf16_t* __restrict__ mask,
+                                                       const bf16_t* __restrict__ w,
+                                                       const float* __restrict__ bias,
+                                                       bf16_t* __restrict__ y, int H, int W, int dil,
+                                                       int relu) {
+    constexpr int K = 9 * CIN, KP = (K + 31) / 32 * 32;
+    __shared__ __align__(16) bf16_t wl[COUT * KP];
+    __shared__ __align__(16) bf16_t col[kTilePx * KP];
+    const int x0 = blockIdx.x * kTilePx, row = blockIdx.y, n = blockIdx.z;
+    const size_t img = (size_t)n * H * W;
+    for (int e = threadIdx.x; e < COUT * KP; e += 256) {
+        const int o = e / KP, k = e - o * KP;
+        wl[e] = k < K ? w[(size_t)o * K + k] : (bf16_t)0;
+    }
+    for (int e = threadIdx.x; e < kTilePx * KP; e += 256) {
+        const int p = e / KP, k = e - p * KP;
+        bf16_t v = 0;
+        if (k < K) {
+            const int tap = k / CIN, i = k - tap * CIN;
+            const int yy = row + (tap / 3 - 1) * dil, xx = x0 + p + (tap % 3 - 1) * dil;
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W && x0 + p < W) {
+                const size_t o = (img + (size_t)yy * W + xx) * CIN + i;
+                v = x[o];
+                if (mask && !(bf2f(mask[o]) > 0.f)) v = 0;
+            }
+        }
+        col[e] = v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ln = lane & 15, g = lane >> 4;
+    v4f acc[COUT / 16];
+#pragma unroll
+    for (int t = 0; t < COUT / 16; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    const bf16_t* bcol = col + (wv * 16 + ln) * KP + 8 * g;
+#pragma unroll
+    for (int ks = 0; ks < KP / 32; ++ks) {
+        const v8bf bv = *reinterpret_cast<const v8bf*>(bcol + ks * 32);
+#pragma unroll
+        for (int t = 0; t < COUT / 16; ++t) {
+            const v8bf av = *reinterpret_cast<const v8bf*>(wl + (t * 16 + ln) * KP + ks * 32 + 8 * g);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+        }
+    }
+    const int px = x0 + wv * 16 + ln;
+    if (px >= W) return;
+    bf16_t* out = y + (img + (size_t)row * W + px) * COUT;
+#pragma unroll
+    for (int t = 0; t < COUT / 16; ++t) {
+        uint32_t packed[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float v0 = acc[t][2 * h] + (bias ? bias[t * 16 + 4 * g + 2 * h] : 0.f);
+            float v1 = acc[t][2 * h + 1] + (bias ? bias[t * 16 + 4 * g + 2 * h + 1] : 0.f);
+            if (relu) {
+                v0 = fmaxf(v0, 0.f);
+                v1 = fmaxf(v1, 0.f);
+            }
+            packed[h] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+        }
+        *reinterpret_cast<uint2*>(out + t * 16 + 4 * g) = make_uint2(packed[0], packed[1]);
+    }
+}
+
+// W'[i][ky][kx][o] = W[o][2 - ky][2 - kx][i]
+__global__ void flip_weights_kernel(const bf16_t* __restrict__ w, bf16_t* __restrict__ wt, int cin,
+                                    int cout) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= cin * 9 * cout) return;
+    const int i = e / (9 * cout), r = e - i * 9 * cout;
+    const int tap = r / cout, o = r - tap * cout;
+    wt[e] = w[((size_t)o * 9 + (8 - tap)) * cin + i];
+}
+
+// ------------------------------------------------------------ weight grad --
+// Block: a 64-pixel-wide band of kWgRows rows.  For every row segment the
+// block stages dz^T [COUT][64] and, for each kernel row, the input row
+// transposed [CIN][64 + 2 d] in LDS; wave t accumulates the (o-tile, i-tile)
+// pair t for all 9 taps (K = pixels).  Partial results per block are reduced
+// in a fixed order by a second kernel.
+constexpr int kWgRows = 16;
+constexpr int kMaxDil = 16;
+
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) conv_wgrad_kernel(const bf16_t* __restrict__ x,
+                                                         const bf16_t* __restrict__ dy,
+                                                         const bf16_t* __restrict__ mask,
+                                                         float* __restrict__ part, int H, int W,
+                                                         int dil) {
+    constexpr int IT = (CIN + 15) / 16, OT = COUT / 16, XW = kTilePx + 2 * kMaxDil;
+    __shared__ __align__(16) bf16_t dzT[COUT][kTilePx];
+    __shared__ __align__(16) bf16_t xT[3][IT * 16][XW];
+    __shared__ float dbs[4][COUT];
+    const int x0 = blockIdx.x * kTilePx, r0 = blockIdx.y * kWgRows, n = blockIdx.z;
+    const size_t img = (size_t)n * H * W;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ln = lane & 15, g = lane >> 4;
+    // wave wv handles pairs wv, wv + 4, ... of the OT x IT (o-tile, i-tile) grid
+    constexpr int NP = OT * IT, PPW = (NP + 3) / 4;
+    v4f acc[PPW][9];
+#pragma unroll
+    for (int q = 0; q < PPW; ++q)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
+    float db = 0.f;  // thread (wv, lane < COUT) sums dz of channel lane over its pixels
+    for (int rr = 0; rr < kWgRows; ++rr) {
+        const int row = r0 + rr;
+        if (row >= H) break;
+        __syncthreads();
+        for (int e = threadIdx.x; e < COUT * kTilePx; e += 256) {
+            const int p = e / COUT, o = e - p * COUT;
+            bf16_t v = 0;
+            if (x0 + p < W) {
+                const size_t off = (img + (size_t)row * W + x0 + p) * COUT + o;
+                v = dy[off];
+                if (mask && !(bf2f(mask[off]) > 0.f)) v = 0;
+            }
+            dzT[o][p] = v;
+        }
+        for (int e = threadIdx.x; e < 3 * IT * 16 * XW; e += 256) {
+            const int ky = e / (IT * 16 * XW), r = e - ky * IT * 16 * XW;
+            const int c = r / XW, j = r - c * XW;
+            const int yy = row + (ky - 1) * dil, xx = x0 - kMaxDil + j;
+            bf16_t v = 0;
+            if (c < CIN && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                v = x[(img + (size_t)yy * W + xx) * CIN + c];
+            xT[ky][c][j] = v;
+        }
+        __syncthreads();
+        if (lane < COUT) {
+            float s = 0.f;
+            for (int p = wv * 16; p < wv * 16 + 16; ++p) s += bf2f(dzT[lane][p]);
+            db += s;
+        }
+#pragma unroll
+        for (int q = 0; q < PPW; ++q) {
+            const int pair = wv + 4 * q;
+            if (pair >= NP) break;
+            const int ot = pair / IT, it = pair - ot * IT;
+#pragma unroll
+            for (int ks = 0; ks < kTilePx / 32; ++ks) {
+                const v8bf av = *reinterpret_cast<const v8bf*>(&dzT[ot * 16 + ln][ks * 32 + 8 * g]);
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap) {
+                    const int ky = tap / 3, kx = tap % 3;
+                    const bf16_t* src = &xT[ky][it * 16 + ln][kMaxDil + (kx - 1) * dil + ks * 32 + 8 * g];
+                    v8bf bv;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) bv[e] = __builtin_bit_cast(__bf16, src[e]);
+                    acc[q][tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q][tap], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // partial layout: [block][COUT][9][IT*16] + db [block][COUT] (after all blocks)
+    const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    float* pw = part + blk * COUT * 9 * IT * 16;
+#pragma unroll
+    for (int q = 0; q < PPW; ++q) {
+        const int pair = wv + 4 * q;
+        if (pair >= NP) break;
+        const int ot = pair / IT, it = pair - ot * IT;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                pw[((size_t)(ot * 16 + 4 * g + e) * 9 + tap) * IT * 16 + it * 16 + ln] = acc[q][tap][e];
+    }
+    if (lane < COUT) dbs[wv][lane] = db;
+    __syncthreads();
+    if (threadIdx.x < COUT) {
+        const size_t nblk = (size_t)gridDim.x * gridDim.y * gridDim.z;
+        part[nblk * COUT * 9 * IT * 16 + blk * COUT + threadIdx.x] =
+            dbs[0][threadIdx.x] + dbs[1][threadIdx.x] + dbs[2][threadIdx.x] + dbs[3][threadIdx.x];
+    }
+}
+
+// Fixed-order sum of the per-block partials: dw [COUT][3][3][CIN], db [COUT].
+__global__ void wgrad_reduce_kernel(const float* __restrict__ part, float* __restrict__ dw,
+                                    float* __restrict__ db, int nblk, int cin, int cout, int cpad) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int nw = cout * 9 * cin;
+    if (e < nw) {
+        const int o = e / (9 * cin), r = e - o * 9 * cin;
+        const int tap = r / cin, i = r - tap * cin;
+        const size_t stride = (size_t)cout * 9 * cpad;
+        const size_t off = ((size_t)o * 9 + tap) * cpad + i;
+        float s = 0.f;
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * stride + off];
+        dw[e] = s;
+    } else if (e < nw + cout) {
+        const int o = e - nw;
+        const float* pd = part + (size_t)nblk * cout * 9 * cpad;
+        float s = 0.f;
+        for (int b = 0; b < nblk; ++b) s += pd[(size_t)b * cout + o];
+        db[o] = s;
+    }
+}
+
+bool conv_shape_ok(int n, int H, int W, int cin, int cout, int dil) {
+    if (n < 1 || H < 1 || W < 1 || H > 16384 || W > 16384 || n > 65535) return false;
+    if (dil < 1 || dil > kMaxDil) return false;
+    return (cin == 3 || cin == 32) && cout == 32;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t wgrad_part_bytes(int n, int H, int W, int cin, int cout) {
+    const size_t nblk = (size_t)((W + kTilePx - 1) / kTilePx) * ((H + kWgRows - 1) / kWgRows) * n;
+    const int cpad = (cin + 15) / 16 * 16;
+    return align256(nblk * ((size_t)cout * 9 * cpad + cout) * sizeof(float));
+}
+
+}  // namespace
+}  // namespace sff
+
+using namespace sff;
+
+extern "C" sff_status sff_conv3x3_bf16_fwd(int32_t n, int32_t H, int32_t W, int32_t cin,
+                                           int32_t cout, int32_t dil, int32_t relu,
+                                           const uint16_t* x, const uint16_t* w, const float* bias,
+                                           uint16_t* y, void* stream) {
+    if (!conv_shape_ok(n, H, W, cin, cout, dil) || !x || !w || !y) return SFF_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(y) & 7) != 0) return SFF_ERR_INVALID_ARG;
+    const dim3 grid((W + kTilePx - 1) / kTilePx, H, n);
+    hipStream_t st = as_stream(stream);
+    if (cin == 3)
+        hipLaunchKernelGGL((conv_fwd_kernel<3, 32>), grid, dim3(256), 0, st, x, nullptr, w, bias, y,
+                           H, W, dil, relu);
+    else
+        hipLaunchKernelGGL((conv_fwd_kernel<32, 32>), grid, dim3(256), 0, st, x, nullptr, w, bias,
+                           y, H, W, dil, relu);
+    return launch_status();
+}
+
+extern "C" size_t sff_conv3x3_bf16_bwd_workspace_bytes(int32_t n, int32_t H, int32_t W,
+                                                       int32_t cin, int32_t cout) {
+    if (!conv_shape_ok(n, H, W, cin, cout, 1)) return 0;
+    return align256((size_t)cin * 9 * cout * sizeof(uint16_t)) +
+           wgrad_part_bytes(n, H, W, cin, cout);
+}
+
+extern "C" sff_status sff_conv3x3_bf16_dgrad(int32_t n, int32_t H, int32_t W, int32_t cin,
+                                             int32_t cout, int32_t dil, const uint16_t* dy,
+                                             const uint16_t* relu_out, const uint16_t* w,
+                                             uint16_t* dx, void* workspace,
+                                             size_t workspace_bytes, void* stream) {
+    if (!conv_shape_ok(n, H, W, cin, cout, dil) || cin != 32 || !dy || !w || !dx)
+        return SFF_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(dx) & 7) != 0) return SFF_ERR_INVALID_ARG;
+    const size_t need = align256((size_t)cin * 9 * cout * sizeof(uint16_t));
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return SFF_ERR_WORKSPACE;
+    hipStream_t st = as_stream(stream);
+    uint16_t* wt = static_cast<uint16_t*>(workspace);
+    hipLaunchKernelGGL(flip_weights_kernel, dim3((cin * 9 * cout + 255) / 256), dim3(256), 0, st, w,
+                       wt, cin, cout);
+    hipLaunchKernelGGL((conv_fwd_kernel<32, 32>), dim3((W + kTilePx - 1) / kTilePx, H, n), dim3(256),
+                       0, st, dy, relu_out, wt, nullptr, dx, H, W, dil, 0);
+    return launch_status();
+}
+
+extern "C" sff_status sff_conv3x3_bf16_wgrad(int32_t n, int32_t H, int32_t W, int32_t cin,
+                                             int32_t cout, int32_t dil, const uint16_t* x,
+                                             const uint16_t* dy, const uint16_t* relu_out,
+                                             float* dw, float* db, void* workspace,
+                                             size_t workspace_bytes, void* stream) {
+    if (!conv_shape_ok(n, H, W, cin, cout, dil) || !x || !dy || !dw || !db)
+        return SFF_ERR_INVALID_ARG;
+    const size_t off = align256((size_t)cin * 9 * cout * sizeof(uint16_t));
+    const size_t need = off + wgrad_part_bytes(n, H, W, cin, cout);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return SFF_ERR_WORKSPACE;
+    hipStream_t st = as_stream(stream);
+    float* part = reinterpret_cast<float*>(static_cast<uint8_t*>(workspace) + off);
+    const dim3 grid((W + kTilePx - 1) / kTilePx, (H + kWgRows - 1) / kWgRows, n);
+    const int nblk = grid.x * grid.y * grid.z;
+    if (cin == 3)
+        hipLaunchKernelGGL((conv_wgrad_kernel<3, 32>), grid, dim3(256), 0, st, x, dy, relu_out, part,
+                           H, W, dil);
+    else
+        hipLaunchKernelGGL((conv_wgrad_kernel<32, 32>), grid, dim3(256), 0, st, x, dy, relu_out,
+                           part, H, W, dil);
+    const int cpad = (cin + 15) / 16 * 16;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((cout * 9 * cin + cout + 255) / 256), dim3(256), 0,
+                       st, part, dw, db, nblk, cin, cout, cpad);
+    return launch_status();
+}

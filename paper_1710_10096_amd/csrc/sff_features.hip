@@ -127,47 +127,69 @@ __device__ __forceinline__ void wht4(int& x0, int& x1, int& x2, int& x3) {
     x3 = c + d;
 }
 
-// One thread per output pixel (all channels).  Block 64 x 4 pixels.
+// Block = 64 x 4 output pixels of one image.  The source region the tile's
+// patches sample, rows y0 - 3n .. y0 + 3 + 4n and columns x0 - 3n .. x0 + 63 + 4n
+// (replicated border), is staged in LDS with coalesced loads; each thread
+// forms its pixel's bin sums from LDS; the coefficients are staged in LDS
+// again so every wave stores its row of 64 descriptors as one contiguous run.
+constexpr int kTW = 64, kTH = 4;
+
+template <int C>
 __global__ void __launch_bounds__(256) wht_kernel(const uint8_t* __restrict__ S,
-                                                  int16_t* __restrict__ desc, int H, int W, int C,
-                                                  int n) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int m = blockIdx.z;
-    if (x >= W || y >= H) return;
+                                                  int16_t* __restrict__ desc, int H, int W, int n) {
+    extern __shared__ uint8_t smem[];
+    const int RW = kTW + 7 * n, RH = kTH + 7 * n;
+    uint8_t* reg = smem;                                                   // [RH][RW][C]
+    int16_t* out = reinterpret_cast<int16_t*>(smem + ((RH * RW * C + 15) & ~15));  // [kTH][kTW][16C]
+    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH, m = blockIdx.z;
     const uint8_t* src = S + (size_t)m * H * W * C;
-    int rows[8], cols[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        rows[t] = clampi(y + n * (t - 3), 0, H - 1) * W;
-        cols[t] = clampi(x + n * (t - 3), 0, W - 1);
+    const int gx0 = x0 - 3 * n, gy0 = y0 - 3 * n;
+    const int rowb = RW * C;
+    for (int idx = threadIdx.x; idx < RH * rowb; idx += 256) {
+        const int ry = idx / rowb, rr = idx - ry * rowb;
+        const int rx = rr / C, c = rr - rx * C;
+        const int gy = clampi(gy0 + ry, 0, H - 1), gx = clampi(gx0 + rx, 0, W - 1);
+        reg[idx] = src[((size_t)gy * W + gx) * C + c];
     }
-    int16_t* out = desc + (((size_t)m * H + y) * W + x) * C * 16;
+    __syncthreads();
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    int16_t* o = out + (ty * kTW + tx) * 16 * C;
+#pragma unroll
     for (int c = 0; c < C; ++c) {
         int B[4][4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a) {
+            const uint8_t* r0 = reg + ((ty + 2 * a * n) * RW + tx) * C + c;
+            const uint8_t* r1 = r0 + n * RW * C;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int r0 = rows[2 * a], r1 = rows[2 * a + 1];
-                const int c0 = cols[2 * b], c1 = cols[2 * b + 1];
-                B[a][b] = (int)src[(size_t)(r0 + c0) * C + c] + (int)src[(size_t)(r0 + c1) * C + c] +
-                          (int)src[(size_t)(r1 + c0) * C + c] + (int)src[(size_t)(r1 + c1) * C + c];
+                const int c0 = 2 * b * n * C, c1 = c0 + n * C;
+                B[a][b] = (int)r0[c0] + (int)r0[c1] + (int)r1[c0] + (int)r1[c1];
             }
+        }
 #pragma unroll
         for (int a = 0; a < 4; ++a) wht4(B[a][0], B[a][1], B[a][2], B[a][3]);
 #pragma unroll
         for (int b = 0; b < 4; ++b) wht4(B[0][b], B[1][b], B[2][b], B[3][b]);
-        uint32_t w[8];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            w[2 * a] = (uint32_t)(uint16_t)(int16_t)B[a][0] | ((uint32_t)(uint16_t)(int16_t)B[a][1] << 16);
-            w[2 * a + 1] = (uint32_t)(uint16_t)(int16_t)B[a][2] | ((uint32_t)(uint16_t)(int16_t)B[a][3] << 16);
-        }
-        uint4* o = reinterpret_cast<uint4*>(out + c * 16);
-        o[0] = make_uint4(w[0], w[1], w[2], w[3]);
-        o[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) o[c * 16 + a * 4 + b] = (int16_t)B[a][b];
     }
+    __syncthreads();
+    // wave ty stores row y0 + ty: 64 descriptors, 2 C 16-byte chunks each
+    const int y = y0 + ty;
+    if (y >= H) return;
+    const int npx = min(kTW, W - x0);
+    const int chunks = npx * 2 * C;
+    const uint4* srow = reinterpret_cast<const uint4*>(out + ty * kTW * 16 * C);
+    uint4* drow = reinterpret_cast<uint4*>(desc + (((size_t)m * H + y) * W + x0) * 16 * C);
+    for (int k = tx; k < chunks; k += 64) drow[k] = srow[k];
+}
+
+inline size_t wht_smem(int n, int C) {
+    const int RW = kTW + 7 * n, RH = kTH + 7 * n;
+    return ((size_t)(RH * RW * C + 15) & ~(size_t)15) + (size_t)kTH * kTW * 16 * C * sizeof(int16_t);
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -186,6 +208,20 @@ WsLayout ws_layout(const sff_params& p, int nimg, int level) {
     L.s_off = L.h_off + align256((size_t)nimg * g.Hk * p.W * C * sizeof(int16_t));
     L.total = L.s_off + align256((size_t)nimg * p.H * p.W * C);
     return L;
+}
+
+void launch_smooth(const sff_params& p, int nimg, int level, const uint8_t* img, uint8_t* A,
+                   int16_t* h, uint8_t* S, hipStream_t st) {
+    const int H = p.H, W = p.W, C = p.C;
+    const LevelGeom g = level_geom(p, level);
+    LanczosTable T;
+    build_table(g.n, &T);
+    hipLaunchKernelGGL(area_kernel, dim3((g.Wk + 63) / 64, g.Hk, nimg), dim3(64), 0, st, img, A, H, W,
+                       C, g.n, g.Hk, g.Wk);
+    hipLaunchKernelGGL(lanczos_h_kernel, dim3((W * C + 255) / 256, g.Hk, nimg), dim3(256), 0, st, A,
+                       h, W, C, g.n, g.Hk, g.Wk, T);
+    hipLaunchKernelGGL(lanczos_v_kernel, dim3((W * C + 255) / 256, H, nimg), dim3(256), 0, st, h, S,
+                       H, W, C, g.n, g.Hk, T);
 }
 
 }  // namespace
@@ -219,23 +255,41 @@ extern "C" sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_
     hipStream_t st = as_stream(stream);
     const int H = p->H, W = p->W, C = p->C;
     const LevelGeom g = level_geom(*p, level);
+    const size_t smem = wht_smem(g.n, C);
+    if (smem > 65536) return SFF_ERR_UNSUPPORTED;  // levels = 5 with C >= 3
     const uint8_t* src = img;
     if (level > 0) {
         uint8_t* ws = static_cast<uint8_t*>(workspace);
-        uint8_t* A = ws + L.a_off;
-        int16_t* h = reinterpret_cast<int16_t*>(ws + L.h_off);
-        uint8_t* S = ws + L.s_off;
-        LanczosTable T;
-        build_table(g.n, &T);
-        hipLaunchKernelGGL(area_kernel, dim3((g.Wk + 63) / 64, g.Hk, nimg), dim3(64), 0, st, img,
-                           A, H, W, C, g.n, g.Hk, g.Wk);
-        hipLaunchKernelGGL(lanczos_h_kernel, dim3((W * C + 255) / 256, g.Hk, nimg), dim3(256), 0,
-                           st, A, h, W, C, g.n, g.Hk, g.Wk, T);
-        hipLaunchKernelGGL(lanczos_v_kernel, dim3((W * C + 255) / 256, H, nimg), dim3(256), 0, st,
-                           h, S, H, W, C, g.n, g.Hk, T);
-        src = S;
+        launch_smooth(*p, nimg, level, img, ws + L.a_off, reinterpret_cast<int16_t*>(ws + L.h_off),
+                      ws + L.s_off, st);
+        src = ws + L.s_off;
     }
-    hipLaunchKernelGGL(wht_kernel, dim3((W + 63) / 64, (H + 3) / 4, nimg), dim3(64, 4), 0, st, src,
-                       desc, H, W, C, g.n);
+    const dim3 grid((W + kTW - 1) / kTW, (H + kTH - 1) / kTH, nimg);
+    switch (C) {
+        case 1: hipLaunchKernelGGL(wht_kernel<1>, grid, dim3(256), smem, st, src, desc, H, W, g.n); break;
+        case 2: hipLaunchKernelGGL(wht_kernel<2>, grid, dim3(256), smem, st, src, desc, H, W, g.n); break;
+        case 3: hipLaunchKernelGGL(wht_kernel<3>, grid, dim3(256), smem, st, src, desc, H, W, g.n); break;
+        default: hipLaunchKernelGGL(wht_kernel<4>, grid, dim3(256), smem, st, src, desc, H, W, g.n); break;
+    }
+    return launch_status();
+}
+
+extern "C" sff_status sff_smooth_level(const sff_params* p, int32_t nimg, int32_t level,
+                                       const uint8_t* img, uint8_t* out, void* workspace,
+                                       size_t workspace_bytes, void* stream) {
+    if (!params_ok(p) || nimg < 1 || nimg > 65535 || level < 0 || level >= p->levels || !img || !out)
+        return SFF_ERR_INVALID_ARG;
+    const WsLayout L = ws_layout(*p, nimg, level);
+    if (level > 0 && (!workspace || workspace_bytes < L.s_off)) return SFF_ERR_WORKSPACE;
+    hipStream_t st = as_stream(stream);
+    if (level == 0) {
+        if (hipMemcpyAsync(out, img, (size_t)nimg * p->H * p->W * p->C, hipMemcpyDeviceToDevice, st) !=
+            hipSuccess)
+            return SFF_ERR_HIP;
+        return SFF_OK;
+    }
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    launch_smooth(*p, nimg, level, img, ws + L.a_off, reinterpret_cast<int16_t*>(ws + L.h_off), out,
+                  st);
     return launch_status();
 }

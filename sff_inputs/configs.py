@@ -45,6 +45,24 @@ def kitti_batch_specs(n: int = 16, first_seed: int = 100):
             for i in range(n)]
 
 
+def sintel_spec(seed: int) -> SceneSpec:
+    """1024x436 RGB pair shaped like MPI Sintel frames (Section 5 evaluates on
+    Sintel; not available here): motions up to |u| <= 400, |v| <= 100 px with
+    a heavy tail (|u| = 400 r^3), disparities up to 128 px and an occluder."""
+    return SceneSpec(H=436, W=1024, C=3, seed=seed, n_segments=(8, 16), d_range=(0, 128),
+                     flow_max=400, flow_max_v=100, flow_power=3.0, delta_max=4, occluder=True,
+                     occluder_scale=0.8, salt=0.0)
+
+
+def sintel_params() -> dict:
+    return params_dict(436, 1024, 3, levels=3, iters=6, fmax=400, dmax=128, tau=1)
+
+
+def sintel_sequence_specs(n_pairs: int = 49, first_seed: int = 600):
+    """The 49 frame pairs of a 50-frame sequence, one seed each."""
+    return [sintel_spec(first_seed + i) for i in range(n_pairs)]
+
+
 def small_spec(H: int, W: int, C: int, seed: int, flow_max: int = 8,
                d_range=(0, 12), **kw) -> SceneSpec:
     """A small scene for tests whose oracle runs must finish in seconds."""
@@ -53,4 +71,5 @@ def small_spec(H: int, W: int, C: int, seed: int, flow_max: int = 8,
 
 
 __all__ = ["SceneSpec", "make_scene", "params_dict", "tiny_spec", "tiny_params",
-           "kitti_spec", "kitti_params", "kitti_batch_specs", "small_spec"]
+           "kitti_spec", "kitti_params", "kitti_batch_specs", "small_spec", "sintel_spec",
+           "sintel_params", "sintel_sequence_specs"]

@@ -46,6 +46,9 @@ class SceneSpec:
     delta_max: int = 0                # |d1 - d0| <= delta_max per segment
     slope_max: float = 0.02           # planar disparity slope bound (px/px)
     occluder: bool = False            # one compact foreground segment
+    occluder_scale: float = 1.0       # size multiplier of the occluder ellipse
+    flow_max_v: int | None = None     # |v| bound if different from flow_max
+    flow_power: float = 1.0           # |u| = flow_max * r^power, r ~ U(0, 1): > 1 favours small motions
     salt: float = 0.0                 # per-pixel salt probability per image
     sigma: float = 1.5                # Gaussian smoothing of the texture
 
@@ -90,6 +93,13 @@ def smoothed_noise(rng: np.random.Generator, H: int, W: int, C: int,
     return out
 
 
+def _motion(rng, F, Fv, power):
+    if power == 1.0:
+        return int(rng.integers(-F, F + 1)), int(rng.integers(-Fv, Fv + 1))
+    r = rng.uniform(0.0, 1.0, 2) ** power * rng.choice([-1.0, 1.0], 2)
+    return int(np.rint(F * r[0])), int(np.rint(Fv * r[1]))
+
+
 def _segments(rng, spec: SceneSpec):
     H, W = spec.H, spec.W
     nseg = int(rng.integers(spec.n_segments[0], spec.n_segments[1] + 1))
@@ -99,6 +109,7 @@ def _segments(rng, spec: SceneSpec):
     labels = np.argmin(d2, axis=0).astype(np.int32)
     dlo, dhi = spec.d_range
     F = spec.flow_max
+    Fv = spec.flow_max if spec.flow_max_v is None else spec.flow_max_v
     d0 = np.zeros((H, W), np.int64)
     d1 = np.zeros((H, W), np.int64)
     u = np.zeros((H, W), np.int64)
@@ -110,23 +121,22 @@ def _segments(rng, spec: SceneSpec):
         plane = dc + bx * (xx - sites[s, 1]) / 8.0 + by * (yy - sites[s, 0]) / 8.0
         dd = np.clip(np.rint(plane), dlo, dhi).astype(np.int64)
         delta = int(rng.integers(-spec.delta_max, spec.delta_max + 1)) if spec.delta_max else 0
-        us = int(rng.integers(-F, F + 1))
-        vs = int(rng.integers(-F, F + 1))
+        us, vs = _motion(rng, F, Fv, spec.flow_power)
         d0[m] = dd[m]
         d1[m] = np.clip(dd[m] + delta, dlo, dhi)
         u[m] = us
         v[m] = vs
     if spec.occluder:
         cy, cx = rng.uniform(0.25 * H, 0.75 * H), rng.uniform(0.2 * W, 0.8 * W)
-        ry, rx = rng.uniform(0.12, 0.22) * H, rng.uniform(0.06, 0.12) * W
+        ry = rng.uniform(0.12, 0.22) * H * spec.occluder_scale
+        rx = rng.uniform(0.06, 0.12) * W * spec.occluder_scale
         m = ((yy - cy) / ry) ** 2 + ((xx - cx) / rx) ** 2 <= 1.0
         labels = labels.copy()
         labels[m] = nseg
         d0[m] = dhi
         delta = int(rng.integers(-spec.delta_max, 1)) if spec.delta_max else 0
         d1[m] = np.clip(dhi + delta, dlo, dhi)
-        u[m] = int(rng.integers(-F, F + 1))
-        v[m] = int(rng.integers(-F, F + 1))
+        u[m], v[m] = _motion(rng, F, Fv, spec.flow_power)
     return labels, u, v, d0, d1
 
 

@@ -1,0 +1,86 @@
+"""GPU checks of the BF16 MFMA 3x3 convolutions against the FP64 oracle on the
+same BF16-rounded inputs.
+
+Tolerances: outputs and input gradients are FP32 sums of at most 288 products
+rounded once to BF16.  The FP32 sum is within 288 2^-24 (< 2e-5) of the sum of
+the terms' magnitudes S from the exact value, and rounding to BF16 adds at most
+one unit in the last place (at most 2^-7 |y|), so the test allows
+2^-7 |y| + 2e-5 S.  Weight gradients are FP32 sums over every pixel in per-block
+partials; the bound is ~(1024 + number of blocks) 2^-24 times the sum of the
+terms' magnitudes; the test allows 2e-4 of that sum.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import featnet as ofn
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sff():
+    import torch
+    import paper_1710_10096_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def _bf(a):
+    import torch
+    return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).cuda()
+
+
+def _np(t):
+    import torch
+    return t.to(torch.float32).cpu().numpy().astype(np.float64)
+
+
+def _within_bf16_ulp(got, ref, abs_sum):
+    # one BF16 unit in the last place: 2^-7 of the binade [2^e, 2^(e+1)) of the value
+    big = np.maximum(np.abs(got), np.abs(ref))
+    return np.abs(got - ref) <= big * 2.0 ** -7 + 2e-5 * abs_sum + 1e-30
+
+
+CASES = [(1, 9, 70, 3, 1), (2, 17, 131, 32, 1), (1, 23, 64, 32, 2), (1, 30, 97, 32, 4),
+         (1, 5, 6, 32, 16), (1, 1, 1, 3, 1)]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[str(c) for c in CASES])
+def test_conv_forward_and_gradients(sff, case):
+    import torch
+    n, H, W, cin, dil = case
+    rng = np.random.default_rng(H * 1000 + W + cin + dil)
+    x = ofn.bf16_round(rng.standard_normal((n, H, W, cin)))
+    w = ofn.bf16_round(rng.standard_normal((32, 3, 3, cin)) / np.sqrt(9 * cin))
+    b = rng.standard_normal(32).astype(np.float32).astype(np.float64)
+    _say("conv", case)
+    for relu in (False, True):
+        y = sff.sff_conv3x3_bf16_fwd(_bf(x), _bf(w), torch.from_numpy(b.astype(np.float32)).cuda(),
+                                     dil, relu)
+        ref = ofn.bf16_round(ofn.conv3x3(x, w, b, dil, relu))
+        S = ofn.conv3x3(np.abs(x), np.abs(w), np.abs(b), dil)
+        assert _within_bf16_ulp(_np(y), ref, S).all(), relu
+    # gradients with a ReLU mask from a layer output
+    relu_out = ofn.bf16_round(np.maximum(rng.standard_normal((n, H, W, 32)), 0))
+    dy = ofn.bf16_round(rng.standard_normal((n, H, W, 32)))
+    dz = dy * (relu_out > 0)
+    dw, db = sff.sff_conv3x3_bf16_wgrad(_bf(x), _bf(dy), dil, _bf(relu_out))
+    rdw, rdb = ofn.conv3x3_wgrad(x, dz, dil)
+    adw, adb = ofn.conv3x3_wgrad(np.abs(x), np.abs(dz), dil)
+    assert (np.abs(dw.cpu().numpy() - rdw) <= 2e-4 * adw + 1e-6).all()
+    assert (np.abs(db.cpu().numpy() - rdb) <= 2e-4 * adb + 1e-6).all()
+    if cin == 32:
+        dx = sff.sff_conv3x3_bf16_dgrad(_bf(dy), _bf(w), dil, _bf(relu_out))
+        rdx = ofn.bf16_round(ofn.conv3x3_dgrad(dz, w, dil))
+        S = ofn.conv3x3_dgrad(np.abs(dz), np.abs(w), dil)
+        assert _within_bf16_ulp(_np(dx), rdx, S).all()
+        dx2 = sff.sff_conv3x3_bf16_dgrad(_bf(dz), _bf(w), dil, None)
+        assert np.array_equal(_np(dx2), _np(dx))
+    dw2, _ = sff.sff_conv3x3_bf16_wgrad(_bf(x), _bf(dy), dil, _bf(relu_out))
+    assert np.array_equal(dw2.cpu().numpy(), dw.cpu().numpy())  # deterministic

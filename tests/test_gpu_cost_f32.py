@@ -1,0 +1,123 @@
+"""GPU checks of the FP32 window cost (eq. (1) window form) and its backward
+against the FP64 oracle and FP64 central finite differences.
+
+Tolerances (FP32 against FP64): the forward sums 3 x 64 x C non-negative
+terms in three nested partial sums (at most 3C + 16 sequential additions per
+partial), so its relative error stays below ~(3C + 16) 2^-24 < 1e-5 for C = 32;
+the test allows 2e-5.  A gradient entry sums about 192 signed terms (more at
+clamped borders) with fused multiply-adds, so the error is bounded by
+~192 2^-24 times the sum of the terms' magnitudes; the test allows
+1e-4 |g| + 1e-4 mean|g|.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cost_f32 as ocf
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sff():
+    import torch
+    import paper_1710_10096_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _grad_close(g, ref):
+    scale = np.abs(ref).mean()
+    return np.abs(g - ref) <= 1e-4 * np.abs(ref) + 1e-4 * scale
+
+
+def _random_case(seed, B, H, W, C, spread):
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((B, 4, H, W, C)).astype(np.float32)
+    hyp = np.empty((B, H, W, 4), np.int16)
+    hyp[..., :2] = rng.integers(-spread, spread + 1, (B, H, W, 2))
+    hyp[..., 2:] = rng.integers(0, spread + 1, (B, H, W, 2))
+    g = rng.uniform(0.2, 2.0, (B, H, W)).astype(np.float32)
+    return F, hyp, g
+
+
+@pytest.mark.parametrize("s", [1, -1])
+@pytest.mark.parametrize("C", [4, 8])
+def test_small_forward_and_backward_match_fp64(sff, s, C):
+    B, H, W = 2, 19, 27
+    F, hyp, g = _random_case(10 + C + (s > 0), B, H, W, C, spread=9)
+    _say("cost_f32 small", s, C)
+    cost = sff.sff_cost_f32_fwd(_dev(F), _dev(hyp), s).cpu().numpy()
+    grad = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), s, _dev(g)).cpu().numpy()
+    for b in range(B):
+        Fb = [F[b, m].astype(np.float64) for m in range(4)]
+        ref = ocf.window_cost(Fb, hyp[b], s)
+        assert np.allclose(cost[b], ref, rtol=2e-5, atol=0), b
+        G = ocf.window_cost_grad(Fb, hyp[b], s, g[b])
+        for m in range(4):
+            assert _grad_close(grad[b, m], G[m]).all(), (b, m)
+    again = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), s, _dev(g)).cpu().numpy()
+    assert np.array_equal(again, grad)  # deterministic
+
+
+def test_one_pixel_and_one_row_images(sff):
+    for (H, W) in ((1, 1), (1, 9), (7, 1)):
+        F, hyp, g = _random_case(H * 31 + W, 1, H, W, 4, spread=3)
+        cost = sff.sff_cost_f32_fwd(_dev(F), _dev(hyp), 1).cpu().numpy()
+        grad = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), 1, _dev(g)).cpu().numpy()
+        Fb = [F[0, m].astype(np.float64) for m in range(4)]
+        assert np.allclose(cost[0], ocf.window_cost(Fb, hyp[0], 1), rtol=2e-5)
+        G = ocf.window_cost_grad(Fb, hyp[0], 1, g[0])
+        for m in range(4):
+            assert _grad_close(grad[0, m], G[m]).all(), (H, W, m)
+
+
+def test_kitti_size_c32_against_finite_differences(sff):
+    """Feature maps C = 32 ~ N(0, 1) at 1242 x 375 for the four views, vectors
+    fixed to the oracle's forward level-0 field of the KITTI-like pair; loss =
+    sum of per-pixel costs; 1000 random entries against FP64 central
+    differences (eps 1e-3)."""
+    import torch
+    import oracle
+    from sff_inputs import kitti_params, kitti_spec, make_scene
+    sc = make_scene(kitti_spec())
+    p = kitti_params()
+    H, W = p["H"], p["W"]
+    _say("oracle field for the fixed vectors")
+    hyp = oracle.match_pair(sc.stack(), p, 2)["hyp"][0]
+    rng = np.random.default_rng(4)
+    F = rng.standard_normal((1, 4, H, W, 32)).astype(np.float32)
+    feat = _dev(F).requires_grad_(True)
+    hyp_t = _dev(hyp[None])
+    _say("autograd forward/backward")
+    cost = sff.MatchCost.apply(feat, hyp_t, 1)
+    cost.sum().backward()
+    grad = feat.grad.cpu().numpy()[0]
+    cost = cost.detach().cpu().numpy()[0]
+    torch.cuda.synchronize()
+    Fb = [F[0, m].astype(np.float64) for m in range(4)]
+    ones = np.ones((H, W))
+    # forward on 2000 sampled pixels (borders included)
+    ys = np.concatenate([rng.integers(0, H, 1990), [0, H - 1, 0, H - 1, 5]])
+    xs = np.concatenate([rng.integers(0, W, 1990), [0, W - 1, W - 1, 0, 0]])
+    ys, xs = ys[:2000], xs[:2000]
+    ref = ocf.cost_px_at(Fb, hyp, 1, ys, xs)
+    assert np.allclose(cost[ys, xs], ref, rtol=2e-5)
+    _say("1000 finite differences")
+    ent = [(int(rng.integers(4)), int(rng.integers(H)), int(rng.integers(W)), int(rng.integers(32)))
+           for _ in range(1000)]
+    fdh = ocf.FiniteDifferences(Fb, hyp, 1, ones)
+    fd = np.array([fdh.grad_entry(*e, eps=1e-3) for e in ent])
+    got = np.array([grad[m, y, x, c] for (m, y, x, c) in ent])
+    scale = np.abs(fd).mean()
+    assert (np.abs(got - fd) <= 1e-4 * np.abs(fd) + 1e-4 * scale).all()

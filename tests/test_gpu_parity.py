@@ -269,3 +269,30 @@ def test_invalid_batch_raises(sff):
     with pytest.raises(sff.SffError):
         sff.sff_wht_features(p, img, 0, torch.zeros((1, 96, 160, 1, 16), dtype=torch.int16,
                                                    device="cuda"))
+
+
+def test_match_level_one_thread_per_pixel_kernel(sff):
+    """Sixteen 96x160 fields in one launch exceed the candidate-parallel
+    threshold, so this exercises the one-thread-per-pixel half-step kernel on
+    sizes the oracle finishes quickly (both kernels must agree with it)."""
+    B, H, W, C = 16, 96, 160, 1
+    p = params_dict(H, W, C, levels=2, iters=2, fmax=16, dmax=12)
+    scenes = [make_scene(small_spec(H, W, C, 500 + b, flow_max=8, d_range=(0, 10))) for b in range(B)]
+    imgs = _imgs_stack(scenes)
+    seeds = np.arange(B, dtype=np.int64) * 7919 + 3
+    _say("match_level batch 16, one thread per pixel")
+    out = sff.PairMatcher(p, B).run(dev(imgs), dev(seeds))
+    hyp = host(out["hyp"])
+    for b in range(0, B, 3):
+        ref = oracle.match_pair(imgs[b], p, int(seeds[b]))
+        assert np.array_equal(hyp[:, b], ref["hyp"]), b
+
+
+def test_pipeline_kitti_batch16(sff):
+    """Sixteen KITTI-like pairs (per-pair seeds, flow <= 64 for pairs 0-7 and
+    <= 256 for 8-15) in one batch, every pair against the oracle."""
+    from sff_inputs import kitti_batch_specs
+    specs = kitti_batch_specs()
+    scenes = [make_scene(s) for s in specs]
+    _say("pipeline kitti batch 16")
+    _check_pipeline(sff, scenes, kitti_params(), [s.seed for s in specs])
