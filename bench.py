@@ -101,6 +101,41 @@ def copy_probe(nbytes: int = 256 * 1024 * 1024, reps: int = 3):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps, "GBps": 2 * nbytes / dt / 1e9}), flush=True)
 
 
+def probes(reps: int = 5) -> dict:
+    """Achievable bandwidth of a streaming copy (512 MiB) and of random record
+    gathers over a buffer the size of one level's four KITTI-size descriptor
+    maps (179 MB), for 96-byte (RGB descriptor) and 128-byte records."""
+    import torch
+    import paper_1710_10096_amd as sff
+    res = {}
+    n = 512 * 1024 * 1024
+    a = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(3)
+    b = torch.empty_like(a)
+    sff.api.sff_probe_copy(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        sff.api.sff_probe_copy(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    res["copy_GBps"] = 2 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    buf = torch.empty(4 * 1242 * 375 * 96, dtype=torch.uint8, device="cuda").fill_(1)
+    threads, per = 256 * 1024 * 4, 8
+    out = torch.empty(threads, dtype=torch.int32, device="cuda")
+    for rb in (96, 128):
+        sff.api.sff_probe_gather(buf, rb, threads, per, out)
+        torch.cuda.synchronize()
+        e0.record()
+        for r in range(reps):
+            sff.api.sff_probe_gather(buf, rb, threads, per, out, seed=r + 2)
+        e1.record()
+        torch.cuda.synchronize()
+        res[f"gather{rb}_GBps"] = rb * threads * per * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +229,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roof,
     }
+    out["probes"] = probes()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scenes, p, seeds)
     print(json.dumps(out), flush=True)

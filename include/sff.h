@@ -260,6 +260,20 @@ sff_status sff_triplet_loss(int32_t npx, const uint16_t* feat, int32_t ntrip,
 /* out[i] = bf16(grad[i]) (nearest even), then grad[i] = 0, for i < n. */
 sff_status sff_take_grad_bf16(size_t n, float* grad, uint16_t* out, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Calibration kernels for the roofline (no part of the method).
+ * sff_probe_copy: dst[i] = src[i] for `bytes` bytes (multiple of 16, both
+ *   16-byte aligned), streaming 16-byte loads and stores.
+ * sff_probe_gather: `threads` threads (multiple of 256) each read `per_thread`
+ *   records of `record_bytes` bytes (16..256, multiple of 16) at pseudo-random
+ *   record indices of buf [buf_bytes] (16-byte aligned) and write one folded
+ *   word to out[thread] (out holds `threads` uint32).
+ * Errors: SFF_ERR_INVALID_ARG. */
+sff_status sff_probe_copy(const void* src, void* dst, size_t bytes, void* stream);
+sff_status sff_probe_gather(const void* buf, size_t buf_bytes, int32_t record_bytes,
+                            int32_t threads, int32_t per_thread, uint64_t seed, uint32_t* out,
+                            void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,8 @@ EXPORTS = ("sff_status_string", "sff_version", "sff_lanczos_q14", "sff_wht_works
            "sff_consistency", "sff_cost_f32_fwd", "sff_cost_f32_bwd_workspace_bytes",
            "sff_cost_f32_bwd", "sff_conv3x3_bf16_fwd", "sff_conv3x3_bf16_bwd_workspace_bytes",
            "sff_conv3x3_bf16_dgrad", "sff_conv3x3_bf16_wgrad", "sff_smooth_level",
-           "sff_quantise_features", "sff_triplet_loss", "sff_take_grad_bf16")
+           "sff_quantise_features", "sff_triplet_loss", "sff_take_grad_bf16", "sff_probe_copy",
+           "sff_probe_gather")
 
 _lib = None
 
@@ -87,5 +88,9 @@ def lib() -> ctypes.CDLL:
     L.sff_triplet_loss.restype = i32
     L.sff_take_grad_bf16.argtypes = [ctypes.c_size_t, P, P, P]
     L.sff_take_grad_bf16.restype = i32
+    L.sff_probe_copy.argtypes = [P, P, ctypes.c_size_t, P]
+    L.sff_probe_copy.restype = i32
+    L.sff_probe_gather.argtypes = [P, ctypes.c_size_t, i32, i32, i32, ctypes.c_uint64, P, P]
+    L.sff_probe_gather.restype = i32
     _lib = L
     return L

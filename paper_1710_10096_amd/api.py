@@ -321,3 +321,16 @@ def sff_take_grad_bf16(grad: torch.Tensor, out=None, stream=None):
                                     _ptr(out, torch.bfloat16, "out"), _stream(stream)),
            "sff_take_grad_bf16")
     return out
+
+
+def sff_probe_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    nb = src.numel() * src.element_size()
+    _check(lib().sff_probe_copy(_ptr(src), _ptr(dst), nb, _stream(stream)), "sff_probe_copy")
+
+
+def sff_probe_gather(buf: torch.Tensor, record_bytes: int, threads: int, per_thread: int,
+                     out: torch.Tensor, seed: int = 1, stream=None):
+    nb = buf.numel() * buf.element_size()
+    _check(lib().sff_probe_gather(_ptr(buf), nb, record_bytes, threads, per_thread, seed,
+                                  _ptr(out, torch.int32, "out"), _stream(stream)),
+           "sff_probe_gather")

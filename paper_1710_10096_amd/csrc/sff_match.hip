@@ -78,8 +78,10 @@ struct Views {
 };
 
 // Blocks are dealt to the 8 XCDs round-robin (block id mod 8).  Renumber them
-// so that each XCD receives one contiguous run of tiles (a band of rows of one
-// field), which keeps the descriptor rows an XCD gathers in its own L2.
+// so that each XCD receives one contiguous run of tiles; tiles are numbered
+// column-major within a field, so that run is a vertical strip of the image,
+// whose targets (shifted by the locally coherent vectors) stay compact and in
+// that XCD's L2.
 __device__ __forceinline__ int xcd_tile(int bid, int nb) {
     const int xcd = bid & 7, k = bid >> 3;
     const int q = nb >> 3, rem = nb & 7;
@@ -98,7 +100,7 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
     const int per_field = tiles_x * tiles_y;
     const int z = tile / per_field;
     const int tr = tile - z * per_field;
-    const int ty = tr / tiles_x, tx = tr - ty * tiles_x;
+    const int tx = tr / tiles_y, ty = tr - tx * tiles_y;
     const int i = ty * 4 + (threadIdx.x >> 6);
     const int jc = tx * 64 + (threadIdx.x & 63);
     if (i >= a.Hk) return;
@@ -193,170 +195,11 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
     a.cost[field_off + o] = bestc;
 }
 
-// Candidate-parallel form of the same half-step, for levels too small to fill
-// the chip with one thread per pixel: four lanes per pixel.  Lane r scores
-// neighbour r (left, up, right, down), then random-search samples r and r + 4.
-// Each phase ends with a minimum over (cost, candidate index) in the group,
-// which selects exactly what the sequential scan with strict improvement
-// selects: the cheapest candidate, the earliest among equals, and only if it
-// is strictly cheaper than the incumbent.
-__device__ __forceinline__ unsigned long long group_min(unsigned long long k) {
-    const unsigned long long k1 = __shfl_xor(k, 1);
-    k = k1 < k ? k1 : k;
-    const unsigned long long k2 = __shfl_xor(k, 2);
-    return k2 < k ? k2 : k;
-}
-
-template <int C>
-__global__ void __launch_bounds__(256) half_step_par_kernel(MatchArgs a, int it, int colour,
-                                                            int mode, int tiles_x, int tiles_y) {
-    // tile = 1 grid row x 64 pixels of the colour; lanes 4 s .. 4 s + 3 share pixel s
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int per_field = tiles_x * tiles_y;
-    const int z = tile / per_field;
-    const int tr = tile - z * per_field;
-    const int i = tr / tiles_x, tx = tr - i * tiles_x;
-    const int r = threadIdx.x & 3;
-    const int jc = tx * 64 + (threadIdx.x >> 2);
-    if (i >= a.Hk) return;
-    const int j = 2 * jc + ((i + colour) & 1);
-    if (j >= a.Wk) return;  // the whole group of four leaves together
-    const int di = z / a.batch, b = z - di * a.batch;
-    const int s = (a.ndir == 2) ? (di == 0 ? 1 : -1) : a.dir0;
-    const size_t mapsz = (size_t)a.H * a.W * 16 * C;
-    const int16_t* base = a.desc + (size_t)b * 4 * mapsz;
-    Views<C> V;
-    V.T = base + (size_t)(s > 0 ? 1 : 2) * mapsz;
-    V.S = base + (size_t)(s > 0 ? 2 : 1) * mapsz;
-    V.X = base + (size_t)(s > 0 ? 3 : 0) * mapsz;
-    V.H = a.H;
-    V.W = a.W;
-    V.s = s;
-    const int16_t* R = base + (size_t)(s > 0 ? 0 : 3) * mapsz;
-    const int n = a.n;
-    const int x = n * j, y = n * i;
-    const Desc<C> ref = load_desc<C>(R, (size_t)y * a.W + x);
-
-    const size_t field_off = (size_t)z * a.Hk * a.Wk;
-    const uint2* field = reinterpret_cast<const uint2*>(a.hyp) + field_off;
-    const uint2* coarse = mode == 0 ? nullptr
-                                    : reinterpret_cast<const uint2*>(a.hyp_coarse) +
-                                          (size_t)z * a.Hc * a.Wc;
-    const size_t o = (size_t)i * a.Wk + j;
-
-    Hyp best;
-    uint32_t bestc;
-    if (mode == 0) {
-        best = unpack(field[o]);
-        bestc = a.cost[field_off + o];
-    } else {
-        best = unpack(coarse[(size_t)(i >> 1) * a.Wc + (j >> 1)]);
-        bestc = V.cost_below(ref, x, y, best, 0xFFFFFFFFu);
-    }
-    // propagation: lane r scores neighbour r (left, up, right, down)
-    const int ni[4] = {i, i - 1, i, i + 1};
-    const int nj[4] = {j - 1, j, j + 1, j};
-    Hyp nh[4];
-    bool in[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        in[q] = ni[q] >= 0 && ni[q] < a.Hk && nj[q] >= 0 && nj[q] < a.Wk;
-        if (in[q])
-            nh[q] = unpack(mode == 1 ? coarse[(size_t)(ni[q] >> 1) * a.Wc + (nj[q] >> 1)]
-                                     : field[(size_t)ni[q] * a.Wk + nj[q]]);
-    }
-    uint32_t c = 0xFFFFFFFFu;
-    {
-        Hyp h = nh[0];
-        bool live = in[0];
-#pragma unroll
-        for (int q = 1; q < 4; ++q)
-            if (r == q) {
-                h = nh[q];
-                live = in[q];
-            }
-        bool dup = !live || same(h, best);
-#pragma unroll
-        for (int p = 0; p < 3; ++p) dup = dup || (p < r && in[p] && same(h, nh[p]));
-        if (!dup) c = V.cost_below(ref, x, y, h, bestc);
-    }
-    unsigned long long k = group_min(((unsigned long long)c << 8) | (unsigned)r);
-    if ((uint32_t)(k >> 8) < bestc) {
-        bestc = (uint32_t)(k >> 8);
-        best = nh[(int)(k & 0xFF)];
-    }
-    // random search: lane r draws samples r and r + 4 around the propagated vector
-    const Hyp centre = best;
-    const uint32_t prop_c = bestc;
-    const uint64_t seed = a.seeds[b];
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    unsigned long long kbest = ~0ull;
-    Hyp cand[2];
-    uint32_t bound = prop_c;
-#pragma unroll
-    for (int round = 0; round < 2; ++round) {
-        const int t = r + 4 * round;
-        uint32_t cc = 0xFFFFFFFFu;
-        Hyp hc = centre;
-        if (t < a.rs_samples) {
-            const int rad = max(1, a.rs_r0 >> t) * n;
-            U4 ctr;
-            ctr.x = (uint32_t)(i * a.Wk + j);
-            ctr.y = (uint32_t)it;
-            ctr.z = ((uint32_t)a.level << 16) | ((uint32_t)t << 8) | (s < 0 ? 1u : 0u);
-            ctr.w = 0u;
-            const U4 rnd = philox4x32_10(ctr, k0, k1);
-            hc.u = clampi(centre.u + uniform_offset(rnd.x, rad), -a.fmax, a.fmax);
-            hc.v = clampi(centre.v + uniform_offset(rnd.y, rad), -a.fmax, a.fmax);
-            hc.d0 = clampi(centre.d0 + uniform_offset(rnd.z, rad), 0, a.dmax);
-            hc.d1 = clampi(centre.d1 + uniform_offset(rnd.w, rad), 0, a.dmax);
-            if (!same(hc, centre)) cc = V.cost_below(ref, x, y, hc, bound);
-        }
-        cand[round] = hc;
-        const unsigned long long kr = group_min(((unsigned long long)cc << 8) | (unsigned)t);
-        kbest = kr < kbest ? kr : kbest;
-        // later samples only matter if strictly cheaper than everything so far
-        bound = min(bound, (uint32_t)(kbest >> 8));
-    }
-    if ((uint32_t)(kbest >> 8) < prop_c) {
-        const int t = (int)(kbest & 0xFF);
-        const int src = (threadIdx.x & ~3) | (t & 3);
-        const Hyp mine = cand[t >> 2];
-        Hyp w;
-        w.u = __shfl(mine.u, src);
-        w.v = __shfl(mine.v, src);
-        w.d0 = __shfl(mine.d0, src);
-        w.d1 = __shfl(mine.d1, src);
-        best = w;
-        bestc = (uint32_t)(kbest >> 8);
-    }
-    if (r == 0) {
-        reinterpret_cast<uint2*>(a.hyp)[field_off + o] = pack(best);
-        a.cost[field_off + o] = bestc;
-    }
-}
-
-// Levels whose half-steps update fewer pixels than this use the
-// candidate-parallel kernel (four lanes per pixel).
-constexpr long kParallelBelow = 200000;
-
 template <int C>
 sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
     const int nz = a.ndir * a.batch;
     const int tiles_y = (a.Hk + 3) / 4;
     const dim3 block(256);
-    const long half_px = (long)a.Hk * ((a.Wk + 1) / 2) * nz;
-    if (iters > 0 && half_px < kParallelBelow && a.rs_samples <= 8) {
-        const int ptx = ((a.Wk + 1) / 2 + 63) / 64;
-        for (int it = 0; it < iters; ++it)
-            for (int colour = 0; colour < 2; ++colour) {
-                int mode = 0;
-                if (a.hyp_coarse && it == 0) mode = colour == 0 ? 1 : 2;
-                hipLaunchKernelGGL(half_step_par_kernel<C>, dim3(ptx * a.Hk * nz), block, 0, st, a,
-                                   it, colour, mode, ptx, a.Hk);
-            }
-        return launch_status();
-    }
     if (a.hyp_coarse && iters == 0) {
         const int tiles_x = (a.Wk + 63) / 64;
         hipLaunchKernelGGL(half_step_kernel<C>, dim3(tiles_x * tiles_y * nz), block, 0, st, a, 0, 0,

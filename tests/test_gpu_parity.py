@@ -271,10 +271,8 @@ def test_invalid_batch_raises(sff):
                                                    device="cuda"))
 
 
-def test_match_level_one_thread_per_pixel_kernel(sff):
-    """Sixteen 96x160 fields in one launch exceed the candidate-parallel
-    threshold, so this exercises the one-thread-per-pixel half-step kernel on
-    sizes the oracle finishes quickly (both kernels must agree with it)."""
+def test_pipeline_batch16_small(sff):
+    """Sixteen 96x160 pairs with distinct seeds in one batch (two levels)."""
     B, H, W, C = 16, 96, 160, 1
     p = params_dict(H, W, C, levels=2, iters=2, fmax=16, dmax=12)
     scenes = [make_scene(small_spec(H, W, C, 500 + b, flow_max=8, d_range=(0, 10))) for b in range(B)]
