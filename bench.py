@@ -6,7 +6,7 @@ propagation + random search on every level for the forward and inverse
 fields, and the consistency check.  Prints one JSON line.
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload kitti|kitti_batch16|tiny]
-                       [--no-cpu-baseline]
+                       [--no-cpu-baseline] [--no-probes]
 """
 from __future__ import annotations
 
@@ -24,6 +24,41 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# Per-launch HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs, calibrated against a copy of known size.  The file records a
+# hash of the kernel sources it was measured with; any later edit of those
+# sources makes the figure stale and it is reported as null.
+KERNEL_COUNTERS = os.path.join(ROOT, "profiles", "half_step_kernel_kitti_counters.txt")
+KERNEL_SOURCES = ["paper_1710_10096_amd/csrc/sff_match.hip",
+                  "paper_1710_10096_amd/csrc/sff_device.hpp",
+                  "paper_1710_10096_amd/csrc/sff_internal.hpp"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(path: str, kernel: str, workload_name: str):
+    """Bytes per launch from a ``TRAFFIC`` line of the counter summary, or None
+    if there is none for this kernel and workload or the sources changed."""
+    if not os.path.exists(path):
+        return None
+    want = kernel_source_hash()
+    with open(path) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) < 2 or f[0] != "TRAFFIC":
+                continue
+            kv = dict(x.split("=", 1) for x in f[1:] if "=" in x)
+            if (kv.get("kernel") == kernel and kv.get("workload") == workload_name
+                    and kv.get("sources") == want):
+                return float(kv["bytes_per_launch"])
+    return None
 
 
 def workload(name: str):
@@ -86,25 +121,11 @@ def cpu_baseline(scenes, p, seeds) -> dict:
             "cpu": platform.processor() or platform.machine()}
 
 
-def copy_probe(nbytes: int = 256 * 1024 * 1024, reps: int = 3):
-    """A plain device-to-device copy of known size: under rocprofv3 --pmc it
-    calibrates FETCH_SIZE / WRITE_SIZE (counter bytes per byte moved)."""
-    import torch
-    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
-    dst = torch.empty_like(src)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    print(json.dumps({"copy_bytes": nbytes, "reps": reps, "GBps": 2 * nbytes / dt / 1e9}), flush=True)
-
-
 def probes(reps: int = 5) -> dict:
     """Achievable bandwidth of a streaming copy (512 MiB) and of random record
     gathers over a buffer the size of one level's four KITTI-size descriptor
-    maps (179 MB), for 96-byte (RGB descriptor) and 128-byte records."""
+    maps (179 MB), for 96-byte (RGB descriptor) and 128-byte records.  Under
+    rocprofv3 --pmc the copy also calibrates FETCH_SIZE / WRITE_SIZE."""
     import torch
     import paper_1710_10096_amd as sff
     res = {}
@@ -143,12 +164,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="kitti")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="only copy 256 MiB device to device three times (counter calibration)")
+    ap.add_argument("--no-probes", action="store_true",
+                    help="skip the copy / gather bandwidth probes")
     args = ap.parse_args()
-    if args.copy_probe:
-        copy_probe()
-        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         raise SystemExit(2)
@@ -192,28 +210,32 @@ def main():
     ab = algorithmic_bytes(p)
     evals = eval_count(p) * B
 
-    # dominant kernel: the stage with the largest share of the step
-    dom = max(stage_ms, key=stage_ms.get)
-    k_dom = dom.split(":")[-1]
+    # dominant kernel: the propagation / random-search half-step, 2 * iters
+    # launches per level (the hand-off is fused into each level's first launch)
     K = p["levels"]
-    roof = None
-    if dom.startswith("match"):
-        lvl = int(k_dom[1:])
-        Hk, Wk = grid(p, lvl)
-        launches = 2 * p["iters"]
-        per_launch_bytes = 2 * B * Hk * Wk / 2 * (128 * p["C"] + 32)
-        avg_us = stage_ms[dom] * 1e3 / launches
-        ach = per_launch_bytes / (avg_us * 1e-6) / 1e9
-        roof = {"kernel": "half_step_kernel", "level": lvl, "bound": "hbm", "achieved": ach,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": None, "avg_launch_us": avg_us}
-    elif dom.startswith("init"):
-        Ht, Wt = grid(p, K - 1)
-        per_launch_bytes = 2 * B * Ht * Wt * (128 * p["C"] + 12)
-        avg_us = stage_ms[dom] * 1e3
-        ach = per_launch_bytes / (avg_us * 1e-6) / 1e9
-        roof = {"kernel": "init_nn_kernel", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_us}
+    launches = 0
+    hs_bytes = 0.0
+    hs_ms = 0.0
+    levels = {}
+    for k in range(K):
+        Hk, Wk = grid(p, k)
+        n_k = 2 * B * Hk * Wk  # grid pixels of both fields
+        b_k = p["iters"] * n_k * (128 * p["C"] + 32)
+        if k < K - 1:
+            b_k += n_k * (20 + 128 * p["C"])
+        t_k = stage_ms[f"match:L{k}"]
+        levels[f"L{k}"] = {"avg_launch_us": t_k * 1e3 / (2 * p["iters"]),
+                           "GBps": b_k / (t_k * 1e-3) / 1e9}
+        launches += 2 * p["iters"]
+        hs_bytes += b_k
+        hs_ms += t_k
+    avg_us = hs_ms * 1e3 / launches
+    ach = hs_bytes / launches / (avg_us * 1e-6) / 1e9
+    traffic = measured_traffic(KERNEL_COUNTERS, "half_step_kernel", args.workload)
+    roof = {"kernel": "half_step_kernel", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": traffic, "algorithmic_bytes_per_launch": hs_bytes / launches,
+            "launches_per_step": launches, "avg_launch_us": avg_us, "levels": levels}
 
     out = {
         "metric": "matched_px_per_s", "value": npx / (ms * 1e-3), "unit": "px/s",
@@ -229,7 +251,8 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roof,
     }
-    out["probes"] = probes()
+    if not args.no_probes:
+        out["probes"] = probes()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scenes, p, seeds)
     print(json.dumps(out), flush=True)

@@ -19,11 +19,14 @@
  *    caller's next synchronisation.
  *  - The library is stateless and thread-safe.
  *
- * Data layouts (row-major, no padding)
+ * Data layouts (row-major)
  *  - image  uint8  [n][H][W][C]                 C = 1..4 channels
- *  - desc   int16  [n][H][W][C][16]             16 = 4x4 lowest-sequency WHT
+ *  - desc   int16  [n][H][W][Cp][16]            16 = 4x4 lowest-sequency WHT
  *                                                coefficients, index a*4 + b
- *                                                (a vertical, b horizontal)
+ *                                                (a vertical, b horizontal);
+ *    Cp = sff_desc_channels(C) = 1, 2, 4, 4 for C = 1..4: each pixel's record
+ *    is padded to 32, 64 or 128 bytes so that it never straddles a 128-byte
+ *    cache line.  Channels C..Cp-1 are never written nor read by the library.
  *  - the four views of a pair are stored consecutively in the canonical order
  *    (I_l^0, I_l^1, I_r^0, I_r^1); `batch` pairs make n = 4 * batch images.
  *  - hyp    int16  [ndir][batch][Hk][Wk][4]     (u, v, d0, d1), full-res px
@@ -75,6 +78,10 @@ const char* sff_status_string(int32_t status);
 /* Library ABI version (major * 10000 + minor * 100 + patch). */
 int32_t sff_version(void);
 
+/* Channels Cp of a stored descriptor record for C image channels: 1, 2, 4, 4
+ * for C = 1..4; 0 for C outside 1..4. */
+int32_t sff_desc_channels(int32_t C);
+
 /* Host-only helper: the Q14 Lanczos-3 weights the smoothing uses for pyramid
  * factor n (2 <= n <= 16), table[p * 6 + t] for phase p = x mod n and tap t
  * at floor((x + 0.5) / n - 0.5) - 2 + t.  `table` is a HOST array of n * 6
@@ -96,7 +103,7 @@ size_t sff_wht_workspace_bytes(const sff_params* p, int32_t nimg, int32_t level)
  *   the unnormalised 2-D Walsh-Hadamard transform and the 16 coefficients of
  *   vertical/horizontal sequency < 4 are stored (exact in int16).
  * img:  [nimg][H][W][C] uint8, read only.
- * desc: [nimg][H][W][C][16] int16, written.
+ * desc: [nimg][H][W][Cp][16] int16, channels 0..C-1 written.
  * workspace: device buffer of at least sff_wht_workspace_bytes(p, nimg, level)
  *   bytes (may be NULL at level 0); contents on entry are ignored.
  * Errors: SFF_ERR_INVALID_ARG (NULL pointers, nimg < 1, level outside
@@ -116,7 +123,7 @@ size_t sff_init_workspace_bytes(const sff_params* p, int32_t batch);
  *   cross partner:    row y + v*, 0 <= d1 <= dmax, target x + u* - s d1;
  * each the exact argmin of the descriptor SSD with ties to the smallest target
  * index y*W + x.  The combination is the hypothesis; its cost is eq. (1).
- * desc: level-(levels-1) descriptors [batch][4][H][W][C][16].
+ * desc: level-(levels-1) descriptors [batch][4][H][W][Cp][16].
  * dir:  SFF_DIR_FORWARD, SFF_DIR_INVERSE or SFF_DIR_BOTH.
  * hyp/cost: coarsest-level field, written.
  * workspace: device buffer, 256-byte aligned, of at least
@@ -141,7 +148,7 @@ sff_status sff_init_nn(const sff_params* p, int32_t batch, int32_t dir, const in
  *     * n, clamped to |u|,|v| <= fmax, 0 <= d <= dmax; Philox4x32-10 with key
  *     = seeds[b] and counter (i*Wk + j, it, (k << 16) | (t << 8) | (s < 0), 0),
  *     offset = floor(x_c (2 r_t + 1) / 2^32) - r_t; kept on strict improvement.
- * desc:  level-k descriptors [batch][4][H][W][C][16].
+ * desc:  level-k descriptors [batch][4][H][W][Cp][16].
  * seeds: [batch] uint64, device.
  * hyp_coarse: level-(k+1) field [ndir][batch][H(k+1)][W(k+1)][4] or NULL;
  *   must not overlap hyp.
@@ -264,15 +271,17 @@ sff_status sff_take_grad_bf16(size_t n, float* grad, uint16_t* out, void* stream
  * Calibration kernels for the roofline (no part of the method).
  * sff_probe_copy: dst[i] = src[i] for `bytes` bytes (multiple of 16, both
  *   16-byte aligned), streaming 16-byte loads and stores.
- * sff_probe_gather: `threads` threads (multiple of 256) each read `per_thread`
+ * sff_probe_gather: `threads` threads (multiple of 256) each own `per_thread`
  *   records of `record_bytes` bytes (16..256, multiple of 16) at pseudo-random
  *   record indices of buf [buf_bytes] (16-byte aligned) and write one folded
- *   word to out[thread] (out holds `threads` uint32).
+ *   word to out[thread] (out holds `threads` uint32).  coop = 0: each thread
+ *   loads its own records; coop = 1: the records of a 64-lane wave are loaded
+ *   by consecutive lanes, 16 bytes each (same records and bytes).
  * Errors: SFF_ERR_INVALID_ARG. */
 sff_status sff_probe_copy(const void* src, void* dst, size_t bytes, void* stream);
 sff_status sff_probe_gather(const void* buf, size_t buf_bytes, int32_t record_bytes,
-                            int32_t threads, int32_t per_thread, uint64_t seed, uint32_t* out,
-                            void* stream);
+                            int32_t threads, int32_t per_thread, uint64_t seed, int32_t coop,
+                            uint32_t* out, void* stream);
 
 #ifdef __cplusplus
 }

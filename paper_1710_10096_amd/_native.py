@@ -27,7 +27,7 @@ class SffParams(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
-EXPORTS = ("sff_status_string", "sff_version", "sff_lanczos_q14", "sff_wht_workspace_bytes",
+EXPORTS = ("sff_status_string", "sff_version", "sff_desc_channels", "sff_lanczos_q14", "sff_wht_workspace_bytes",
            "sff_wht_features", "sff_init_workspace_bytes", "sff_init_nn", "sff_match_level",
            "sff_consistency", "sff_cost_f32_fwd", "sff_cost_f32_bwd_workspace_bytes",
            "sff_cost_f32_bwd", "sff_conv3x3_bf16_fwd", "sff_conv3x3_bf16_bwd_workspace_bytes",
@@ -52,6 +52,8 @@ def lib() -> ctypes.CDLL:
     L.sff_status_string.restype = ctypes.c_char_p
     L.sff_version.argtypes = []
     L.sff_version.restype = i32
+    L.sff_desc_channels.argtypes = [i32]
+    L.sff_desc_channels.restype = i32
     L.sff_lanczos_q14.argtypes = [i32, P]
     L.sff_lanczos_q14.restype = i32
     L.sff_wht_workspace_bytes.argtypes = [PP, i32, i32]
@@ -90,7 +92,7 @@ def lib() -> ctypes.CDLL:
     L.sff_take_grad_bf16.restype = i32
     L.sff_probe_copy.argtypes = [P, P, ctypes.c_size_t, P]
     L.sff_probe_copy.restype = i32
-    L.sff_probe_gather.argtypes = [P, ctypes.c_size_t, i32, i32, i32, ctypes.c_uint64, P, P]
+    L.sff_probe_gather.argtypes = [P, ctypes.c_size_t, i32, i32, i32, ctypes.c_uint64, i32, P, P]
     L.sff_probe_gather.restype = i32
     _lib = L
     return L

@@ -66,6 +66,20 @@ def sff_lanczos_q14(n: int):
     return [[buf[p * 6 + t] for t in range(6)] for p in range(n)]
 
 
+def desc_channels(C: int) -> int:
+    """Channels of a stored descriptor record (records are padded to 32, 64
+    or 128 bytes): 1, 2, 4, 4 for C = 1..4."""
+    cp = int(lib().sff_desc_channels(int(C)))
+    if cp == 0:
+        raise ValueError(f"C must be 1..4, got {C}")
+    return cp
+
+
+def _check_shape(t: torch.Tensor, shape, name: str):
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
 def sff_wht_workspace_bytes(p, nimg: int, level: int) -> int:
     pp = _params(p)
     return int(lib().sff_wht_workspace_bytes(ctypes.byref(pp), nimg, level))
@@ -73,13 +87,17 @@ def sff_wht_workspace_bytes(p, nimg: int, level: int) -> int:
 
 def sff_wht_features(p, img: torch.Tensor, level: int, desc: torch.Tensor | None = None,
                      workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """img uint8 [n][H][W][C] -> desc int16 [n][H][W][C][16] at ``level``."""
+    """img uint8 [n][H][W][C] -> desc int16 [n][H][W][Cp][16] at ``level``
+    (Cp = desc_channels(C); channels C..Cp-1 are left as they are, zero for a
+    descriptor tensor allocated here)."""
     pp = _params(p)
     nimg = img.shape[0]
     if tuple(img.shape[1:]) != (pp.H, pp.W, pp.C):
         raise ValueError("img shape does not match params")
+    shape = (nimg, pp.H, pp.W, desc_channels(pp.C), 16)
     if desc is None:
-        desc = torch.empty((nimg, pp.H, pp.W, pp.C, 16), dtype=torch.int16, device=img.device)
+        desc = torch.zeros(shape, dtype=torch.int16, device=img.device)
+    _check_shape(desc, shape, "desc")
     need = sff_wht_workspace_bytes(pp, nimg, level)
     if workspace is None and need > 0:
         workspace = torch.empty(need, dtype=torch.uint8, device=img.device)
@@ -96,7 +114,13 @@ def _field(p, batch, ndir, level, device, hyp=None, cost=None):
         hyp = torch.empty((ndir, batch, Hk, Wk, 4), dtype=torch.int16, device=device)
     if cost is None:
         cost = torch.empty((ndir, batch, Hk, Wk), dtype=torch.int32, device=device)
+    _check_shape(hyp, (ndir, batch, Hk, Wk, 4), "hyp")
+    _check_shape(cost, (ndir, batch, Hk, Wk), "cost")
     return hyp, cost
+
+
+def _check_pair_desc(pp, desc: torch.Tensor):
+    _check_shape(desc, (desc.shape[0], 4, pp.H, pp.W, desc_channels(pp.C), 16), "desc")
 
 
 def sff_init_workspace_bytes(p, batch: int) -> int:
@@ -106,8 +130,9 @@ def sff_init_workspace_bytes(p, batch: int) -> int:
 
 def sff_init_nn(p, desc: torch.Tensor, dir: int = DIR_BOTH, hyp=None, cost=None,
                 workspace: torch.Tensor | None = None, stream=None):
-    """desc int16 [batch][4][H][W][C][16] at the coarsest level -> (hyp, cost)."""
+    """desc int16 [batch][4][H][W][Cp][16] at the coarsest level -> (hyp, cost)."""
     pp = _params(p)
+    _check_pair_desc(pp, desc)
     batch = desc.shape[0]
     ndir = 2 if dir == DIR_BOTH else 1
     hyp, cost = _field(pp, batch, ndir, pp.levels - 1, desc.device, hyp, cost)
@@ -125,9 +150,16 @@ def sff_init_nn(p, desc: torch.Tensor, dir: int = DIR_BOTH, hyp=None, cost=None,
 def sff_match_level(p, desc: torch.Tensor, dir: int, level: int, seeds: torch.Tensor,
                     hyp: torch.Tensor | None = None, cost: torch.Tensor | None = None,
                     hyp_coarse: torch.Tensor | None = None, stream=None):
-    """One level of propagation + random search, in place on (hyp, cost)."""
+    """One level of propagation + random search, in place on (hyp, cost);
+    desc int16 [batch][4][H][W][Cp][16] at ``level``."""
     pp = _params(p)
+    _check_pair_desc(pp, desc)
     batch = desc.shape[0]
+    if seeds.numel() != batch:
+        raise ValueError("seeds must hold one value per pair")
+    if hyp_coarse is not None:
+        Hc, Wc = grid_shape(pp, level + 1)
+        _check_shape(hyp_coarse, (2 if dir == DIR_BOTH else 1, batch, Hc, Wc, 4), "hyp_coarse")
     ndir = 2 if dir == DIR_BOTH else 1
     if hyp_coarse is None and (hyp is None or cost is None):
         raise ValueError("without hyp_coarse the starting field (hyp, cost) is required")
@@ -329,8 +361,9 @@ def sff_probe_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
 
 
 def sff_probe_gather(buf: torch.Tensor, record_bytes: int, threads: int, per_thread: int,
-                     out: torch.Tensor, seed: int = 1, stream=None):
+                     out: torch.Tensor, seed: int = 1, coop: bool = False, stream=None):
     nb = buf.numel() * buf.element_size()
     _check(lib().sff_probe_gather(_ptr(buf), nb, record_bytes, threads, per_thread, seed,
+                                  int(bool(coop)),
                                   _ptr(out, torch.int32, "out"), _stream(stream)),
            "sff_probe_gather")

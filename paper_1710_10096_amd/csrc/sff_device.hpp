@@ -9,6 +9,12 @@ namespace sff {
 
 typedef short short2v __attribute__((ext_vector_type(2)));
 
+// Descriptor records are padded to a power-of-two channel count (1, 2, 4, 4
+// for C = 1..4), so a record is 32, 64 or 128 bytes and, in a map aligned to
+// 128 bytes, never straddles a cache line.  The padding is never read.
+template <int C>
+constexpr int kRecC = C == 3 ? 4 : C;
+
 // C channels x 16 coefficients = 8 C packed int16 pairs.
 template <int C>
 struct Desc {
@@ -17,7 +23,7 @@ struct Desc {
 
 template <int C>
 __device__ __forceinline__ Desc<C> load_desc(const int16_t* __restrict__ map, size_t pix) {
-    const uint4* p = reinterpret_cast<const uint4*>(map + pix * (size_t)(16 * C));
+    const uint4* p = reinterpret_cast<const uint4*>(map + pix * (size_t)(16 * kRecC<C>));
     Desc<C> d;
 #pragma unroll
     for (int k = 0; k < 2 * C; ++k) {
@@ -28,6 +34,17 @@ __device__ __forceinline__ Desc<C> load_desc(const int16_t* __restrict__ map, si
         d.w[4 * k + 3] = v.w;
     }
     return d;
+}
+
+// Squared distance of one 16-byte piece (8 coefficients) of two descriptors.
+__device__ __forceinline__ int piece_ssd(uint4 a, uint4 b, int acc) {
+    const uint32_t aw[4] = {a.x, a.y, a.z, a.w}, bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const short2v d = __builtin_bit_cast(short2v, aw[k]) - __builtin_bit_cast(short2v, bw[k]);
+        acc = __builtin_amdgcn_sdot2(d, d, acc, false);
+    }
+    return acc;
 }
 
 // Squared distance of two descriptors.  Coefficients lie in [-16320, 16320],

@@ -14,7 +14,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "sff_internal.hpp"
+#include "sff_device.hpp"
 
 namespace sff {
 namespace {
@@ -177,14 +177,19 @@ __global__ void __launch_bounds__(256) wht_kernel(const uint8_t* __restrict__ S,
             for (int b = 0; b < 4; ++b) o[c * 16 + a * 4 + b] = (int16_t)B[a][b];
     }
     __syncthreads();
-    // wave ty stores row y0 + ty: 64 descriptors, 2 C 16-byte chunks each
+    // wave ty stores row y0 + ty: 64 descriptors, 2 C 16-byte chunks each, at
+    // a record stride of 2 Cp chunks (padding chunks are not written)
     const int y = y0 + ty;
     if (y >= H) return;
+    constexpr int P = 2 * C, RS = 2 * kRecC<C>;
     const int npx = min(kTW, W - x0);
-    const int chunks = npx * 2 * C;
+    const int chunks = npx * P;
     const uint4* srow = reinterpret_cast<const uint4*>(out + ty * kTW * 16 * C);
-    uint4* drow = reinterpret_cast<uint4*>(desc + (((size_t)m * H + y) * W + x0) * 16 * C);
-    for (int k = tx; k < chunks; k += 64) drow[k] = srow[k];
+    uint4* drow = reinterpret_cast<uint4*>(desc) + (((size_t)m * H + y) * W + x0) * RS;
+    for (int k = tx; k < chunks; k += 64) {
+        const int px = k / P;
+        drow[px * RS + (k - px * P)] = srow[k];
+    }
 }
 
 inline size_t wht_smem(int n, int C) {

@@ -19,7 +19,7 @@ namespace sff {
 namespace {
 
 struct InitArgs {
-    const int16_t* desc;  // [batch][4][H][W][C][16]
+    const int16_t* desc;  // [batch][4][H][W][Cp][16], Cp = kRecC<C>
     int16_t* hyp;         // [ndir][batch][Hk][Wk][4]
     uint32_t* cost;       // [ndir][batch][Hk][Wk]
     int H, W, n, Hk, Wk, fm, dm;
@@ -48,8 +48,8 @@ __global__ void __launch_bounds__(256) split_kernel(const int16_t* __restrict__ 
     const int z = blockIdx.y;
     if (p >= Hk * Wk || z >= nz) return;
     const int i = p / Wk, j = p - i * Wk;
-    const size_t mapsz = (size_t)H * W * 16 * C;
-    const int16_t* d = desc + (size_t)z * mapsz + ((size_t)(n * i) * W + n * j) * 16 * C;
+    const size_t mapsz = (size_t)H * W * 16 * kRecC<C>;
+    const int16_t* d = desc + (size_t)z * mapsz + ((size_t)(n * i) * W + n * j) * 16 * kRecC<C>;
     uint32_t hw[kKBytes / 4], lw[kKBytes / 4];
     uint32_t sq = 0;
 #pragma unroll
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
     const bool live = iq < Hk && jqq < Wk;
     const int x = n * min(jqq, Wk - 1), y = n * min(iq, Hk - 1);
     const int W = a.W;
-    const size_t mapsz = (size_t)a.H * W * 16 * C;
+    const size_t mapsz = (size_t)a.H * W * 16 * kRecC<C>;
     const int16_t* base = a.desc + (size_t)b * 4 * mapsz;
     const Desc<C> qd = load_desc<C>(base + (size_t)vR * mapsz, (size_t)y * W + x);
     const int16_t* Sm = base + (size_t)vS * mapsz;

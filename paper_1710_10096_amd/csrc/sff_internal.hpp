@@ -13,6 +13,9 @@ namespace sff {
 constexpr int kMaxLevels = 5;  // pyramid factor n <= 16
 constexpr int kMaxC = 4;
 
+// Channels of a stored descriptor record (power of two >= C).
+inline int rec_channels(int C) { return C == 3 ? 4 : C; }
+
 struct LevelGeom {
     int n, Hk, Wk;
 };

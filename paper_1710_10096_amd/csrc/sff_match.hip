@@ -18,7 +18,7 @@ namespace sff {
 namespace {
 
 struct MatchArgs {
-    const int16_t* desc;        // [batch][4][H][W][C][16]
+    const int16_t* desc;        // [batch][4][H][W][Cp][16], Cp = kRecC<C>
     const uint64_t* seeds;      // [batch]
     const int16_t* hyp_coarse;  // [ndir][batch][Hc][Wc][4] or null
     int16_t* hyp;               // [ndir][batch][Hk][Wk][4]
@@ -52,27 +52,90 @@ __device__ __forceinline__ bool same(const Hyp& a, const Hyp& b) {
     return a.u == b.u && a.v == b.v && a.d0 == b.d0 && a.d1 == b.d1;
 }
 
+// Wave-level ordering of LDS accesses made by different lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Descriptor gathers of one wave, done cooperatively.  Lane l of the wave owns
+// one pixel (its reference descriptor and hypothesis); a descriptor is P = 2C
+// pieces of 16 bytes.  Gathering one descriptor per owner takes P wave-wide
+// loads; in load k lane l fetches piece w = f mod P of owner o = f / P, with
+// f = 64 k + l, so the lanes of one load read consecutive pieces of a few
+// records (each inside one cache line) instead of 64 unrelated lines.  Each
+// lane keeps the reference pieces of its (o, w) slots in registers, forms the
+// piece's partial squared distance, and the P partials of an owner are summed
+// through the wave's LDS slice.
+template <int C>
+struct Coop {
+    static constexpr int P = 2 * C;
+    static constexpr int RS = 2 * kRecC<C>;  // record stride in 16-byte pieces
+    uint4 refp[P];                          // reference piece of slot k
+    uint32_t* part;                         // this wave's LDS slice [64 P]
+    int lane;
+
+    __device__ __forceinline__ static int owner(int k, int lane) { return (64 * k + lane) / P; }
+    __device__ __forceinline__ static int piece(int k, int lane) { return (64 * k + lane) % P; }
+
+    // Load the reference pieces; pix_of(o) is owner o's pixel in map R.
+    template <class F>
+    __device__ __forceinline__ void load_ref(const uint4* __restrict__ R, F pix_of) {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            refp[k] = R[(size_t)pix_of(owner(k, lane)) * RS + piece(k, lane)];
+    }
+
+    // Squared distance between each owner's reference descriptor and the
+    // descriptor of pixel tp in map M (0 for owners passing tp < 0).  Must be
+    // called by all lanes of the wave.
+    __device__ __forceinline__ uint32_t ssd(const uint4* __restrict__ M, int tp) {
+        int t[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) t[k] = __shfl(tp, owner(k, lane));
+        uint4 v[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) v[k] = M[(size_t)max(t[k], 0) * RS + piece(k, lane)];
+#pragma unroll
+        for (int k = 0; k < P; ++k) part[64 * k + lane] = t[k] >= 0 ? (uint32_t)piece_ssd(refp[k], v[k], 0) : 0u;
+        wave_sync();
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < P; ++w) c += part[lane * P + w];
+        wave_sync();
+        return c;
+    }
+};
+
 template <int C>
 struct Views {
-    const int16_t *T, *S, *X;
+    const uint4 *T, *S, *X;
     int H, W, s;
 
     // eq. (1): temporal (x+u, y+v), stereo (x - s d0, y), cross (x+u - s d1, y+v),
     // each target clamped to the image.  The three squared distances are
     // non-negative, so once a partial sum reaches `bound` the candidate cannot
-    // be strictly cheaper than `bound`; the remaining gathers are skipped and a
-    // value >= bound is returned.  Below `bound` the exact cost is returned.
-    __device__ __forceinline__ uint32_t cost_below(const Desc<C>& ref, int x, int y, const Hyp& h,
+    // be strictly cheaper than `bound`; the remaining gathers are skipped for
+    // that lane (and for the wave once no lane needs them) and a value >= bound
+    // is returned.  Below `bound` the exact cost is returned.  `want` = false
+    // lanes take part in the gathers without a candidate; their result is
+    // meaningless.  Must be called by all lanes of the wave.
+    __device__ __forceinline__ uint32_t cost_below(Coop<C>& cp, bool want, int x, int y, const Hyp& h,
                                                    uint32_t bound) const {
         const int ty = clampi(y + h.v, 0, H - 1);
         const int txT = clampi(x + h.u, 0, W - 1);
-        uint32_t c = desc_ssd<C>(ref, load_desc<C>(T, (size_t)ty * W + txT));
-        if (c >= bound) return c;
-        const int txS = clampi(x - s * h.d0, 0, W - 1);
-        c += desc_ssd<C>(ref, load_desc<C>(S, (size_t)y * W + txS));
-        if (c >= bound) return c;
-        const int txX = clampi(x + h.u - s * h.d1, 0, W - 1);
-        c += desc_ssd<C>(ref, load_desc<C>(X, (size_t)ty * W + txX));
+        uint32_t c = cp.ssd(T, want ? ty * W + txT : -1);
+        bool alive = want && c < bound;
+        if (__any(alive)) {
+            const int txS = clampi(x - s * h.d0, 0, W - 1);
+            c += cp.ssd(S, alive ? y * W + txS : -1);
+            alive = alive && c < bound;
+            if (__any(alive)) {
+                const int txX = clampi(x + h.u - s * h.d1, 0, W - 1);
+                c += cp.ssd(X, alive ? ty * W + txX : -1);
+            }
+        }
         return c;
     }
 };
@@ -92,24 +155,30 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // and neighbours from the coarse field); 2 = iteration-0 black half after a
 // hand-off (own from the coarse field, neighbours already at this level);
 // 3 = hand-off only (no propagation or search), used when iters == 0.
+//
+// Block = 4 waves, one grid row each, 64 pixels of the half-step's colour per
+// wave (all pixels for mode 3).  Lanes past the row's end stay in the wave for
+// the cooperative gathers without a pixel of their own.
 template <int C>
 __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int colour, int mode,
                                                         int tiles_x, int tiles_y) {
-    // tile = 4 grid rows x 64 pixels of the half-step's colour (all pixels for mode 3)
+    __shared__ uint32_t part_lds[4][64 * Coop<C>::P];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int per_field = tiles_x * tiles_y;
     const int z = tile / per_field;
     const int tr = tile - z * per_field;
     const int tx = tr / tiles_y, ty = tr - tx * tiles_y;
-    const int i = ty * 4 + (threadIdx.x >> 6);
-    const int jc = tx * 64 + (threadIdx.x & 63);
-    if (i >= a.Hk) return;
-    const int j = mode == 3 ? jc : 2 * jc + ((i + colour) & 1);
-    if (j >= a.Wk) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = ty * 4 + wv;
+    if (i >= a.Hk) return;  // whole wave
+    const int par = mode == 3 ? 0 : ((i + colour) & 1);
+    const int step = mode == 3 ? 1 : 2;
+    const int j = step * (tx * 64 + lane) + par;
+    const bool act = j < a.Wk;
     const int di = z / a.batch, b = z - di * a.batch;
     const int s = (a.ndir == 2) ? (di == 0 ? 1 : -1) : a.dir0;
-    const size_t mapsz = (size_t)a.H * a.W * 16 * C;
-    const int16_t* base = a.desc + (size_t)b * 4 * mapsz;
+    const size_t mapsz = (size_t)a.H * a.W * Coop<C>::RS;  // in 16-byte pieces
+    const uint4* base = reinterpret_cast<const uint4*>(a.desc) + (size_t)b * 4 * mapsz;
     Views<C> V;
     V.T = base + (size_t)(s > 0 ? 1 : 2) * mapsz;
     V.S = base + (size_t)(s > 0 ? 2 : 1) * mapsz;
@@ -117,17 +186,24 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
     V.H = a.H;
     V.W = a.W;
     V.s = s;
-    const int16_t* R = base + (size_t)(s > 0 ? 0 : 3) * mapsz;
+    const uint4* R = base + (size_t)(s > 0 ? 0 : 3) * mapsz;
     const int n = a.n;
-    const int x = n * j, y = n * i;
-    const Desc<C> ref = load_desc<C>(R, (size_t)y * a.W + x);
+    const int x = n * min(j, a.Wk - 1), y = n * i;
+    Coop<C> cp;
+    cp.lane = lane;
+    cp.part = part_lds[wv];
+    {
+        const int j0 = step * tx * 64 + par, W = a.W, Wk1 = a.Wk - 1;
+        cp.load_ref(R, [=](int o) { return y * W + n * min(j0 + step * o, Wk1); });
+    }
 
     const size_t field_off = (size_t)z * a.Hk * a.Wk;
     const uint2* field = reinterpret_cast<const uint2*>(a.hyp) + field_off;
     const uint2* coarse = mode == 0 ? nullptr
                                     : reinterpret_cast<const uint2*>(a.hyp_coarse) +
                                           (size_t)z * a.Hc * a.Wc;
-    const size_t o = (size_t)i * a.Wk + j;
+    const int jj = min(j, a.Wk - 1);
+    const size_t o = (size_t)i * a.Wk + jj;
 
     Hyp best;
     uint32_t bestc;
@@ -135,35 +211,37 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
         best = unpack(field[o]);
         bestc = a.cost[field_off + o];
     } else {
-        best = unpack(coarse[(size_t)(i >> 1) * a.Wc + (j >> 1)]);
-        bestc = V.cost_below(ref, x, y, best, 0xFFFFFFFFu);
+        best = unpack(coarse[(size_t)(i >> 1) * a.Wc + (jj >> 1)]);
+        bestc = V.cost_below(cp, act, x, y, best, 0xFFFFFFFFu);
     }
     if (mode != 3) {
         // propagation: left, up, right, down.  A vector equal to one already
         // scored has the same cost and cannot be a strict improvement.
         const int ni[4] = {i, i - 1, i, i + 1};
-        const int nj[4] = {j - 1, j, j + 1, j};
-        Hyp nh[4];
+        const int nj[4] = {jj - 1, jj, jj + 1, jj};
+        uint2 nh[4];
         bool in[4];
+        const uint2 own = pack(best);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            in[q] = ni[q] >= 0 && ni[q] < a.Hk && nj[q] >= 0 && nj[q] < a.Wk;
+            in[q] = act && ni[q] >= 0 && ni[q] < a.Hk && nj[q] >= 0 && nj[q] < a.Wk;
+            nh[q] = own;
             if (in[q])
-                nh[q] = unpack(mode == 1 ? coarse[(size_t)(ni[q] >> 1) * a.Wc + (nj[q] >> 1)]
-                                         : field[(size_t)ni[q] * a.Wk + nj[q]]);
+                nh[q] = mode == 1 ? coarse[(size_t)(ni[q] >> 1) * a.Wc + (nj[q] >> 1)]
+                                  : field[(size_t)ni[q] * a.Wk + nj[q]];
         }
-        const Hyp own = best;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (!in[q]) continue;
-            bool dup = same(nh[q], own);
+            bool dup = nh[q].x == own.x && nh[q].y == own.y;
 #pragma unroll
-            for (int p = 0; p < q; ++p) dup = dup || (in[p] && same(nh[q], nh[p]));
-            if (dup) continue;
-            const uint32_t c = V.cost_below(ref, x, y, nh[q], bestc);
-            if (c < bestc) {
+            for (int p = 0; p < q; ++p) dup = dup || (in[p] && nh[q].x == nh[p].x && nh[q].y == nh[p].y);
+            const bool want = in[q] && !dup;
+            if (!__any(want)) continue;
+            const Hyp h = unpack(nh[q]);
+            const uint32_t c = V.cost_below(cp, want, x, y, h, bestc);
+            if (want && c < bestc) {
                 bestc = c;
-                best = nh[q];
+                best = h;
             }
         }
         // random search around the propagated vector
@@ -173,7 +251,7 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
         for (int t = 0; t < a.rs_samples; ++t) {
             const int r = max(1, a.rs_r0 >> t) * n;
             U4 ctr;
-            ctr.x = (uint32_t)(i * a.Wk + j);
+            ctr.x = (uint32_t)(i * a.Wk + jj);
             ctr.y = (uint32_t)it;
             ctr.z = ((uint32_t)a.level << 16) | ((uint32_t)t << 8) | (s < 0 ? 1u : 0u);
             ctr.w = 0u;
@@ -183,16 +261,19 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
             c.v = clampi(centre.v + uniform_offset(rnd.y, r), -a.fmax, a.fmax);
             c.d0 = clampi(centre.d0 + uniform_offset(rnd.z, r), 0, a.dmax);
             c.d1 = clampi(centre.d1 + uniform_offset(rnd.w, r), 0, a.dmax);
-            if (same(c, centre)) continue;
-            const uint32_t cc = V.cost_below(ref, x, y, c, bestc);
-            if (cc < bestc) {
+            const bool want = act && !same(c, centre);
+            if (!__any(want)) continue;
+            const uint32_t cc = V.cost_below(cp, want, x, y, c, bestc);
+            if (want && cc < bestc) {
                 bestc = cc;
                 best = c;
             }
         }
     }
-    reinterpret_cast<uint2*>(a.hyp)[field_off + o] = pack(best);
-    a.cost[field_off + o] = bestc;
+    if (act) {
+        reinterpret_cast<uint2*>(a.hyp)[field_off + o] = pack(best);
+        a.cost[field_off + o] = bestc;
+    }
 }
 
 template <int C>

@@ -20,18 +20,30 @@ __global__ void __launch_bounds__(256) copy_kernel(const uint4* __restrict__ src
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
-// Each thread gathers `per_thread` records of `rec16` 16-byte words at
+// Each thread owns `per_thread` records of `rec16` 16-byte words at
 // pseudo-random record indices in [0, nrec) and folds them into one word.
+// coop = 0: a thread loads its own records, one 16-byte word per instruction,
+// so one wave-wide load touches 64 unrelated cache lines.  coop = 1: the 64
+// records of a wave are loaded word by word by consecutive lanes (lane l of
+// load k takes word (64 k + l) mod rec16 of record (64 k + l) / rec16), so one
+// load touches the few lines of 64 / rec16 records.  Same records, same bytes.
 __global__ void __launch_bounds__(256) gather_kernel(const uint4* __restrict__ buf, size_t nrec,
                                                      int rec16, int per_thread, uint64_t seed,
-                                                     uint32_t* __restrict__ out) {
+                                                     int coop, uint32_t* __restrict__ out) {
     const size_t tid = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     uint32_t acc = 0;
     for (int g = 0; g < per_thread; ++g) {
-        const size_t r = (size_t)mix(seed ^ (tid * 0x100000001B3ull + g)) % nrec;
-        const uint4* p = buf + r * rec16;
         for (int k = 0; k < rec16; ++k) {
-            const uint4 v = p[k];
+            size_t owner = tid;
+            int word = k;
+            if (coop) {
+                const int flat = k * 64 + lane;
+                owner = tid - lane + flat / rec16;
+                word = flat % rec16;
+            }
+            const size_t r = (size_t)mix(seed ^ (owner * 0x100000001B3ull + g)) % nrec;
+            const uint4 v = buf[r * rec16 + word];
             acc ^= v.x + v.y + v.z + v.w;
         }
     }
@@ -56,13 +68,13 @@ extern "C" sff_status sff_probe_copy(const void* src, void* dst, size_t bytes, v
 
 extern "C" sff_status sff_probe_gather(const void* buf, size_t buf_bytes, int32_t record_bytes,
                                        int32_t threads, int32_t per_thread, uint64_t seed,
-                                       uint32_t* out, void* stream) {
+                                       int32_t coop, uint32_t* out, void* stream) {
     if (!buf || !out || record_bytes < 16 || record_bytes > 256 || (record_bytes & 15) != 0 ||
-        buf_bytes < (size_t)record_bytes || threads < 256 || (threads & 255) != 0 || per_thread < 1 ||
+        buf_bytes < (size_t)record_bytes || threads < 256 || (threads & 255) != 0 || per_thread < 1 || (coop != 0 && coop != 1) ||
         (reinterpret_cast<uintptr_t>(buf) & 15) != 0)
         return SFF_ERR_INVALID_ARG;
     const size_t nrec = buf_bytes / (size_t)record_bytes;
     hipLaunchKernelGGL(gather_kernel, dim3(threads / 256), dim3(256), 0, as_stream(stream),
-                       static_cast<const uint4*>(buf), nrec, record_bytes / 16, per_thread, seed, out);
+                       static_cast<const uint4*>(buf), nrec, record_bytes / 16, per_thread, seed, coop, out);
     return launch_status();
 }

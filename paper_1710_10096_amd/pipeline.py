@@ -21,7 +21,8 @@ class PairMatcher:
         self.batch = int(batch)
         p, B = self.p, self.batch
         dev = torch.device(device)
-        self.desc = torch.empty((B, 4, p.H, p.W, p.C, 16), dtype=torch.int16, device=dev)
+        self.desc = torch.zeros((B, 4, p.H, p.W, api.desc_channels(p.C), 16), dtype=torch.int16,
+                                device=dev)
         ws = max(api.sff_wht_workspace_bytes(p, 4 * B, k) for k in range(p.levels))
         ws = max(ws, api.sff_init_workspace_bytes(p, B))
         self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
@@ -42,7 +43,7 @@ class PairMatcher:
         if tuple(imgs.shape) != (B, 4, p.H, p.W, p.C):
             raise ValueError(f"imgs must be [{B}, 4, {p.H}, {p.W}, {p.C}]")
         flat_img = imgs.view(4 * B, p.H, p.W, p.C)
-        flat_desc = self.desc.view(4 * B, p.H, p.W, p.C, 16)
+        flat_desc = self.desc.view(4 * B, p.H, p.W, self.desc.shape[4], 16)
         top = p.levels - 1
         mk("start")
         for k in range(top, -1, -1):

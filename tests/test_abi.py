@@ -60,7 +60,13 @@ def test_status_strings_and_version():
     assert L.sff_status_string(0) == b"ok"
     assert L.sff_status_string(1) == b"invalid argument"
     assert L.sff_status_string(99) == b"unknown status"
-    assert L.sff_version() >= 100
+    assert L.sff_version() >= 200
+
+
+def test_descriptor_record_channels():
+    """Records are padded to a power-of-two channel count (32/64/128 bytes)."""
+    L = _native.lib()
+    assert [L.sff_desc_channels(c) for c in range(6)] == [0, 1, 2, 4, 4, 0]
 
 
 def _good():

@@ -63,11 +63,15 @@ def test_wht_features_parity(sff, case):
     rng = np.random.default_rng(abs(hash(name)) % 2 ** 32)
     imgs = rng.integers(0, 256, (4, H, W, C), dtype=np.uint8)
     p = params_dict(H, W, C, levels=levels, iters=1)
+    Cp = sff.desc_channels(C)
     for lv in lvls:
         _say("features", name, "level", lv)
-        d = host(sff.sff_wht_features(p, dev(imgs), lv))
+        # padding channels of a record are never written: pre-fill a sentinel
+        out = dev(np.full((4, H, W, Cp, 16), 0x5A5A, np.int16))
+        d = host(sff.sff_wht_features(p, dev(imgs), lv, out))
         for m in range(4):
-            assert np.array_equal(d[m], oracle.features(imgs[m], lv)), (name, lv, m)
+            assert np.array_equal(d[m][:, :, :C], oracle.features(imgs[m], lv)), (name, lv, m)
+        assert (d[:, :, :, C:] == 0x5A5A).all()
 
 
 def test_wht_features_kitti_full(sff):
@@ -79,7 +83,7 @@ def test_wht_features_kitti_full(sff):
         _say("features kitti level", lv)
         d = host(sff.sff_wht_features(p, g, lv))
         for m in range(4):
-            assert np.array_equal(d[m], oracle.features(imgs[m], lv)), (lv, m)
+            assert np.array_equal(d[m][:, :, :p["C"]], oracle.features(imgs[m], lv)), (lv, m)
 
 
 # ----------------------------------------------------------------- init ----
@@ -100,7 +104,7 @@ def test_init_nn_parity(sff, case):
     p = params_dict(H, W, C, levels=levels, iters=1, fmax=fmax, dmax=dmax)
     top = levels - 1
     imgs = sc.stack()
-    desc = sff.sff_wht_features(p, dev(imgs), top).view(1, 4, H, W, C, 16)
+    desc = sff.sff_wht_features(p, dev(imgs), top).view(1, 4, H, W, sff.desc_channels(C), 16)
     D = _oracle_descs(imgs, top)
     _say("init", name, "both directions")
     hyp, cost = sff.sff_init_nn(p, desc, sff.DIR_BOTH)
@@ -121,7 +125,8 @@ def test_init_nn_kitti_full(sff):
     p = kitti_params()
     imgs = sc.stack()
     top = p["levels"] - 1
-    desc = sff.sff_wht_features(p, dev(imgs), top).view(1, 4, p["H"], p["W"], p["C"], 16)
+    desc = sff.sff_wht_features(p, dev(imgs), top).view(1, 4, p["H"], p["W"],
+                                                        sff.desc_channels(p["C"]), 16)
     _say("init kitti")
     hyp, cost = sff.sff_init_nn(p, desc, sff.DIR_BOTH)
     D = _oracle_descs(imgs, top)
@@ -141,6 +146,8 @@ LEVEL_CASES = [
     ("handoff_only", 38, 61, 1, 2, 0, 0, 6, 1),
     ("no_search", 30, 50, 1, 1, 0, 3, 0, 3),
     ("odd_sizes", 17, 9, 2, 2, 1, 5, 6, 1),
+    ("c4_handoff", 29, 53, 4, 2, 0, 2, 6, 1),
+    ("wide_c3", 11, 300, 3, 1, 0, 2, 6, 1),
 ]
 
 
@@ -155,7 +162,7 @@ def test_match_level_parity(sff, case):
     imgs = _imgs_stack(scenes)
     seeds = np.array([11 + 1000003 * b for b in range(B)], np.int64)
     flat = dev(imgs.reshape(4 * B, H, W, C))
-    desc_l = sff.sff_wht_features(p, flat, level).view(B, 4, H, W, C, 16)
+    desc_l = sff.sff_wht_features(p, flat, level).view(B, 4, H, W, sff.desc_channels(C), 16)
     Dl = [_oracle_descs(imgs[b], level) for b in range(B)]
     if level < levels - 1:
         # a coarse field: oracle init at the next level (both sides get the same input)
@@ -267,7 +274,7 @@ def test_invalid_batch_raises(sff):
     p = tiny_params()
     img = torch.zeros((0, 96, 160, 1), dtype=torch.uint8, device="cuda")
     with pytest.raises(sff.SffError):
-        sff.sff_wht_features(p, img, 0, torch.zeros((1, 96, 160, 1, 16), dtype=torch.int16,
+        sff.sff_wht_features(p, img, 0, torch.zeros((0, 96, 160, 1, 16), dtype=torch.int16,
                                                    device="cuda"))
 
 
