@@ -153,6 +153,9 @@ sff_status sff_init_nn(const sff_params* p, int32_t batch, int32_t dir, const in
  * hyp_coarse: level-(k+1) field [ndir][batch][H(k+1)][W(k+1)][4] or NULL;
  *   must not overlap hyp.
  * hyp/cost: level-k field, read and written in place.
+ * Two kernels with identical results gather the descriptors: one lane per
+ *   pixel for small levels, wave-cooperative loads otherwise; the environment
+ *   variable SFF_MATCH_EVAL=lane|coop forces one (testing and timing).
  * Errors: SFF_ERR_INVALID_ARG (also for level >= levels - 1 with a non-NULL
  *   hyp_coarse, and for overlapping hyp/hyp_coarse). */
 sff_status sff_match_level(const sff_params* p, int32_t batch, int32_t dir, int32_t level,

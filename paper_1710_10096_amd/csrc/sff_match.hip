@@ -12,6 +12,9 @@
 // The hand-off from the coarser level is fused into iteration 0: a pixel whose
 // level-k vector has not been written yet reads its parent's vector from the
 // coarse field and computes its cost at this level.
+#include <cstdlib>
+#include <cstring>
+
 #include "sff_device.hpp"
 
 namespace sff {
@@ -108,21 +111,62 @@ struct Coop {
     }
 };
 
+// eq. (1): temporal (x+u, y+v), stereo (x - s d0, y), cross (x+u - s d1, y+v),
+// each target clamped to the image.  The three squared distances are
+// non-negative, so once a partial sum reaches `bound` the candidate cannot be
+// strictly cheaper than `bound`: the remaining gathers are skipped and a value
+// >= bound is returned.  Below `bound` the exact cost is returned.  Lanes with
+// want = false have no candidate; their result is meaningless.
+//
+// Two evaluators with the same results: LaneEval gathers each lane's records
+// itself (fewest instructions and round trips; best when a launch has too few
+// waves to fill the chip), CoopEval gathers cooperatively (fewest cache-line
+// lookups; best when the chip is full).  CoopEval must be called by all lanes
+// of the wave.
 template <int C>
-struct Views {
+struct LaneEval {
+    static constexpr int kLdsWords = 1;
     const uint4 *T, *S, *X;
     int H, W, s;
+    Desc<C> ref;
 
-    // eq. (1): temporal (x+u, y+v), stereo (x - s d0, y), cross (x+u - s d1, y+v),
-    // each target clamped to the image.  The three squared distances are
-    // non-negative, so once a partial sum reaches `bound` the candidate cannot
-    // be strictly cheaper than `bound`; the remaining gathers are skipped for
-    // that lane (and for the wave once no lane needs them) and a value >= bound
-    // is returned.  Below `bound` the exact cost is returned.  `want` = false
-    // lanes take part in the gathers without a candidate; their result is
-    // meaningless.  Must be called by all lanes of the wave.
-    __device__ __forceinline__ uint32_t cost_below(Coop<C>& cp, bool want, int x, int y, const Hyp& h,
-                                                   uint32_t bound) const {
+    template <class F>
+    __device__ __forceinline__ void init(const uint4* R, int x, int y, int, uint32_t*, F) {
+        ref = load_desc<C>(reinterpret_cast<const int16_t*>(R), (size_t)y * W + x);
+    }
+
+    __device__ __forceinline__ uint32_t map_ssd(const uint4* M, int pix) const {
+        return desc_ssd<C>(ref, load_desc<C>(reinterpret_cast<const int16_t*>(M), (size_t)pix));
+    }
+
+    __device__ __forceinline__ uint32_t cost_below(bool want, int x, int y, const Hyp& h,
+                                                   uint32_t bound) {
+        if (!want) return 0xFFFFFFFFu;
+        const int ty = clampi(y + h.v, 0, H - 1);
+        uint32_t c = map_ssd(T, ty * W + clampi(x + h.u, 0, W - 1));
+        if (c >= bound) return c;
+        c += map_ssd(S, y * W + clampi(x - s * h.d0, 0, W - 1));
+        if (c >= bound) return c;
+        return c + map_ssd(X, ty * W + clampi(x + h.u - s * h.d1, 0, W - 1));
+    }
+};
+
+template <int C>
+struct CoopEval {
+    static constexpr int kLdsWords = 64 * Coop<C>::P;
+    const uint4 *T, *S, *X;
+    int H, W, s;
+    Coop<C> cp;
+
+    template <class F>
+    __device__ __forceinline__ void init(const uint4* R, int, int, int lane, uint32_t* part, F pix_of) {
+        cp.lane = lane;
+        cp.part = part;
+        cp.load_ref(R, pix_of);
+    }
+
+    __device__ __forceinline__ uint32_t cost_below(bool want, int x, int y, const Hyp& h,
+                                                   uint32_t bound) {
         const int ty = clampi(y + h.v, 0, H - 1);
         const int txT = clampi(x + h.u, 0, W - 1);
         uint32_t c = cp.ssd(T, want ? ty * W + txT : -1);
@@ -157,12 +201,12 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // 3 = hand-off only (no propagation or search), used when iters == 0.
 //
 // Block = 4 waves, one grid row each, 64 pixels of the half-step's colour per
-// wave (all pixels for mode 3).  Lanes past the row's end stay in the wave for
-// the cooperative gathers without a pixel of their own.
-template <int C>
+// wave (all pixels for mode 3).  Lanes past the row's end stay in the wave
+// (for the cooperative gathers) without a pixel of their own.
+template <int C, class E>
 __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int colour, int mode,
                                                         int tiles_x, int tiles_y) {
-    __shared__ uint32_t part_lds[4][64 * Coop<C>::P];
+    __shared__ uint32_t part_lds[4][E::kLdsWords];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int per_field = tiles_x * tiles_y;
     const int z = tile / per_field;
@@ -179,7 +223,7 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
     const int s = (a.ndir == 2) ? (di == 0 ? 1 : -1) : a.dir0;
     const size_t mapsz = (size_t)a.H * a.W * Coop<C>::RS;  // in 16-byte pieces
     const uint4* base = reinterpret_cast<const uint4*>(a.desc) + (size_t)b * 4 * mapsz;
-    Views<C> V;
+    E V;
     V.T = base + (size_t)(s > 0 ? 1 : 2) * mapsz;
     V.S = base + (size_t)(s > 0 ? 2 : 1) * mapsz;
     V.X = base + (size_t)(s > 0 ? 3 : 0) * mapsz;
@@ -189,12 +233,9 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
     const uint4* R = base + (size_t)(s > 0 ? 0 : 3) * mapsz;
     const int n = a.n;
     const int x = n * min(j, a.Wk - 1), y = n * i;
-    Coop<C> cp;
-    cp.lane = lane;
-    cp.part = part_lds[wv];
     {
         const int j0 = step * tx * 64 + par, W = a.W, Wk1 = a.Wk - 1;
-        cp.load_ref(R, [=](int o) { return y * W + n * min(j0 + step * o, Wk1); });
+        V.init(R, x, y, lane, part_lds[wv], [=](int o) { return y * W + n * min(j0 + step * o, Wk1); });
     }
 
     const size_t field_off = (size_t)z * a.Hk * a.Wk;
@@ -212,7 +253,7 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
         bestc = a.cost[field_off + o];
     } else {
         best = unpack(coarse[(size_t)(i >> 1) * a.Wc + (jj >> 1)]);
-        bestc = V.cost_below(cp, act, x, y, best, 0xFFFFFFFFu);
+        bestc = V.cost_below(act, x, y, best, 0xFFFFFFFFu);
     }
     if (mode != 3) {
         // propagation: left, up, right, down.  A vector equal to one already
@@ -238,7 +279,7 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
             const bool want = in[q] && !dup;
             if (!__any(want)) continue;
             const Hyp h = unpack(nh[q]);
-            const uint32_t c = V.cost_below(cp, want, x, y, h, bestc);
+            const uint32_t c = V.cost_below(want, x, y, h, bestc);
             if (want && c < bestc) {
                 bestc = c;
                 best = h;
@@ -263,7 +304,7 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
             c.d1 = clampi(centre.d1 + uniform_offset(rnd.w, r), 0, a.dmax);
             const bool want = act && !same(c, centre);
             if (!__any(want)) continue;
-            const uint32_t cc = V.cost_below(cp, want, x, y, c, bestc);
+            const uint32_t cc = V.cost_below(want, x, y, c, bestc);
             if (want && cc < bestc) {
                 bestc = cc;
                 best = c;
@@ -276,15 +317,20 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
     }
 }
 
-template <int C>
-sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
+// Below this many pixel updates per launch (about one wave per SIMD) the chip
+// is not full and each wave's chain of dependent gathers sets the time; the
+// per-lane evaluator has the shorter chain there.
+constexpr long kCoopMinUpdates = 65536;
+
+template <int C, class E>
+sff_status launch_level(const MatchArgs& a, int iters, hipStream_t st) {
     const int nz = a.ndir * a.batch;
     const int tiles_y = (a.Hk + 3) / 4;
     const dim3 block(256);
     if (a.hyp_coarse && iters == 0) {
         const int tiles_x = (a.Wk + 63) / 64;
-        hipLaunchKernelGGL(half_step_kernel<C>, dim3(tiles_x * tiles_y * nz), block, 0, st, a, 0, 0,
-                           3, tiles_x, tiles_y);
+        hipLaunchKernelGGL((half_step_kernel<C, E>), dim3(tiles_x * tiles_y * nz), block, 0, st, a,
+                           0, 0, 3, tiles_x, tiles_y);
         return launch_status();
     }
     const int tiles_x = ((a.Wk + 1) / 2 + 63) / 64;
@@ -292,10 +338,24 @@ sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
         for (int colour = 0; colour < 2; ++colour) {
             int mode = 0;
             if (a.hyp_coarse && it == 0) mode = colour == 0 ? 1 : 2;
-            hipLaunchKernelGGL(half_step_kernel<C>, dim3(tiles_x * tiles_y * nz), block, 0, st, a,
-                               it, colour, mode, tiles_x, tiles_y);
+            hipLaunchKernelGGL((half_step_kernel<C, E>), dim3(tiles_x * tiles_y * nz), block, 0, st,
+                               a, it, colour, mode, tiles_x, tiles_y);
         }
     return launch_status();
+}
+
+// SFF_MATCH_EVAL = "lane" or "coop" forces an evaluator (both give identical
+// results; the switch exists to test and time each one); anything else: auto.
+template <int C>
+sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
+    const long updates = (long)a.ndir * a.batch * a.Hk * ((a.Wk + 1) / 2);
+    bool coop = updates >= kCoopMinUpdates;
+    if (const char* e = std::getenv("SFF_MATCH_EVAL")) {
+        if (std::strcmp(e, "lane") == 0) coop = false;
+        if (std::strcmp(e, "coop") == 0) coop = true;
+    }
+    if (!coop) return launch_level<C, LaneEval<C>>(a, iters, st);
+    return launch_level<C, CoopEval<C>>(a, iters, st);
 }
 
 }  // namespace

@@ -151,9 +151,13 @@ LEVEL_CASES = [
 ]
 
 
+@pytest.mark.parametrize("evaluator", ["lane", "coop"])
 @pytest.mark.parametrize("case", LEVEL_CASES, ids=[c[0] for c in LEVEL_CASES])
-def test_match_level_parity(sff, case):
+def test_match_level_parity(sff, case, evaluator, monkeypatch):
+    """Both descriptor-gather kernels (per-lane and wave-cooperative) against
+    the oracle; SFF_MATCH_EVAL forces one of them."""
     import torch
+    monkeypatch.setenv("SFF_MATCH_EVAL", evaluator)
     name, H, W, C, levels, level, iters, rs, B = case
     fmax, dmax = 16, 12
     p = params_dict(H, W, C, levels=levels, iters=iters, rs_samples=rs, fmax=fmax, dmax=dmax)
@@ -169,7 +173,7 @@ def test_match_level_parity(sff, case):
         Dc = [_oracle_descs(imgs[b], level + 1) for b in range(B)]
         coarse = np.stack([np.stack([oracle.init_nn(Dc[b], level + 1, s, fmax, dmax)[0]
                                      for b in range(B)]) for s in (1, -1)])
-        _say("match_level", name, "hand-off")
+        _say("match_level", name, evaluator, "hand-off")
         hyp, cost = sff.sff_match_level(p, desc_l, sff.DIR_BOTH, level, dev(seeds),
                                         hyp_coarse=dev(coarse))
         for di, s in enumerate((1, -1)):
@@ -183,7 +187,7 @@ def test_match_level_parity(sff, case):
                                     for b in range(B)]) for s in (1, -1)])
         startc = np.stack([np.stack([oracle.init_nn(Dl[b], level, s, fmax, dmax)[1]
                                      for b in range(B)]) for s in (1, -1)])
-        _say("match_level", name, "from init")
+        _say("match_level", name, evaluator, "from init")
         hyp = dev(start)
         cost = dev(startc.view(np.int32))
         sff.sff_match_level(p, desc_l, sff.DIR_BOTH, level, dev(seeds), hyp, cost)
@@ -264,8 +268,10 @@ def test_pipeline_ragged_batch_on_side_stream(sff):
         _check_pipeline(sff, scenes, p, [5, 6, 7], stream=st)
 
 
-def test_pipeline_kitti_full(sff):
-    _say("pipeline kitti 1242x375")
+@pytest.mark.parametrize("evaluator", ["auto", "lane", "coop"])
+def test_pipeline_kitti_full(sff, evaluator, monkeypatch):
+    monkeypatch.setenv("SFF_MATCH_EVAL", evaluator)
+    _say("pipeline kitti 1242x375", evaluator)
     _check_pipeline(sff, [make_scene(kitti_spec())], kitti_params(), [2])
 
 
