@@ -18,6 +18,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-file code generation options.  The exact-NN kernel consumes every MFMA
+# result in VALU code at once; keeping the results in VGPRs (instead of
+# accumulation registers that need a copy-out each) removes 3 moves per element.
+EXTRA = {"sff_init.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def sources():
@@ -31,7 +35,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in sources():
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [HIPCC] + COMMON + (HIP_FLAGS if src.endswith(".hip") else []) + ["-c", src, "-o", obj]
+        cmd = [HIPCC] + COMMON + (HIP_FLAGS if src.endswith(".hip") else [])
+        cmd += EXTRA.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), src))

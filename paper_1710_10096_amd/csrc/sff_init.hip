@@ -10,9 +10,15 @@
 // every int16 coefficient split exactly into a = 256 a_h + a_l (a_l in
 // [-128, 127], a_h in [-64, 64]):
 //   a.b = 65536 (a_h.b_h) + 256 (a_h.b_l + a_l.b_h) + a_l.b_l,
-// each partial an exact int32 MFMA accumulation.  The true squared distance of
-// up to 4 channels is below 2^32, so evaluating the identity modulo 2^32 in
-// uint32 arithmetic yields it exactly.
+// each partial an exact int32 MFMA accumulation.  The queries enter negated
+// (the split of -a), so the MFMAs give the partials of -a.b, and the argmin
+// key |b|^2 - 2 a.b = |a - b|^2 - |a|^2 is three shift-adds per candidate.
+// A squared distance of one view is below 2^31 (at most 4 channels), so the
+// key lies in (-2^31, 2^31) and its int32 value, computed modulo 2^32, is
+// exact; |a|^2 is added back to the winner.
+#include <climits>
+#include <type_traits>
+
 #include "sff_device.hpp"
 
 namespace sff {
@@ -33,11 +39,13 @@ constexpr int kWaves = 4;    // waves per block, splitting the candidate rows
 constexpr int kKBytes = 64;  // MFMA K: 16 C int8 values, zero padded (C <= 4)
 
 // Split planes of the coarsest-level grid of all four views:
-//   hi[z][p][64], lo[z][p][64] int8 and sq[z][p] = |desc|^2 mod 2^32,
-// z = pair * 4 + view, p = i * Wk + j.
+//   hi[z][p][64], lo[z][p][64] int8 (the split of desc), nhi, nlo (the split
+//   of -desc) and sq[z][p] = |desc|^2, z = pair * 4 + view, p = i * Wk + j.
 struct SplitPlanes {
     int8_t* hi;
     int8_t* lo;
+    int8_t* nhi;
+    int8_t* nlo;
     uint32_t* sq;
 };
 
@@ -50,29 +58,34 @@ __global__ void __launch_bounds__(256) split_kernel(const int16_t* __restrict__ 
     const int i = p / Wk, j = p - i * Wk;
     const size_t mapsz = (size_t)H * W * 16 * kRecC<C>;
     const int16_t* d = desc + (size_t)z * mapsz + ((size_t)(n * i) * W + n * j) * 16 * kRecC<C>;
-    uint32_t hw[kKBytes / 4], lw[kKBytes / 4];
+    uint32_t hw[2][kKBytes / 4], lw[2][kKBytes / 4];
     uint32_t sq = 0;
 #pragma unroll
     for (int w = 0; w < kKBytes / 4; ++w) {
-        hw[w] = 0;
-        lw[w] = 0;
+        hw[0][w] = lw[0][w] = hw[1][w] = lw[1][w] = 0;
     }
 #pragma unroll
     for (int k = 0; k < 16 * C; ++k) {
         const int a = d[k];
-        const int lo = ((a + 128) & 255) - 128;
-        const int hi = (a - lo) >> 8;
         sq += (uint32_t)(a * a);
-        hw[k >> 2] |= (uint32_t)(uint8_t)(int8_t)hi << (8 * (k & 3));
-        lw[k >> 2] |= (uint32_t)(uint8_t)(int8_t)lo << (8 * (k & 3));
+#pragma unroll
+        for (int neg = 0; neg < 2; ++neg) {
+            const int v = neg ? -a : a;
+            const int lo = ((v + 128) & 255) - 128;
+            const int hi = (v - lo) >> 8;
+            hw[neg][k >> 2] |= (uint32_t)(uint8_t)(int8_t)hi << (8 * (k & 3));
+            lw[neg][k >> 2] |= (uint32_t)(uint8_t)(int8_t)lo << (8 * (k & 3));
+        }
     }
     const size_t o = (size_t)z * Hk * Wk + p;
-    uint4* ho = reinterpret_cast<uint4*>(P.hi + o * kKBytes);
-    uint4* lo4 = reinterpret_cast<uint4*>(P.lo + o * kKBytes);
+    int8_t* const dst[4] = {P.hi, P.lo, P.nhi, P.nlo};
 #pragma unroll
-    for (int q = 0; q < kKBytes / 16; ++q) {
-        ho[q] = make_uint4(hw[4 * q], hw[4 * q + 1], hw[4 * q + 2], hw[4 * q + 3]);
-        lo4[q] = make_uint4(lw[4 * q], lw[4 * q + 1], lw[4 * q + 2], lw[4 * q + 3]);
+    for (int m = 0; m < 4; ++m) {
+        const uint32_t* src = (m & 1) ? lw[m >> 1] : hw[m >> 1];
+        uint4* out = reinterpret_cast<uint4*>(dst[m] + o * kKBytes);
+#pragma unroll
+        for (int q = 0; q < kKBytes / 16; ++q)
+            out[q] = make_uint4(src[4 * q], src[4 * q + 1], src[4 * q + 2], src[4 * q + 3]);
     }
     P.sq[o] = sq;
 }
@@ -96,7 +109,7 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
     __shared__ int res_u[kQRows][16], res_v[kQRows][16];
     __shared__ uint32_t res_t[kQRows][16];
     __shared__ unsigned long long red2[4][kQRows][16];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_id();
     const int nq = lane & 15, g = lane >> 4;
     const int j0 = blockIdx.x * 16, i0 = blockIdx.y * kQRows;
     const int z = blockIdx.z;  // dir_index * batch + b
@@ -108,65 +121,154 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
     const size_t Nk = (size_t)Hk * Wk;
     const size_t zR = ((size_t)b * 4 + vR) * Nk, zT = ((size_t)b * 4 + vT) * Nk;
 
-    // queries (B operands), one 16-column tile per query row
+    const int W = a.W;
+    const size_t mapsz = (size_t)a.H * W * 16 * kRecC<C>;
+    const int16_t* base = a.desc + (size_t)b * 4 * mapsz;
+
+    // queries (B operands, negated), one 16-column tile per query row
     v4i qh[kQRows], ql[kQRows];
-    uint32_t asq[kQRows], best[kQRows], bidx[kQRows];
+    int best[kQRows], btile[kQRows];
     const int jq = min(j0 + nq, Wk - 1);
 #pragma unroll
     for (int t = 0; t < kQRows; ++t) {
         const size_t o = zR + (size_t)min(i0 + t, Hk - 1) * Wk + jq;
-        qh[t] = load16(P.hi + o * kKBytes + 16 * g);
-        ql[t] = load16(P.lo + o * kKBytes + 16 * g);
-        asq[t] = P.sq[o];
-        best[t] = 0xFFFFFFFFu;
-        bidx[t] = 0;
+        qh[t] = load16(P.nhi + o * kKBytes + 16 * g);
+        ql[t] = load16(P.nlo + o * kKBytes + 16 * g);
+        best[t] = INT_MAX;
+        btile[t] = 0;
     }
+    // Scan: per query only the minimum key over this lane's candidates and the
+    // first tile (in increasing target index) that reaches it are kept; the
+    // target inside that tile is recovered afterwards.
     const int rlo = max(0, i0 - F), rhi = min(Hk - 1, i0 + kQRows - 1 + F);
     const int nct = (16 + 2 * F + 15) / 16;
+    // candidate tiles of this wave: rows rlo + w, rlo + w + kWaves, ... and the
+    // column tiles that overlap the image, visited in increasing target index
+    const int ct_lo = max(0, (F - j0) >> 4);                     // first c0 + 15 >= 0
+    const int ct_hi = min(nct - 1, (Wk - 1 - j0 + F) >> 4);      // last c0 < Wk
+    const int ntl = ct_hi - ct_lo + 1;
+    const int nrw = rlo + w <= rhi ? (rhi - rlo - w) / kWaves + 1 : 0;
+    const int total = ntl > 0 ? nrw * ntl : 0;
     const v4i zero = {0, 0, 0, 0};
-    for (int r = rlo + w; r <= rhi; r += kWaves) {
+
+    struct Tile {
+        v4i ah, al;
+        int bsq[4];
+    };
+    // Loads of tile (r, ct); the scan issues those of the next tile before it
+    // scores the current one.
+    auto load_tile = [&](int r, int ct) {
+        Tile T;
         const size_t rowT = zT + (size_t)r * Wk;
-        for (int ct = 0; ct < nct; ++ct) {
-            const int c0 = j0 - F + 16 * ct;
-            if (c0 + 15 < 0 || c0 >= Wk) continue;
-            const size_t oa = rowT + clampi(c0 + nq, 0, Wk - 1);
-            const v4i ah = load16(P.hi + oa * kKBytes + 16 * g);
-            const v4i al = load16(P.lo + oa * kKBytes + 16 * g);
-            uint32_t bsq[4];
+        const int c0 = j0 - F + 16 * ct;
+        const size_t oa = rowT + clampi(c0 + nq, 0, Wk - 1);
+        T.ah = load16(P.hi + oa * kKBytes + 16 * g);
+        T.al = load16(P.lo + oa * kKBytes + 16 * g);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) bsq[e] = P.sq[rowT + clampi(c0 + 4 * g + e, 0, Wk - 1)];
-            // every candidate of the tile inside the image and in every query's box
-            const bool full = c0 >= 0 && c0 + 15 < Wk && c0 >= j0 + 15 - F && c0 + 15 <= j0 + F;
-#pragma unroll
-            for (int t = 0; t < kQRows; ++t) {
-                const int iq = i0 + t;
-                if (iq >= Hk || r < iq - F || r > iq + F) continue;
-                const v4i hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, qh[t], zero, 0, 0, 0);
-                v4i cr = __builtin_amdgcn_mfma_i32_16x16x64_i8(ah, ql[t], zero, 0, 0, 0);
-                cr = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, qh[t], cr, 0, 0, 0);
-                const v4i ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(al, ql[t], zero, 0, 0, 0);
+        for (int e = 0; e < 4; ++e) T.bsq[e] = (int)P.sq[rowT + clampi(c0 + 4 * g + e, 0, Wk - 1)];
+        return T;
+    };
+    Tile cur{};
+    int r = rlo + w, ct = ct_lo;
+    if (total > 0) cur = load_tile(r, ct);
+    for (int q = 0; q < total; ++q) {
+        Tile nxt{};
+        int rn = r, ctn = ct + 1;
+        if (ctn > ct_hi) {
+            ctn = ct_lo;
+            rn += kWaves;
+        }
+        if (q + 1 < total) nxt = load_tile(rn, ctn);
+        const int c0 = j0 - F + 16 * ct;
+        const int tile_id = (r << 16) | ct;
+        // every query row of the block has row r inside its box (wave-uniform)
+        const bool all_rows = i0 + kQRows - 1 < Hk && r >= i0 + kQRows - 1 - F && r <= i0 + F;
+        // Keys of one tile for every query row.  Candidates outside the image
+        // or this lane's query box get INT_MAX (above any true key); interior
+        // tiles (every candidate inside every query's box) and rows inside
+        // every query row's box skip those tests.  Both conditions are
+        // wave-uniform.
+        auto score = [&](auto interior, auto rows_in) {
+            constexpr bool kInterior = decltype(interior)::value;
+            constexpr bool kRowsIn = decltype(rows_in)::value;
+            bool ok[4] = {true, true, true, true};
+            if constexpr (!kInterior) {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int jc = c0 + 4 * g + e;
-                    // 2 a.b mod 2^32 = 2 (256 (256 hh + cr) + ll)
-                    const uint32_t ab = ((((uint32_t)hh[e] << 8) + (uint32_t)cr[e]) << 8) + (uint32_t)ll[e];
-                    uint32_t ssd = asq[t] + bsq[e] - (ab << 1);
-                    if (!full) {
-                        const bool ok = (unsigned)(jc - (j0 + nq) + F) <= (unsigned)(2 * F) &&
-                                        (unsigned)jc < (unsigned)Wk;
-                        ssd = ok ? ssd : 0xFFFFFFFFu;
-                    }
-                    if (ssd < best[t]) {
-                        best[t] = ssd;
-                        bidx[t] = (uint32_t)(r * Wk + jc);
+                    ok[e] = (unsigned)(jc - jq + F) <= (unsigned)(2 * F) && (unsigned)jc < (unsigned)Wk;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kQRows; ++t) {
+                if constexpr (!kRowsIn) {
+                    const int iq = i0 + t;
+                    if (iq >= Hk || r < iq - F || r > iq + F) continue;
+                }
+                const v4i hh = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur.ah, qh[t], zero, 0, 0, 0);
+                v4i cr = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur.ah, ql[t], zero, 0, 0, 0);
+                cr = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur.al, qh[t], cr, 0, 0, 0);
+                const v4i ll = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur.al, ql[t], zero, 0, 0, 0);
+                int k[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    // |b|^2 + 2 (-a.b), -a.b = 256 (256 hh + cr) + ll  (mod 2^32)
+                    const uint32_t key = (uint32_t)cur.bsq[e] + ((uint32_t)ll[e] << 1) +
+                                         ((uint32_t)cr[e] << 9) + ((uint32_t)hh[e] << 17);
+                    k[e] = (int)key;
+                    if constexpr (!kInterior) k[e] = ok[e] ? k[e] : INT_MAX;
+                }
+                const int m = min(min(k[0], k[1]), min(k[2], k[3]));
+                const bool better = m < best[t];
+                btile[t] = better ? tile_id : btile[t];
+                best[t] = better ? m : best[t];
+            }
+        };
+        const bool interior = c0 >= 0 && c0 + 15 < Wk && c0 >= j0 + 15 - F && c0 + 15 <= j0 + F;
+        if (interior) {
+            if (all_rows)
+                score(std::true_type{}, std::true_type{});
+            else
+                score(std::true_type{}, std::false_type{});
+        } else {
+            if (all_rows)
+                score(std::false_type{}, std::true_type{});
+            else
+                score(std::false_type{}, std::false_type{});
+        }
+        cur = nxt;
+        r = rn;
+        ct = ctn;
+    }
+    // the smallest target index of the winning tile that reaches the minimum
+    // (exact squared distances from the int16 descriptors, equal to the MFMA
+    // identity's)
+    const int16_t* Tm = base + (size_t)vT * mapsz;
+    const int16_t* Rm = base + (size_t)vR * mapsz;
+#pragma unroll 1
+    for (int t = 0; t < kQRows; ++t) {
+        uint32_t bssd = 0xFFFFFFFFu, bidx = 0;
+        if (best[t] != INT_MAX) {
+            const int r = btile[t] >> 16, c0 = j0 - F + 16 * (btile[t] & 0xFFFF);
+            const Desc<C> qd = load_desc<C>(Rm, (size_t)(n * min(i0 + t, Hk - 1)) * W + n * jq);
+            const uint32_t asq = P.sq[zR + (size_t)min(i0 + t, Hk - 1) * Wk + jq];
+            bssd = (uint32_t)best[t] + asq;
+            bool found = false;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int jc = c0 + 4 * g + e;
+                const bool ok = (unsigned)(jc - jq + F) <= (unsigned)(2 * F) && (unsigned)jc < (unsigned)Wk;
+                if (ok && !found) {
+                    const uint32_t d = desc_ssd<C>(qd, load_desc<C>(Tm, (size_t)(n * r) * W + n * jc));
+                    if (d == bssd) {
+                        found = true;
+                        bidx = (uint32_t)(r * Wk + jc);
                     }
                 }
             }
         }
+        red[w * 4 + g][t][nq] = ((unsigned long long)bssd << 32) | bidx;
     }
-#pragma unroll
-    for (int t = 0; t < kQRows; ++t)
-        red[w * 4 + g][t][nq] = ((unsigned long long)best[t] << 32) | bidx[t];
     __syncthreads();
     // combine the 16 partial minima (waves x lane groups) of each query
     if (threadIdx.x < kQRows * 16) {
@@ -187,10 +289,7 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
     const int iq = i0 + t, jqq = j0 + q;
     const bool live = iq < Hk && jqq < Wk;
     const int x = n * min(jqq, Wk - 1), y = n * min(iq, Hk - 1);
-    const int W = a.W;
-    const size_t mapsz = (size_t)a.H * W * 16 * kRecC<C>;
-    const int16_t* base = a.desc + (size_t)b * 4 * mapsz;
-    const Desc<C> qd = load_desc<C>(base + (size_t)vR * mapsz, (size_t)y * W + x);
+    const Desc<C> qd = load_desc<C>(Rm, (size_t)y * W + x);
     const int16_t* Sm = base + (size_t)vS * mapsz;
     const int16_t* Xm = base + (size_t)vX * mapsz;
     // stereo partner on row y: target tx = x - s d0, increasing tx
@@ -243,7 +342,7 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct InitWs {
-    size_t hi, lo, sq, total;
+    size_t hi, lo, nhi, nlo, sq, total;
 };
 
 InitWs init_ws(const sff_params& p, int batch) {
@@ -252,7 +351,9 @@ InitWs init_ws(const sff_params& p, int batch) {
     InitWs L;
     L.hi = 0;
     L.lo = align256(cnt * kKBytes);
-    L.sq = L.lo + align256(cnt * kKBytes);
+    L.nhi = L.lo + align256(cnt * kKBytes);
+    L.nlo = L.nhi + align256(cnt * kKBytes);
+    L.sq = L.nlo + align256(cnt * kKBytes);
     L.total = L.sq + align256(cnt * sizeof(uint32_t));
     return L;
 }
@@ -299,6 +400,8 @@ extern "C" sff_status sff_init_nn(const sff_params* p, int32_t batch, int32_t di
     SplitPlanes P;
     P.hi = reinterpret_cast<int8_t*>(ws + L.hi);
     P.lo = reinterpret_cast<int8_t*>(ws + L.lo);
+    P.nhi = reinterpret_cast<int8_t*>(ws + L.nhi);
+    P.nlo = reinterpret_cast<int8_t*>(ws + L.nlo);
     P.sq = reinterpret_cast<uint32_t*>(ws + L.sq);
     const int nz4 = 4 * batch;
     const dim3 sgrid((g.Hk * g.Wk + 255) / 256, nz4);

@@ -52,6 +52,10 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // ---------------------------------------------------------------- device --
 __device__ __forceinline__ int clampi(int a, int lo, int hi) { return min(max(a, lo), hi); }
 
+// Index of the calling wave (64 lanes) in its block, as a scalar: lets the
+// compiler keep per-wave quantities and branches in scalar registers.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds, multipliers 0xD2511F53 and
 // 0xCD9E8D57, Weyl key increments 0x9E3779B9 and 0xBB67AE85.
 struct U4 {

@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
     const int z = tile / per_field;
     const int tr = tile - z * per_field;
     const int tx = tr / tiles_y, ty = tr - tx * tiles_y;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     const int i = ty * 4 + wv;
     if (i >= a.Hk) return;  // whole wave
     const int par = mode == 3 ? 0 : ((i + colour) & 1);
