@@ -121,6 +121,31 @@ def cpu_baseline(scenes, p, seeds) -> dict:
             "cpu": platform.processor() or platform.machine()}
 
 
+def with_upload(m, imgs, seeds, steps: int) -> dict:
+    """The same step preceded by the upload of the batch's images from pinned
+    host memory (PCIe-inclusive rate; the library itself takes device
+    buffers, so this is context, not the headline value)."""
+    import torch
+    host = imgs.cpu().pin_memory()
+    st = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    up = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e0.record(st)
+        imgs.copy_(host, non_blocking=True)
+        e1.record(st)
+        m.run(imgs, seeds)
+        e2.record(st)
+        e2.synchronize()
+        up += e0.elapsed_time(e1)
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    npx = imgs.shape[0] * imgs.shape[2] * imgs.shape[3]
+    return {"ms_per_step": ms, "px_per_s": npx / (ms * 1e-3), "h2d_ms": up / steps,
+            "h2d_bytes": host.numel()}
+
+
 def probes(reps: int = 5) -> dict:
     """Achievable bandwidth of a streaming copy (512 MiB) and of random record
     gathers over a buffer the size of one level's four KITTI-size descriptor
@@ -251,6 +276,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roof,
     }
+    out["with_upload"] = with_upload(m, imgs, seeds_t, args.steps)
     if not args.no_probes:
         out["probes"] = probes()
     if not args.no_cpu_baseline:
