@@ -17,6 +17,9 @@ Each wrapper names the passage its C function follows:
 * ``init_nn`` -- initialisation by nearest neighbours, Section 3.1.
 * ``match_level`` -- propagation and random search, Section 3.1.
 * ``consistency`` -- consistency check, Section 3.1 and tau_c of Section 5.
+* ``region_filter`` -- region filter, Section 3.1 (second step of the
+  consistency check) and s_c of Section 5.
+* ``sparsify`` -- best match per 3x3 block, Section 3.2 "Sparsification".
 * ``match_pair`` -- the whole stage for one pair, Section 3 overview.
 """
 from __future__ import annotations
@@ -50,6 +53,8 @@ def lib():
         L.orc_match_level.argtypes = ([P, P, P, P] + [i32] * 5 + [ctypes.c_uint64]
                                       + [i32] * 5 + [P, i32, i32, P, P])
         L.orc_consistency.argtypes = [P, P, i32, i32, i32, P, P]
+        L.orc_region_filter.argtypes = [P, P, i32, i32, i32, i32, P]
+        L.orc_sparsify.argtypes = [P, P, i32, i32, P]
         L.orc_match_pair.argtypes = ([P] + [i32] * 10 + [ctypes.c_uint64, i32] + [P] * 4)
         L.orc_max_threads.restype = i32
         L.orc_rs_candidate.argtypes = ([ctypes.c_uint64] + [i32] * 10 + [P, P])
@@ -176,6 +181,29 @@ def consistency(hyp_fwd, hyp_inv, tau: int):
     err = np.zeros((H, W), np.uint32)
     assert lib().orc_consistency(_p(hf), _p(hi), H, W, tau, _p(valid), _p(err)) == 0
     return valid, err
+
+
+def region_filter(hyp_fwd, valid, tau: int, s_c: int):
+    """Region filter (Section 3.1, "Consistency Check", second step): keep
+    uint8 [H][W] from the forward field [H][W][4] and the consistency mask."""
+    hf = _c(hyp_fwd, np.int16)
+    va = _c(valid, np.uint8)
+    H, W, _ = hf.shape
+    keep = np.zeros((H, W), np.uint8)
+    assert lib().orc_region_filter(_p(hf), _p(va), H, W, tau, s_c, _p(keep)) == 0
+    return keep
+
+
+def sparsify(keep, err):
+    """Sparsification (Section 3.2): per non-overlapping 3x3 block the index
+    y*W + x of the surviving match with the lowest error (ties: lowest index),
+    or -1; int32 [ceil(H/3)][ceil(W/3)]."""
+    kp = _c(keep, np.uint8)
+    er = _c(err, np.uint32)
+    H, W = kp.shape
+    seeds = np.zeros(((H + 2) // 3, (W + 2) // 3), np.int32)
+    assert lib().orc_sparsify(_p(kp), _p(er), H, W, _p(seeds)) == 0
+    return seeds
 
 
 def match_pair(imgs, params: dict, seed: int, nthreads: int = 0):

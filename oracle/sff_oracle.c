@@ -533,6 +533,107 @@ int orc_consistency(const int16_t* hyp_fwd, const int16_t* hyp_inv, int H, int W
 }
 
 /* ------------------------------------------------------------------------- */
+/* Region filter (Section 3.1, "Consistency Check", second step; s_c, Section */
+/* 5).  The consistent pixels are grouped into regions: two 4-neighbours     */
+/* belong to one region when both are consistent and their vectors are       */
+/* approximately the same -- read as every component (u, v, d0, d1) differing */
+/* by at most tau px.  A region is removed when it has fewer than s_c pixels  */
+/* and one of the already removed pixels (consistency outliers) next to it   */
+/* could be added by the same rule, i.e. some inconsistent 4-neighbour of a  */
+/* region pixel has approximately that pixel's vector.                        */
+/* hyp: forward field int16 [H][W][4]; valid: consistency result u8 [H][W];   */
+/* keep: u8 [H][W] output, 1 for a surviving match.                           */
+/* Plain breadth-first region growing in raster order.                        */
+/* ------------------------------------------------------------------------- */
+static int similar_vec(const int16_t* a, const int16_t* b, int tau) {
+    for (int c = 0; c < 4; ++c) {
+        const int d = (int)a[c] - (int)b[c];
+        if (d > tau || d < -tau) return 0;
+    }
+    return 1;
+}
+
+int orc_region_filter(const int16_t* hyp, const uint8_t* valid, int H, int W, int tau, int s_c,
+                      uint8_t* keep) {
+    const size_t npx = (size_t)H * W;
+    int32_t* label = (int32_t*)malloc(sizeof(int32_t) * npx);
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * npx);
+    int32_t* size = (int32_t*)malloc(sizeof(int32_t) * npx);
+    uint8_t* flag = (uint8_t*)malloc(npx);
+    if (!label || !queue || !size || !flag) {
+        free(label); free(queue); free(size); free(flag);
+        return ORC_ERR;
+    }
+    static const int DX[4] = {-1, 1, 0, 0}, DY[4] = {0, 0, -1, 1};
+    for (size_t p = 0; p < npx; ++p) label[p] = -1;
+    int nreg = 0;
+    for (int y0 = 0; y0 < H; ++y0)
+        for (int x0 = 0; x0 < W; ++x0) {
+            const size_t p0 = (size_t)y0 * W + x0;
+            if (!valid[p0] || label[p0] >= 0) continue;
+            /* grow region nreg from p0 */
+            size_t head = 0, tail = 0;
+            label[p0] = nreg;
+            queue[tail++] = (int32_t)p0;
+            while (head < tail) {
+                const int32_t p = queue[head++];
+                const int x = p % W, y = p / W;
+                for (int k = 0; k < 4; ++k) {
+                    const int xn = x + DX[k], yn = y + DY[k];
+                    if (xn < 0 || xn >= W || yn < 0 || yn >= H) continue;
+                    const size_t q = (size_t)yn * W + xn;
+                    if (!valid[q] || label[q] >= 0) continue;
+                    if (!similar_vec(hyp + (size_t)p * 4, hyp + q * 4, tau)) continue;
+                    label[q] = nreg;
+                    queue[tail++] = (int32_t)q;
+                }
+            }
+            size[nreg] = (int32_t)tail;
+            flag[nreg] = 0;
+            ++nreg;
+        }
+    /* outliers that could join a neighbouring region */
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const size_t p = (size_t)y * W + x;
+            if (valid[p]) continue;
+            for (int k = 0; k < 4; ++k) {
+                const int xn = x + DX[k], yn = y + DY[k];
+                if (xn < 0 || xn >= W || yn < 0 || yn >= H) continue;
+                const size_t q = (size_t)yn * W + xn;
+                if (valid[q] && similar_vec(hyp + p * 4, hyp + q * 4, tau)) flag[label[q]] = 1;
+            }
+        }
+    for (size_t p = 0; p < npx; ++p)
+        keep[p] = (valid[p] && !(flag[label[p]] && size[label[p]] < s_c)) ? 1 : 0;
+    free(label); free(queue); free(size); free(flag);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sparsification (Section 3.2 "Sparsification"): in every non-overlapping    */
+/* 3 x 3 block (aligned at the origin; blocks at the right and bottom border  */
+/* are cut by the image), the surviving match with the lowest consistency     */
+/* error; ties to the lowest raster index y * W + x.  seeds: int32             */
+/* [ceil(H/3)][ceil(W/3)], the pixel index y * W + x, or -1 for a block       */
+/* without a surviving match.                                                 */
+/* ------------------------------------------------------------------------- */
+int orc_sparsify(const uint8_t* keep, const uint32_t* err, int H, int W, int32_t* seeds) {
+    const int Hb = (H + 2) / 3, Wb = (W + 2) / 3;
+    for (int bi = 0; bi < Hb; ++bi)
+        for (int bj = 0; bj < Wb; ++bj) {
+            int32_t best = -1;
+            for (int y = 3 * bi; y < 3 * bi + 3 && y < H; ++y)
+                for (int x = 3 * bj; x < 3 * bj + 3 && x < W; ++x) {
+                    const int32_t p = y * W + x;
+                    if (keep[p] && (best < 0 || err[p] < err[best])) best = p;
+                }
+            seeds[(size_t)bi * Wb + bj] = best;
+        }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Whole stage for one pair (Section 3 overview up to the consistency check): */
 /* descriptors of the four images at every level, then for the forward        */
 /* (s = +1) and inverse (s = -1) fields: exact-NN initialisation at the       */

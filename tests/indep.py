@@ -147,3 +147,64 @@ def exhaustive_min(Bs, s, level, fmax, dmax):
                 best = tot if best is None else min(best, tot)
             out[i, j] = best
     return out
+
+
+def region_filter_union_find(hyp, valid, tau, s_c):
+    """Region filter by union-find over the similarity edges (a different
+    algorithm from the oracle's breadth-first growing): edges join
+    4-neighbours that are both valid with every vector component within tau;
+    a component is dropped when it has fewer than s_c pixels and an invalid
+    4-neighbour of one of its pixels is within tau of that pixel's vector."""
+    H, W = valid.shape
+    parent = np.arange(H * W)
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    h = hyp.reshape(H * W, 4).astype(np.int64)
+    v = valid.reshape(-1).astype(bool)
+    sim = lambda p, q: bool(np.all(np.abs(h[p] - h[q]) <= tau))
+    for y in range(H):
+        for x in range(W):
+            p = y * W + x
+            for q in ([p + 1] if x + 1 < W else []) + ([p + W] if y + 1 < H else []):
+                if v[p] and v[q] and sim(p, q):
+                    a, b = find(p), find(q)
+                    if a != b:
+                        parent[max(a, b)] = min(a, b)
+    root = np.array([find(p) for p in range(H * W)])
+    size = np.bincount(root[v], minlength=H * W)
+    flagged = np.zeros(H * W, bool)
+    for y in range(H):
+        for x in range(W):
+            p = y * W + x
+            if v[p]:
+                continue
+            for yn, xn in ((y, x - 1), (y, x + 1), (y - 1, x), (y + 1, x)):
+                if 0 <= yn < H and 0 <= xn < W:
+                    q = yn * W + xn
+                    if v[q] and sim(p, q):
+                        flagged[root[q]] = True
+    drop = flagged[root] & (size[root] < s_c)
+    return (v & ~drop).reshape(H, W).astype(np.uint8)
+
+
+def sparsify_blocks(keep, err):
+    """Per 3x3 block: argmin over (err, raster index) of the kept pixels, by a
+    padded reshape and a lexicographic key; -1 for empty blocks."""
+    H, W = keep.shape
+    Hb, Wb = -(-H // 3), -(-W // 3)
+    idx = np.full((Hb * 3, Wb * 3), -1, np.int64)
+    idx[:H, :W] = np.arange(H * W).reshape(H, W)
+    e = np.full((Hb * 3, Wb * 3), np.iinfo(np.int64).max, np.int64)
+    k = np.zeros((Hb * 3, Wb * 3), bool)
+    k[:H, :W] = keep.astype(bool)
+    e[:H, :W] = err.astype(np.int64)
+    key = np.where(k, e * (H * W + 1) + idx, np.iinfo(np.int64).max)
+    blocks = key.reshape(Hb, 3, Wb, 3).transpose(0, 2, 1, 3).reshape(Hb, Wb, 9)
+    m = blocks.min(axis=2)
+    out = np.where(m == np.iinfo(np.int64).max, -1, m % (H * W + 1))
+    return out.astype(np.int32)
