@@ -121,6 +121,35 @@ def cpu_baseline(scenes, p, seeds) -> dict:
             "cpu": platform.processor() or platform.machine()}
 
 
+def region_stage(p, B, m, steps: int) -> dict:
+    """The step after the consistency check (region filter with s_c = 150,
+    then the 3x3 sparsification) on the last step's fields, timed with events
+    on the launching stream; not part of the headline step."""
+    import torch
+    import paper_1710_10096_amd as sff
+    dev = m.valid.device
+    keep = torch.empty_like(m.valid)
+    seeds = torch.empty((B, (p["H"] + 2) // 3, (p["W"] + 2) // 3), dtype=torch.int32, device=dev)
+    ws = torch.empty(sff.sff_region_workspace_bytes(p, B), dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    sff.sff_region_filter(p, m.hyp[0][0], m.valid, 150, keep, ws)
+    torch.cuda.synchronize()
+    t_r = t_s = 0.0
+    for _ in range(steps):
+        ev[0].record(st)
+        sff.sff_region_filter(p, m.hyp[0][0], m.valid, 150, keep, ws)
+        ev[1].record(st)
+        sff.sff_sparsify(p, keep, m.err, seeds)
+        ev[2].record(st)
+        ev[2].synchronize()
+        t_r += ev[0].elapsed_time(ev[1])
+        t_s += ev[1].elapsed_time(ev[2])
+    return {"region_ms": t_r / steps, "sparsify_ms": t_s / steps, "s_c": 150,
+            "kept": int(keep.sum().item()), "consistent": int(m.valid.sum().item()),
+            "seeds": int((seeds >= 0).sum().item())}
+
+
 def with_upload(m, imgs, seeds, steps: int) -> dict:
     """The same step preceded by the upload of the batch's images from pinned
     host memory (PCIe-inclusive rate; the library itself takes device
@@ -277,6 +306,7 @@ def main():
         "roofline": roof,
     }
     out["with_upload"] = with_upload(m, imgs, seeds_t, args.steps)
+    out["region_sparsify"] = region_stage(p, B, m, args.steps)
     if not args.no_probes:
         out["probes"] = probes()
     if not args.no_cpu_baseline:

@@ -174,6 +174,38 @@ sff_status sff_match_level(const sff_params* p, int32_t batch, int32_t dir, int3
 sff_status sff_consistency(const sff_params* p, int32_t batch, const int16_t* hyp_fwd,
                            const int16_t* hyp_inv, uint8_t* valid, uint32_t* err, void* stream);
 
+/* Device workspace (bytes) that sff_region_filter needs for `batch` fields
+ * (12 bytes per pixel); 0 for invalid arguments. */
+size_t sff_region_workspace_bytes(const sff_params* p, int32_t batch);
+
+/* Region filter (Section 3.1, "Consistency Check", second step; the paper
+ * uses s_c = 150, Section 5).  Consistent pixels form regions: two
+ * 4-neighbours belong to one region when both are valid and every component
+ * of their vectors differs by at most p->tau.  A region is dropped when it has
+ * fewer than s_c pixels and some inconsistent 4-neighbour of one of its pixels
+ * has a vector within p->tau of that pixel's (a removed outlier that could
+ * join it).  The result does not depend on the order of evaluation.
+ * hyp_fwd: level-0 forward field [batch][H][W][4] (8-byte aligned);
+ * valid: [batch][H][W] uint8 from sff_consistency;
+ * keep: [batch][H][W] uint8 (0/1), written;
+ * workspace: at least sff_region_workspace_bytes(p, batch) bytes, 256-byte
+ *   aligned; contents on entry are ignored.
+ * Errors: SFF_ERR_INVALID_ARG (also s_c < 1), SFF_ERR_WORKSPACE. */
+sff_status sff_region_filter(const sff_params* p, int32_t batch, int32_t s_c,
+                             const int16_t* hyp_fwd, const uint8_t* valid, uint8_t* keep,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
+/* Sparsification (Section 3.2, "Sparsification"): in each non-overlapping
+ * 3 x 3 block (aligned at the origin, cut at the right and bottom borders) the
+ * kept match with the lowest consistency error, ties to the lowest raster
+ * index y * W + x.
+ * keep: [batch][H][W] uint8; err: [batch][H][W] uint32 (from sff_consistency);
+ * seeds: [batch][ceil(H/3)][ceil(W/3)] int32, written: the pixel index y*W + x
+ *   of the block's seed, or -1 for a block without a kept match.
+ * Errors: SFF_ERR_INVALID_ARG. */
+sff_status sff_sparsify(const sff_params* p, int32_t batch, const uint8_t* keep,
+                        const uint32_t* err, int32_t* seeds, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Window form of the matching cost on real-valued feature maps (eq. (1),
  * Section 3.1: feature distances summed over a window around the pixel for the

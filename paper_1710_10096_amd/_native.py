@@ -29,7 +29,8 @@ class SffParams(ctypes.Structure):
 
 EXPORTS = ("sff_status_string", "sff_version", "sff_desc_channels", "sff_lanczos_q14", "sff_wht_workspace_bytes",
            "sff_wht_features", "sff_init_workspace_bytes", "sff_init_nn", "sff_match_level",
-           "sff_consistency", "sff_cost_f32_fwd", "sff_cost_f32_bwd_workspace_bytes",
+           "sff_consistency", "sff_region_workspace_bytes", "sff_region_filter", "sff_sparsify",
+           "sff_cost_f32_fwd", "sff_cost_f32_bwd_workspace_bytes",
            "sff_cost_f32_bwd", "sff_conv3x3_bf16_fwd", "sff_conv3x3_bf16_bwd_workspace_bytes",
            "sff_conv3x3_bf16_dgrad", "sff_conv3x3_bf16_wgrad", "sff_smooth_level",
            "sff_quantise_features", "sff_triplet_loss", "sff_take_grad_bf16", "sff_probe_copy",
@@ -68,6 +69,12 @@ def lib() -> ctypes.CDLL:
     L.sff_match_level.restype = i32
     L.sff_consistency.argtypes = [PP, i32, P, P, P, P, P]
     L.sff_consistency.restype = i32
+    L.sff_region_workspace_bytes.argtypes = [PP, i32]
+    L.sff_region_workspace_bytes.restype = ctypes.c_size_t
+    L.sff_region_filter.argtypes = [PP, i32, i32, P, P, P, P, ctypes.c_size_t, P]
+    L.sff_region_filter.restype = i32
+    L.sff_sparsify.argtypes = [PP, i32, P, P, P, P]
+    L.sff_sparsify.restype = i32
     L.sff_cost_f32_fwd.argtypes = [i32] * 5 + [P, P, P, P]
     L.sff_cost_f32_fwd.restype = i32
     L.sff_cost_f32_bwd_workspace_bytes.argtypes = [i32] * 3

@@ -189,6 +189,52 @@ def sff_consistency(p, hyp_fwd: torch.Tensor, hyp_inv: torch.Tensor, valid=None,
     return valid, err
 
 
+def sff_region_workspace_bytes(p, batch: int) -> int:
+    pp = _params(p)
+    return int(lib().sff_region_workspace_bytes(ctypes.byref(pp), batch))
+
+
+def sff_region_filter(p, hyp_fwd: torch.Tensor, valid: torch.Tensor, s_c: int = 150, keep=None,
+                      workspace=None, stream=None) -> torch.Tensor:
+    """Region filter: level-0 forward field [batch][H][W][4] and consistency
+    mask [batch][H][W] -> keep uint8 [batch][H][W] (tau of the params is the
+    vector similarity threshold, s_c the minimal region size)."""
+    pp = _params(p)
+    batch = hyp_fwd.shape[0]
+    _check_shape(hyp_fwd, (batch, pp.H, pp.W, 4), "hyp_fwd")
+    _check_shape(valid, (batch, pp.H, pp.W), "valid")
+    if keep is None:
+        keep = torch.empty((batch, pp.H, pp.W), dtype=torch.uint8, device=hyp_fwd.device)
+    _check_shape(keep, (batch, pp.H, pp.W), "keep")
+    if workspace is None:
+        workspace = torch.empty(sff_region_workspace_bytes(pp, batch), dtype=torch.uint8,
+                                device=hyp_fwd.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(lib().sff_region_filter(ctypes.byref(pp), batch, int(s_c),
+                                   _ptr(hyp_fwd, torch.int16, "hyp_fwd"),
+                                   _ptr(valid, torch.uint8, "valid"), _ptr(keep, torch.uint8, "keep"),
+                                   _ptr(workspace, None, "workspace"), ws_bytes, _stream(stream)),
+           "sff_region_filter")
+    return keep
+
+
+def sff_sparsify(p, keep: torch.Tensor, err: torch.Tensor, seeds=None, stream=None) -> torch.Tensor:
+    """Best match per 3x3 block: keep uint8 and err (uint32 bits in int32)
+    [batch][H][W] -> seeds int32 [batch][ceil(H/3)][ceil(W/3)] (index or -1)."""
+    pp = _params(p)
+    batch = keep.shape[0]
+    _check_shape(keep, (batch, pp.H, pp.W), "keep")
+    _check_shape(err, (batch, pp.H, pp.W), "err")
+    shape = (batch, (pp.H + 2) // 3, (pp.W + 2) // 3)
+    if seeds is None:
+        seeds = torch.empty(shape, dtype=torch.int32, device=keep.device)
+    _check_shape(seeds, shape, "seeds")
+    _check(lib().sff_sparsify(ctypes.byref(pp), batch, _ptr(keep, torch.uint8, "keep"),
+                              _ptr(err, torch.int32, "err"), _ptr(seeds, torch.int32, "seeds"),
+                              _stream(stream)), "sff_sparsify")
+    return seeds
+
+
 def sff_cost_f32_fwd(feat: torch.Tensor, hyp: torch.Tensor, dir: int, cost=None, stream=None):
     """feat float32 [batch][4][H][W][cf], hyp int16 [batch][H][W][4] -> cost [batch][H][W]."""
     B, four, H, W, cf = feat.shape

@@ -3,7 +3,9 @@ overview, up to the consistency check), as a sequence of libsff calls on one
 stream: for levels K-1 .. 0, WHT features of the four views, exact-NN
 initialisation at the coarsest level, propagation + random search with the
 hand-off from the coarser level; then the consistency check at level 0.
-Forward and inverse fields run together (SFF_DIR_BOTH).
+Forward and inverse fields run together (SFF_DIR_BOTH).  With ``s_c`` set,
+the region filter (Section 3.1, second consistency step) and the 3x3
+sparsification (Section 3.2) follow, giving the seeds of the interpolation.
 
 Buffers are allocated once per shape; a call only enqueues kernels.
 """
@@ -16,7 +18,8 @@ from ._native import SffParams
 
 
 class PairMatcher:
-    def __init__(self, params, batch: int = 1, device: str | torch.device = "cuda"):
+    def __init__(self, params, batch: int = 1, device: str | torch.device = "cuda",
+                 s_c: int | None = None):
         self.p = params if isinstance(params, SffParams) else SffParams.from_dict(params)
         self.batch = int(batch)
         p, B = self.p, self.batch
@@ -33,6 +36,13 @@ class PairMatcher:
             self.cost.append(torch.empty((2, B, Hk, Wk), dtype=torch.int32, device=dev))
         self.valid = torch.empty((B, p.H, p.W), dtype=torch.uint8, device=dev)
         self.err = torch.empty((B, p.H, p.W), dtype=torch.int32, device=dev)
+        self.s_c = s_c
+        if s_c is not None:
+            self.keep = torch.empty((B, p.H, p.W), dtype=torch.uint8, device=dev)
+            self.seeds = torch.empty((B, (p.H + 2) // 3, (p.W + 2) // 3), dtype=torch.int32,
+                                     device=dev)
+            self.ws_region = torch.empty(api.sff_region_workspace_bytes(p, B), dtype=torch.uint8,
+                                         device=dev)
 
     def run(self, imgs: torch.Tensor, seeds: torch.Tensor, stream=None, mark=None) -> dict:
         """imgs uint8 [batch][4][H][W][C] (l0, l1, r0, r1); seeds int64 [batch].
@@ -61,7 +71,21 @@ class PairMatcher:
             mk(f"match:L{k}")
         api.sff_consistency(p, self.hyp[0][0], self.hyp[0][1], self.valid, self.err, stream)
         mk("consistency:L0")
-        return dict(hyp=self.hyp[0], cost=self.cost[0], valid=self.valid, err=self.err)
+        out = dict(hyp=self.hyp[0], cost=self.cost[0], valid=self.valid, err=self.err)
+        if self.s_c is not None:
+            self.filter_and_sparsify(stream, mk)
+            out.update(keep=self.keep, seeds=self.seeds)
+        return out
+
+    def filter_and_sparsify(self, stream=None, mark=None):
+        """Region filter and 3x3 sparsification of the last run's result."""
+        mk = mark if mark is not None else (lambda name: None)
+        p = self.p
+        api.sff_region_filter(p, self.hyp[0][0], self.valid, self.s_c, self.keep, self.ws_region,
+                              stream)
+        mk("region:L0")
+        api.sff_sparsify(p, self.keep, self.err, self.seeds, stream)
+        mk("sparsify:L0")
 
 
 def match_pairs(params, imgs: torch.Tensor, seeds: torch.Tensor) -> dict:

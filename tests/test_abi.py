@@ -128,6 +128,18 @@ def test_invalid_arguments_rejected():
     assert L.sff_wht_workspace_bytes(ctypes.byref(p2), 4, 0) == 0
     assert L.sff_wht_features(ctypes.byref(p2), 4, 1, f, f, None, 0, None) == 4
     assert L.sff_wht_features(ctypes.byref(p2), 4, 1, f, f, f, need - 1, None) == 4
+    # region filter and sparsification
+    need = L.sff_region_workspace_bytes(P, 1)
+    assert need == 3 * ((96 * 160 * 4 + 255) // 256 * 256)
+    assert L.sff_region_workspace_bytes(P, 0) == 0
+    assert L.sff_region_filter(P, 1, 0, f, f, f, f, need, None) == 1        # s_c < 1
+    assert L.sff_region_filter(P, 1, 150, None, f, f, f, need, None) == 1
+    assert L.sff_region_filter(P, 1, 150, ctypes.c_void_p(0x1004), f, f, f, need, None) == 1
+    assert L.sff_region_filter(P, 1, 150, f, f, f, f, need - 1, None) == 4
+    assert L.sff_region_filter(P, 1, 150, f, f, f, ctypes.c_void_p(0x1010), need, None) == 4
+    assert L.sff_sparsify(P, 1, f, f, None, None) == 1
+    assert L.sff_sparsify(P, 0, f, f, f, None) == 1
+    assert L.sff_sparsify(P, 1, f, ctypes.c_void_p(0x1002), f, None) == 1
     # overlapping hand-off buffers
     p3 = _good()
     p3.levels = 2
