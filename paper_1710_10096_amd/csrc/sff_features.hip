@@ -81,41 +81,44 @@ __global__ void area_kernel(const uint8_t* __restrict__ img, uint8_t* __restrict
     }
 }
 
-// h: one thread per (img, i, x, c).
-__global__ void lanczos_h_kernel(const uint8_t* __restrict__ A, int16_t* __restrict__ h, int W,
-                                 int C, int n, int Hk, int Wk, LanczosTable T) {
-    const int xc = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = blockIdx.y;
-    const int m = blockIdx.z;
-    if (xc >= W * C) return;
-    const int x = xc / C, c = xc - x * C;
-    const int p = x % n, j = x / n;
-    const uint8_t* row = A + ((size_t)m * Hk + i) * Wk * C;
-    int acc = 8192;
-#pragma unroll
-    for (int t = 0; t < 6; ++t) {
-        const int jj = clampi(j + T.base[p] + t, 0, Wk - 1);
-        acc += T.w[p][t] * (int)row[jj * C + c];
-    }
-    h[(((size_t)m * Hk + i) * W) * C + xc] = (int16_t)floor_shift14(acc);
-}
+// Both Lanczos passes in one kernel.  Block = 256 consecutive (x, c) columns
+// of kBandRows output rows of one image: the horizontal pass is computed for
+// the block-mean rows the band needs (at most kBandRows / n + 7) into LDS, then
+// each thread forms its column's vertical pass.  Both passes round exactly as
+// in the separate definition: h = (sum + 8192) >> 14 unclamped, then
+// S = clamp((sum + 8192) >> 14, 0, 255).
+constexpr int kBandRows = 32;
+constexpr int kBandH = kBandRows + 7;  // h rows for n = 1 (the largest count)
 
-// S: one thread per (img, y, x, c).
-__global__ void lanczos_v_kernel(const int16_t* __restrict__ h, uint8_t* __restrict__ S, int H,
-                                 int W, int C, int n, int Hk, LanczosTable T) {
-    const int xc = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
-    const int m = blockIdx.z;
-    if (xc >= W * C) return;
-    const int p = y % n, i = y / n;
-    const int16_t* plane = h + (size_t)m * Hk * W * C;
-    int acc = 8192;
+__global__ void __launch_bounds__(256) lanczos_hv_kernel(const uint8_t* __restrict__ A,
+                                                         uint8_t* __restrict__ S, int H, int W,
+                                                         int C, int n, int Hk, int Wk,
+                                                         LanczosTable T) {
+    __shared__ int hb[kBandH][256];
+    const int xc = blockIdx.x * 256 + threadIdx.x;
+    const int y0 = blockIdx.y * kBandRows, m = blockIdx.z;
+    const int y1 = min(y0 + kBandRows, H);
+    // vertical taps of rows y0..y1-1 reach block-mean rows y/n - 3 .. y/n + 3
+    const int ilo = y0 / n - 3, ihi = (y1 - 1) / n + 3;
+    const bool live = xc < W * C;
+    const int x = live ? xc / C : 0, c = xc - x * C;
+    const int ph = x % n, jh = x / n + T.base[ph];
+    const uint8_t* Am = A + (size_t)m * Hk * Wk * C;
+    for (int r = 0; r <= ihi - ilo; ++r) {
+        const uint8_t* row = Am + (size_t)clampi(ilo + r, 0, Hk - 1) * Wk * C;
+        int acc = 8192;
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
-        const int ii = clampi(i + T.base[p] + t, 0, Hk - 1);
-        acc += T.w[p][t] * (int)plane[(size_t)ii * W * C + xc];
+        for (int t = 0; t < 6; ++t) acc += T.w[ph][t] * (int)row[clampi(jh + t, 0, Wk - 1) * C + c];
+        hb[r][threadIdx.x] = floor_shift14(acc);
     }
-    S[((size_t)m * H + y) * W * C + xc] = (uint8_t)clampi(floor_shift14(acc), 0, 255);
+    if (!live) return;  // no barrier follows: each thread reads only its own column
+    for (int y = y0; y < y1; ++y) {
+        const int pv = y % n, ib = y / n + T.base[pv] - ilo;
+        int acc = 8192;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) acc += T.w[pv][t] * hb[ib + t][threadIdx.x];
+        S[((size_t)m * H + y) * W * C + xc] = (uint8_t)clampi(floor_shift14(acc), 0, 255);
+    }
 }
 
 // 4-point sequency-ordered WHT: rows (1,1,1,1), (1,1,-1,-1), (1,-1,-1,1), (1,-1,1,-1).
@@ -134,9 +137,11 @@ __device__ __forceinline__ void wht4(int& x0, int& x1, int& x2, int& x3) {
 // again so every wave stores its row of 64 descriptors as one contiguous run.
 constexpr int kTW = 64, kTH = 4;
 
-template <int C>
+// n (the pyramid factor) is a template parameter so that every LDS offset
+// of the bin sums is an immediate.
+template <int C, int n>
 __global__ void __launch_bounds__(256) wht_kernel(const uint8_t* __restrict__ S,
-                                                  int16_t* __restrict__ desc, int H, int W, int n) {
+                                                  int16_t* __restrict__ desc, int H, int W) {
     extern __shared__ uint8_t smem[];
     const int RW = kTW + 7 * n, RH = kTH + 7 * n;
     uint8_t* reg = smem;                                                   // [RH][RW][C]
@@ -145,11 +150,24 @@ __global__ void __launch_bounds__(256) wht_kernel(const uint8_t* __restrict__ S,
     const uint8_t* src = S + (size_t)m * H * W * C;
     const int gx0 = x0 - 3 * n, gy0 = y0 - 3 * n;
     const int rowb = RW * C;
-    for (int idx = threadIdx.x; idx < RH * rowb; idx += 256) {
-        const int ry = idx / rowb, rr = idx - ry * rowb;
-        const int rx = rr / C, c = rr - rx * C;
-        const int gy = clampi(gy0 + ry, 0, H - 1), gx = clampi(gx0 + rx, 0, W - 1);
-        reg[idx] = src[((size_t)gy * W + gx) * C + c];
+    // wave w stages region rows w, w + 4, ...; lanes walk the row's bytes
+    // (only divisions by the compile-time channel count)
+    {
+        const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        const bool inner = gx0 >= 0 && gx0 + RW <= W;  // no column clamping (block-uniform)
+        for (int ry = wv; ry < RH; ry += 4) {
+            const uint8_t* srow = src + (size_t)clampi(gy0 + ry, 0, H - 1) * W * C;
+            uint8_t* drow = reg + ry * rowb;
+            if (inner) {
+                const uint8_t* seg = srow + gx0 * C;
+                for (int rr = ln; rr < rowb; rr += 64) drow[rr] = seg[rr];
+            } else {
+                for (int rr = ln; rr < rowb; rr += 64) {
+                    const int rx = rr / C, c = rr - rx * C;
+                    drow[rr] = srow[clampi(gx0 + rx, 0, W - 1) * C + c];
+                }
+            }
+        }
     }
     __syncthreads();
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -192,6 +210,18 @@ __global__ void __launch_bounds__(256) wht_kernel(const uint8_t* __restrict__ S,
     }
 }
 
+template <int C>
+void launch_wht(int n, dim3 grid, size_t smem, hipStream_t st, const uint8_t* src, int16_t* desc,
+                int H, int W) {
+    switch (n) {
+        case 1: hipLaunchKernelGGL((wht_kernel<C, 1>), grid, dim3(256), smem, st, src, desc, H, W); break;
+        case 2: hipLaunchKernelGGL((wht_kernel<C, 2>), grid, dim3(256), smem, st, src, desc, H, W); break;
+        case 4: hipLaunchKernelGGL((wht_kernel<C, 4>), grid, dim3(256), smem, st, src, desc, H, W); break;
+        case 8: hipLaunchKernelGGL((wht_kernel<C, 8>), grid, dim3(256), smem, st, src, desc, H, W); break;
+        default: hipLaunchKernelGGL((wht_kernel<C, 16>), grid, dim3(256), smem, st, src, desc, H, W); break;
+    }
+}
+
 inline size_t wht_smem(int n, int C) {
     const int RW = kTW + 7 * n, RH = kTH + 7 * n;
     return ((size_t)(RH * RW * C + 15) & ~(size_t)15) + (size_t)kTH * kTW * 16 * C * sizeof(int16_t);
@@ -200,33 +230,30 @@ inline size_t wht_smem(int n, int C) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t a_off, h_off, s_off, total;
+    size_t a_off, s_off, total;
 };
 
 WsLayout ws_layout(const sff_params& p, int nimg, int level) {
-    WsLayout L{0, 0, 0, 0};
+    WsLayout L{0, 0, 0};
     if (level == 0) return L;
     const LevelGeom g = level_geom(p, level);
     const size_t C = (size_t)p.C;
     L.a_off = 0;
-    L.h_off = align256((size_t)nimg * g.Hk * g.Wk * C);
-    L.s_off = L.h_off + align256((size_t)nimg * g.Hk * p.W * C * sizeof(int16_t));
+    L.s_off = align256((size_t)nimg * g.Hk * g.Wk * C);
     L.total = L.s_off + align256((size_t)nimg * p.H * p.W * C);
     return L;
 }
 
 void launch_smooth(const sff_params& p, int nimg, int level, const uint8_t* img, uint8_t* A,
-                   int16_t* h, uint8_t* S, hipStream_t st) {
+                   uint8_t* S, hipStream_t st) {
     const int H = p.H, W = p.W, C = p.C;
     const LevelGeom g = level_geom(p, level);
     LanczosTable T;
     build_table(g.n, &T);
     hipLaunchKernelGGL(area_kernel, dim3((g.Wk + 63) / 64, g.Hk, nimg), dim3(64), 0, st, img, A, H, W,
                        C, g.n, g.Hk, g.Wk);
-    hipLaunchKernelGGL(lanczos_h_kernel, dim3((W * C + 255) / 256, g.Hk, nimg), dim3(256), 0, st, A,
-                       h, W, C, g.n, g.Hk, g.Wk, T);
-    hipLaunchKernelGGL(lanczos_v_kernel, dim3((W * C + 255) / 256, H, nimg), dim3(256), 0, st, h, S,
-                       H, W, C, g.n, g.Hk, T);
+    hipLaunchKernelGGL(lanczos_hv_kernel, dim3((W * C + 255) / 256, (H + kBandRows - 1) / kBandRows, nimg),
+                       dim3(256), 0, st, A, S, H, W, C, g.n, g.Hk, g.Wk, T);
 }
 
 }  // namespace
@@ -265,16 +292,16 @@ extern "C" sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_
     const uint8_t* src = img;
     if (level > 0) {
         uint8_t* ws = static_cast<uint8_t*>(workspace);
-        launch_smooth(*p, nimg, level, img, ws + L.a_off, reinterpret_cast<int16_t*>(ws + L.h_off),
+        launch_smooth(*p, nimg, level, img, ws + L.a_off,
                       ws + L.s_off, st);
         src = ws + L.s_off;
     }
     const dim3 grid((W + kTW - 1) / kTW, (H + kTH - 1) / kTH, nimg);
     switch (C) {
-        case 1: hipLaunchKernelGGL(wht_kernel<1>, grid, dim3(256), smem, st, src, desc, H, W, g.n); break;
-        case 2: hipLaunchKernelGGL(wht_kernel<2>, grid, dim3(256), smem, st, src, desc, H, W, g.n); break;
-        case 3: hipLaunchKernelGGL(wht_kernel<3>, grid, dim3(256), smem, st, src, desc, H, W, g.n); break;
-        default: hipLaunchKernelGGL(wht_kernel<4>, grid, dim3(256), smem, st, src, desc, H, W, g.n); break;
+        case 1: launch_wht<1>(g.n, grid, smem, st, src, desc, H, W); break;
+        case 2: launch_wht<2>(g.n, grid, smem, st, src, desc, H, W); break;
+        case 3: launch_wht<3>(g.n, grid, smem, st, src, desc, H, W); break;
+        default: launch_wht<4>(g.n, grid, smem, st, src, desc, H, W); break;
     }
     return launch_status();
 }
@@ -294,7 +321,6 @@ extern "C" sff_status sff_smooth_level(const sff_params* p, int32_t nimg, int32_
         return SFF_OK;
     }
     uint8_t* ws = static_cast<uint8_t*>(workspace);
-    launch_smooth(*p, nimg, level, img, ws + L.a_off, reinterpret_cast<int16_t*>(ws + L.h_off), out,
-                  st);
+    launch_smooth(*p, nimg, level, img, ws + L.a_off, out, st);
     return launch_status();
 }
