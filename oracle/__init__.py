@@ -20,7 +20,9 @@ Each wrapper names the passage its C function follows:
 * ``region_filter`` -- region filter, Section 3.1 (second step of the
   consistency check) and s_c of Section 5.
 * ``sparsify`` -- best match per 3x3 block, Section 3.2 "Sparsification".
-* ``match_pair`` -- the whole stage for one pair, Section 3 overview.
+* ``match_pair`` -- the whole stage for one pair, Section 3 overview
+  (``schedule="scan"``: the paper's sequential four-corner propagation,
+  ``match_level_scan``, CPU only, to measure the red-black schedule).
 """
 from __future__ import annotations
 
@@ -56,6 +58,10 @@ def lib():
         L.orc_region_filter.argtypes = [P, P, i32, i32, i32, i32, P]
         L.orc_sparsify.argtypes = [P, P, i32, i32, P]
         L.orc_match_pair.argtypes = ([P] + [i32] * 10 + [ctypes.c_uint64, i32] + [P] * 4)
+        L.orc_match_pair_schedule.argtypes = ([P] + [i32] * 10 + [ctypes.c_uint64, i32, i32]
+                                              + [P] * 4)
+        L.orc_match_level_scan.argtypes = ([P] * 4 + [i32] * 5 + [ctypes.c_uint64] + [i32] * 5
+                                           + [P, i32, P, P])
         L.orc_max_threads.restype = i32
         L.orc_rs_candidate.argtypes = ([ctypes.c_uint64] + [i32] * 10 + [P, P])
         _lib = L
@@ -206,7 +212,24 @@ def sparsify(keep, err):
     return seeds
 
 
-def match_pair(imgs, params: dict, seed: int, nthreads: int = 0):
+def match_level_scan(descs, level: int, s: int, seed: int, iters: int, rs_r0: int,
+                     rs_samples: int, fmax: int, dmax: int, hyp0, cost0, hyp_coarse=None,
+                     nthreads: int = 0):
+    """One level with the paper's sequential four-corner schedule (CPU only)."""
+    D = [_c(d, np.int16) for d in descs]
+    H, W, C, _ = D[0].shape
+    n = 1 << level
+    Hk, Wk = -(-H // n), -(-W // n)
+    hyp = np.zeros((Hk, Wk, 4), np.int16) if hyp0 is None else _c(hyp0, np.int16).copy()
+    cost = np.zeros((Hk, Wk), np.uint32) if cost0 is None else _c(cost0, np.uint32).copy()
+    hc = None if hyp_coarse is None else _c(hyp_coarse, np.int16)
+    assert lib().orc_match_level_scan(*[_p(d) for d in D], H, W, C, level, s, seed, iters, rs_r0,
+                                      rs_samples, fmax, dmax, None if hc is None else _p(hc),
+                                      nthreads, _p(hyp), _p(cost)) == 0
+    return hyp, cost
+
+
+def match_pair(imgs, params: dict, seed: int, nthreads: int = 0, schedule: str = "red-black"):
     """Whole stage on one pair.  imgs: uint8 [4][H][W][C] (l0, l1, r0, r1).
     Returns dict with hyp [2][H][W][4] (forward, inverse), cost [2][H][W],
     valid [H][W], err [H][W]."""
@@ -217,7 +240,9 @@ def match_pair(imgs, params: dict, seed: int, nthreads: int = 0):
     valid = np.zeros((H, W), np.uint8)
     err = np.zeros((H, W), np.uint32)
     p = params
-    assert lib().orc_match_pair(_p(im), H, W, C, p["levels"], p["iters"], p["rs_r0"],
-                                p["rs_samples"], p["fmax"], p["dmax"], p["tau"], seed, nthreads,
-                                _p(hyp), _p(cst), _p(valid), _p(err)) == 0
+    scan = {"red-black": 0, "scan": 1}[schedule]
+    assert lib().orc_match_pair_schedule(_p(im), H, W, C, p["levels"], p["iters"], p["rs_r0"],
+                                         p["rs_samples"], p["fmax"], p["dmax"], p["tau"], seed,
+                                         nthreads, scan, _p(hyp), _p(cst), _p(valid),
+                                         _p(err)) == 0
     return dict(hyp=hyp, cost=cst, valid=valid, err=err)

@@ -492,6 +492,75 @@ int orc_match_level(const int16_t* l0, const int16_t* l1, const int16_t* r0, con
 }
 
 /* ------------------------------------------------------------------------- */
+/* The paper's own propagation schedule (Section 3.1, "Multi-Scale            */
+/* Propagation"), kept to measure what the red-black Jacobi schedule changes  */
+/* (CPU only).  Iteration it scans the grid sequentially from corner it mod 4 */
+/* (top-left, bottom-right, top-right, bottom-left), so each direction is     */
+/* used equally; each pixel takes the cheapest of its own vector and the      */
+/* vectors of its two already-visited neighbours (the one before it in the   */
+/* row, then the one in the previous row; strict improvement), so a better    */
+/* vector travels along the whole scan path.  After the scan every pixel runs */
+/* the random search around its vector, with the same samples as the         */
+/* red-black schedule (iteration counter it).                                 */
+/* ------------------------------------------------------------------------- */
+int orc_match_level_scan(const int16_t* l0, const int16_t* l1, const int16_t* r0,
+                         const int16_t* r1, int H, int W, int C, int level, int s, uint64_t seed,
+                         int iters, int rs_r0, int rs_samples, int fmax, int dmax,
+                         const int16_t* hyp_coarse, int nthreads, int16_t* hyp, uint32_t* cost) {
+    const int n = 1 << level;
+    const int Hk = (H + n - 1) / n, Wk = (W + n - 1) / n;
+    orc_views V = make_views(l0, l1, r0, r1, H, W, C, s);
+    set_threads(nthreads);
+    if (hyp_coarse) {
+        const int Wc = (W + 2 * n - 1) / (2 * n);
+        for (int i = 0; i < Hk; ++i)
+            for (int j = 0; j < Wk; ++j) {
+                int16_t* h = hyp + ((size_t)i * Wk + j) * 4;
+                hyp_copy(h, hyp_coarse + ((size_t)(i >> 1) * Wc + (j >> 1)) * 4);
+                cost[(size_t)i * Wk + j] = cost_eq1(&V, n * j, n * i, h);
+            }
+    }
+    for (int it = 0; it < iters; ++it) {
+        const int dir = it & 3;
+        const int sy = (dir == 0 || dir == 2) ? 1 : -1;  /* rows top-down or bottom-up */
+        const int sx = (dir == 0 || dir == 3) ? 1 : -1;  /* columns left-right or right-left */
+        for (int ii = 0; ii < Hk; ++ii) {
+            const int i = sy > 0 ? ii : Hk - 1 - ii;
+            for (int jj = 0; jj < Wk; ++jj) {
+                const int j = sx > 0 ? jj : Wk - 1 - jj;
+                int16_t* own = hyp + ((size_t)i * Wk + j) * 4;
+                uint32_t* oc = cost + (size_t)i * Wk + j;
+                const int pi[2] = {i, i - sy}, pj[2] = {j - sx, j};
+                for (int q = 0; q < 2; ++q) {
+                    if (pi[q] < 0 || pi[q] >= Hk || pj[q] < 0 || pj[q] >= Wk) continue;
+                    const int16_t* nh = hyp + ((size_t)pi[q] * Wk + pj[q]) * 4;
+                    const uint32_t c = cost_eq1(&V, n * j, n * i, nh);
+                    if (c < *oc) { *oc = c; hyp_copy(own, nh); }
+                }
+            }
+        }
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int i = 0; i < Hk; ++i)
+            for (int j = 0; j < Wk; ++j) {
+                int16_t* own = hyp + ((size_t)i * Wk + j) * 4;
+                int16_t centre[4], best[4];
+                hyp_copy(centre, own);
+                hyp_copy(best, own);
+                uint32_t bestc = cost[(size_t)i * Wk + j];
+                for (int t = 0; t < rs_samples; ++t) {
+                    int16_t cand[4];
+                    orc_rs_candidate(seed, level, s, i, j, Wk, it, t, rs_r0, fmax, dmax, centre, cand);
+                    const uint32_t c = cost_eq1(&V, n * j, n * i, cand);
+                    if (c < bestc) { bestc = c; hyp_copy(best, cand); }
+                }
+                hyp_copy(own, best);
+                cost[(size_t)i * Wk + j] = bestc;
+            }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Consistency check (Section 3.1, "Consistency Check"; tau_c, Section 5).    */
 /* The inverse field has reference I_r^1.  At the cross target q = p +        */
 /* (u - d1, v) its vector (u', v', d0', d1') implies a left flow               */
@@ -642,9 +711,24 @@ int orc_sparsify(const uint8_t* keep, const uint32_t* err, int H, int W, int32_t
 /* imgs: uint8 [4][H][W][C] in order (l0, l1, r0, r1).                        */
 /* hyp_out: int16 [2][H][W][4] (forward, inverse), cost_out uint32 [2][H][W]. */
 /* ------------------------------------------------------------------------- */
+int orc_match_pair_schedule(const uint8_t* imgs, int H, int W, int C, int levels, int iters,
+                            int rs_r0, int rs_samples, int fmax, int dmax, int tau, uint64_t seed,
+                            int nthreads, int scan, int16_t* hyp_out, uint32_t* cost_out,
+                            uint8_t* valid, uint32_t* err);
+
 int orc_match_pair(const uint8_t* imgs, int H, int W, int C, int levels, int iters, int rs_r0,
                    int rs_samples, int fmax, int dmax, int tau, uint64_t seed, int nthreads,
                    int16_t* hyp_out, uint32_t* cost_out, uint8_t* valid, uint32_t* err) {
+    return orc_match_pair_schedule(imgs, H, W, C, levels, iters, rs_r0, rs_samples, fmax, dmax,
+                                   tau, seed, nthreads, 0, hyp_out, cost_out, valid, err);
+}
+
+/* scan = 0: red-black schedule (the one the GPU path implements); scan = 1:
+ * the sequential four-corner schedule above. */
+int orc_match_pair_schedule(const uint8_t* imgs, int H, int W, int C, int levels, int iters,
+                            int rs_r0, int rs_samples, int fmax, int dmax, int tau, uint64_t seed,
+                            int nthreads, int scan, int16_t* hyp_out, uint32_t* cost_out,
+                            uint8_t* valid, uint32_t* err) {
     const size_t npx = (size_t)H * W;
     const size_t dsz = npx * C * 16;
     int16_t* desc = (int16_t*)malloc(sizeof(int16_t) * dsz * 4);
@@ -664,14 +748,22 @@ int orc_match_pair(const uint8_t* imgs, int H, int W, int C, int levels, int ite
             uint32_t* cst = cost_out + (size_t)dir * npx;
             if (k == levels - 1) {
                 orc_init_nn(l0, l1, r0, r1, H, W, C, k, s, fmax, dmax, nthreads, hyp, cst);
-                orc_match_level(l0, l1, r0, r1, H, W, C, k, s, seed, iters, rs_r0, rs_samples,
-                                fmax, dmax, NULL, 0, nthreads, hyp, cst);
+                if (scan)
+                    orc_match_level_scan(l0, l1, r0, r1, H, W, C, k, s, seed, iters, rs_r0,
+                                         rs_samples, fmax, dmax, NULL, nthreads, hyp, cst);
+                else
+                    orc_match_level(l0, l1, r0, r1, H, W, C, k, s, seed, iters, rs_r0, rs_samples,
+                                    fmax, dmax, NULL, 0, nthreads, hyp, cst);
             } else {
                 const int n = 1 << (k + 1);
                 const size_t nc = (size_t)((H + n - 1) / n) * ((W + n - 1) / n);
                 memcpy(hyp_c, hyp, sizeof(int16_t) * nc * 4);
-                orc_match_level(l0, l1, r0, r1, H, W, C, k, s, seed, iters, rs_r0, rs_samples,
-                                fmax, dmax, hyp_c, 0, nthreads, hyp, cst);
+                if (scan)
+                    orc_match_level_scan(l0, l1, r0, r1, H, W, C, k, s, seed, iters, rs_r0,
+                                         rs_samples, fmax, dmax, hyp_c, nthreads, hyp, cst);
+                else
+                    orc_match_level(l0, l1, r0, r1, H, W, C, k, s, seed, iters, rs_r0, rs_samples,
+                                    fmax, dmax, hyp_c, 0, nthreads, hyp, cst);
             }
         }
     }
