@@ -52,13 +52,14 @@ def lib():
         L.orc_cost.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, i32, P]
         L.orc_cost.restype = ctypes.c_uint32
         L.orc_init_nn.argtypes = [P, P, P, P] + [i32] * 8 + [P, P]
+        L.orc_init_nn_leaves.argtypes = [P] * 4 + [i32] * 9 + [P, P]
         L.orc_match_level.argtypes = ([P, P, P, P] + [i32] * 5 + [ctypes.c_uint64]
                                       + [i32] * 5 + [P, i32, i32, P, P])
         L.orc_consistency.argtypes = [P, P, i32, i32, i32, P, P]
         L.orc_region_filter.argtypes = [P, P, i32, i32, i32, i32, P]
         L.orc_sparsify.argtypes = [P, P, i32, i32, P]
         L.orc_match_pair.argtypes = ([P] + [i32] * 10 + [ctypes.c_uint64, i32] + [P] * 4)
-        L.orc_match_pair_schedule.argtypes = ([P] + [i32] * 10 + [ctypes.c_uint64, i32, i32]
+        L.orc_match_pair_schedule.argtypes = ([P] + [i32] * 10 + [ctypes.c_uint64, i32, i32, i32]
                                               + [P] * 4)
         L.orc_match_level_scan.argtypes = ([P] * 4 + [i32] * 5 + [ctypes.c_uint64] + [i32] * 5
                                            + [P, i32, P, P])
@@ -145,13 +146,20 @@ def grid_shape(H: int, W: int, level: int):
     return (H + n - 1) // n, (W + n - 1) // n
 
 
-def init_nn(descs, level: int, s: int, fmax: int, dmax: int, nthreads: int = 0):
+def init_nn(descs, level: int, s: int, fmax: int, dmax: int, nthreads: int = 0,
+            leaves: int = 1):
+    """Exact-NN initialisation; ``leaves`` > 1 keeps that many temporal leaves
+    and picks the cheapest combination by eq. (1)."""
     ds, H, W, C = _descs(descs)
     Hk, Wk = grid_shape(H, W, level)
     hyp = np.zeros((Hk, Wk, 4), np.int16)
     cst = np.zeros((Hk, Wk), np.uint32)
-    assert lib().orc_init_nn(*[_p(d) for d in ds], H, W, C, level, s, fmax, dmax, nthreads,
-                             _p(hyp), _p(cst)) == 0
+    if leaves == 1:
+        assert lib().orc_init_nn(*[_p(d) for d in ds], H, W, C, level, s, fmax, dmax, nthreads,
+                                 _p(hyp), _p(cst)) == 0
+    else:
+        assert lib().orc_init_nn_leaves(*[_p(d) for d in ds], H, W, C, level, s, fmax, dmax,
+                                        leaves, nthreads, _p(hyp), _p(cst)) == 0
     return hyp, cst
 
 
@@ -229,7 +237,8 @@ def match_level_scan(descs, level: int, s: int, seed: int, iters: int, rs_r0: in
     return hyp, cost
 
 
-def match_pair(imgs, params: dict, seed: int, nthreads: int = 0, schedule: str = "red-black"):
+def match_pair(imgs, params: dict, seed: int, nthreads: int = 0, schedule: str = "red-black",
+               leaves: int = 1):
     """Whole stage on one pair.  imgs: uint8 [4][H][W][C] (l0, l1, r0, r1).
     Returns dict with hyp [2][H][W][4] (forward, inverse), cost [2][H][W],
     valid [H][W], err [H][W]."""
@@ -243,6 +252,6 @@ def match_pair(imgs, params: dict, seed: int, nthreads: int = 0, schedule: str =
     scan = {"red-black": 0, "scan": 1}[schedule]
     assert lib().orc_match_pair_schedule(_p(im), H, W, C, p["levels"], p["iters"], p["rs_r0"],
                                          p["rs_samples"], p["fmax"], p["dmax"], p["tau"], seed,
-                                         nthreads, scan, _p(hyp), _p(cst), _p(valid),
+                                         nthreads, scan, leaves, _p(hyp), _p(cst), _p(valid),
                                          _p(err)) == 0
     return dict(hyp=hyp, cost=cst, valid=valid, err=err)

@@ -322,21 +322,54 @@ uint32_t orc_cost(const int16_t* l0, const int16_t* l1, const int16_t* r0, const
 /* ties to the smallest target index y*W + x.  The single combination of the   */
 /* three returned leaves is the hypothesis; its cost is eq. (1).              */
 /* ------------------------------------------------------------------------- */
+int orc_init_nn_leaves(const int16_t* l0, const int16_t* l1, const int16_t* r0,
+                       const int16_t* r1, int H, int W, int C, int level, int s, int fmax,
+                       int dmax, int leaves, int nthreads, int16_t* hyp, uint32_t* cost);
+
 int orc_init_nn(const int16_t* l0, const int16_t* l1, const int16_t* r0, const int16_t* r1,
                 int H, int W, int C, int level, int s, int fmax, int dmax, int nthreads,
                 int16_t* hyp, uint32_t* cost) {
+    return orc_init_nn_leaves(l0, l1, r0, r1, H, W, C, level, s, fmax, dmax, 1, nthreads, hyp,
+                              cost);
+}
+
+/* The same initialisation with several leaves of the temporal tree: the     */
+/* `leaves` temporal targets of smallest descriptor distance (ties to the     */
+/* smaller target index), each combined with its own cross partner (argmin on */
+/* its row y + v) and with the stereo partner, all combinations compared by   */
+/* the data term eq. (1) (the paper's "comparing all combinations of the      */
+/* leafs").  Eq. (1) is a sum over the three views, so more stereo or cross   */
+/* leaves cannot change the winner: the best combination pairs each temporal  */
+/* leaf with the best cross target of its row.  Ties between combinations go  */
+/* to the earlier temporal leaf.  leaves = 1 is the plain initialisation.     */
+int orc_init_nn_leaves(const int16_t* l0, const int16_t* l1, const int16_t* r0,
+                       const int16_t* r1, int H, int W, int C, int level, int s, int fmax,
+                       int dmax, int leaves, int nthreads, int16_t* hyp, uint32_t* cost) {
+    if (leaves < 1) return ORC_ERR;
     const int n = 1 << level;
     const int Hk = (H + n - 1) / n, Wk = (W + n - 1) / n;
     orc_views V = make_views(l0, l1, r0, r1, H, W, C, s);
     const int fm = (fmax / n) * n, dm = (dmax / n) * n;
     set_threads(nthreads);
+    int fail = 0;
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int i = 0; i < Hk; ++i)
+    for (int i = 0; i < Hk; ++i) {
+        uint32_t* le = (uint32_t*)malloc(sizeof(uint32_t) * leaves);
+        int* lu = (int*)malloc(sizeof(int) * leaves);
+        int* lv = (int*)malloc(sizeof(int) * leaves);
+        if (!le || !lu || !lv) {
+            free(le); free(lu); free(lv);
+#pragma omp atomic write
+            fail = 1;
+            continue;
+        }
         for (int j = 0; j < Wk; ++j) {
             const int x = n * j, y = n * i;
-            /* temporal partner: scan targets in increasing linear index */
-            uint32_t bestT = UINT32_MAX;
-            int bu = 0, bv = 0;
+            /* temporal partner: the `leaves` best targets, scanned in
+             * increasing linear index, kept sorted by distance; a target
+             * enters after every kept target of equal distance (the earlier
+             * index stays first) */
+            int nl = 0;
             for (int v = -fm; v <= fm; v += n) {
                 int ty = y + v;
                 if (ty < 0 || ty >= H) continue;
@@ -344,7 +377,14 @@ int orc_init_nn(const int16_t* l0, const int16_t* l1, const int16_t* r0, const i
                     int tx = x + u;
                     if (tx < 0 || tx >= W) continue;
                     uint32_t e = ssd_at(&V, V.T, x, y, tx, ty);
-                    if (e < bestT) { bestT = e; bu = u; bv = v; }
+                    if (nl == leaves && e >= le[nl - 1]) continue;
+                    int pos = nl < leaves ? nl : leaves - 1;
+                    while (pos > 0 && le[pos - 1] > e) {
+                        le[pos] = le[pos - 1]; lu[pos] = lu[pos - 1]; lv[pos] = lv[pos - 1];
+                        --pos;
+                    }
+                    le[pos] = e; lu[pos] = u; lv[pos] = v;
+                    if (nl < leaves) ++nl;
                 }
             }
             /* stereo partner, same row: target tx = x - s*d0 */
@@ -356,20 +396,29 @@ int orc_init_nn(const int16_t* l0, const int16_t* l1, const int16_t* r0, const i
                 uint32_t e = ssd_at(&V, V.S, x, y, tx, y);
                 if (e < bestS) { bestS = e; bd0 = d0; }
             }
-            /* cross partner, row y + v*: target tx = x + u* - s*d1 */
-            uint32_t bestX = UINT32_MAX;
-            int bd1 = 0;
-            for (int tx = 0; tx < W; ++tx) {
-                int d1 = s * (x + bu - tx);
-                if (d1 < 0 || d1 > dm || (d1 % n) != 0) continue;
-                uint32_t e = ssd_at(&V, V.X, x, y, tx, y + bv);
-                if (e < bestX) { bestX = e; bd1 = d1; }
+            /* each temporal leaf with its cross partner on row y + v:
+             * target tx = x + u - s*d1; keep the cheapest combination */
+            uint64_t bestJ = UINT64_MAX;
+            int bu = 0, bv = 0, bd1 = 0;
+            for (int l = 0; l < nl; ++l) {
+                uint32_t bestX = UINT32_MAX;
+                int d1l = 0;
+                for (int tx = 0; tx < W; ++tx) {
+                    int d1 = s * (x + lu[l] - tx);
+                    if (d1 < 0 || d1 > dm || (d1 % n) != 0) continue;
+                    uint32_t e = ssd_at(&V, V.X, x, y, tx, y + lv[l]);
+                    if (e < bestX) { bestX = e; d1l = d1; }
+                }
+                const uint64_t joint = (uint64_t)le[l] + bestS + bestX;
+                if (joint < bestJ) { bestJ = joint; bu = lu[l]; bv = lv[l]; bd1 = d1l; }
             }
             int16_t* h = hyp + ((size_t)i * Wk + j) * 4;
             h[0] = (int16_t)bu; h[1] = (int16_t)bv; h[2] = (int16_t)bd0; h[3] = (int16_t)bd1;
             cost[(size_t)i * Wk + j] = cost_eq1(&V, x, y, h);
         }
-    return ORC_OK;
+        free(le); free(lu); free(lv);
+    }
+    return fail ? ORC_ERR : ORC_OK;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -713,22 +762,23 @@ int orc_sparsify(const uint8_t* keep, const uint32_t* err, int H, int W, int32_t
 /* ------------------------------------------------------------------------- */
 int orc_match_pair_schedule(const uint8_t* imgs, int H, int W, int C, int levels, int iters,
                             int rs_r0, int rs_samples, int fmax, int dmax, int tau, uint64_t seed,
-                            int nthreads, int scan, int16_t* hyp_out, uint32_t* cost_out,
-                            uint8_t* valid, uint32_t* err);
+                            int nthreads, int scan, int leaves, int16_t* hyp_out,
+                            uint32_t* cost_out, uint8_t* valid, uint32_t* err);
 
 int orc_match_pair(const uint8_t* imgs, int H, int W, int C, int levels, int iters, int rs_r0,
                    int rs_samples, int fmax, int dmax, int tau, uint64_t seed, int nthreads,
                    int16_t* hyp_out, uint32_t* cost_out, uint8_t* valid, uint32_t* err) {
     return orc_match_pair_schedule(imgs, H, W, C, levels, iters, rs_r0, rs_samples, fmax, dmax,
-                                   tau, seed, nthreads, 0, hyp_out, cost_out, valid, err);
+                                   tau, seed, nthreads, 0, 1, hyp_out, cost_out, valid, err);
 }
 
 /* scan = 0: red-black schedule (the one the GPU path implements); scan = 1:
- * the sequential four-corner schedule above. */
+ * the sequential four-corner schedule above.  leaves: temporal leaves of the
+ * initialisation (1 = the plain one). */
 int orc_match_pair_schedule(const uint8_t* imgs, int H, int W, int C, int levels, int iters,
                             int rs_r0, int rs_samples, int fmax, int dmax, int tau, uint64_t seed,
-                            int nthreads, int scan, int16_t* hyp_out, uint32_t* cost_out,
-                            uint8_t* valid, uint32_t* err) {
+                            int nthreads, int scan, int leaves, int16_t* hyp_out,
+                            uint32_t* cost_out, uint8_t* valid, uint32_t* err) {
     const size_t npx = (size_t)H * W;
     const size_t dsz = npx * C * 16;
     int16_t* desc = (int16_t*)malloc(sizeof(int16_t) * dsz * 4);
@@ -747,7 +797,11 @@ int orc_match_pair_schedule(const uint8_t* imgs, int H, int W, int C, int levels
             int16_t* hyp = hyp_out + (size_t)dir * npx * 4;
             uint32_t* cst = cost_out + (size_t)dir * npx;
             if (k == levels - 1) {
-                orc_init_nn(l0, l1, r0, r1, H, W, C, k, s, fmax, dmax, nthreads, hyp, cst);
+                if (orc_init_nn_leaves(l0, l1, r0, r1, H, W, C, k, s, fmax, dmax, leaves, nthreads,
+                                       hyp, cst) != ORC_OK) {
+                    free(desc); free(hyp_c);
+                    return ORC_ERR;
+                }
                 if (scan)
                     orc_match_level_scan(l0, l1, r0, r1, H, W, C, k, s, seed, iters, rs_r0,
                                          rs_samples, fmax, dmax, NULL, nthreads, hyp, cst);

@@ -208,3 +208,49 @@ def sparsify_blocks(keep, err):
     m = blocks.min(axis=2)
     out = np.where(m == np.iinfo(np.int64).max, -1, m % (H * W + 1))
     return out.astype(np.int32)
+
+
+def brute_init_leaves(Bs, s, level, fmax, dmax, leaves):
+    """Initialisation with `leaves` temporal leaves by brute force: the whole
+    temporal box sorted by (distance, linear index) with lexsort, each of the
+    first `leaves` targets paired with the exhaustive cross argmin of its row,
+    the combination with the smallest T + S + X distance (first on ties)."""
+    n = 1 << level
+    R, T, S, X = views(Bs, s)
+    H, W = R.shape[:2]
+    Hk, Wk = (H + n - 1) // n, (W + n - 1) // n
+    hyp = np.zeros((Hk, Wk, 4), np.int64)
+    joint = np.zeros((Hk, Wk), np.int64)
+    gy = np.arange(0, H, n)
+    gx = np.arange(0, W, n)
+
+    def row_argmin(img_row, q, tx_of_d):
+        d = np.arange(0, dmax + 1, n)
+        tx = tx_of_d(d)
+        ok = (tx >= 0) & (tx < W)
+        d, tx = d[ok], tx[ok]
+        e = 16 * ((img_row[tx] - q) ** 2).sum(axis=(1, 2, 3))
+        k = np.lexsort((tx, e))[0]
+        return d[k], e[k]
+
+    for i in range(Hk):
+        for j in range(Wk):
+            x, y = n * j, n * i
+            q = R[y, x]
+            cy = gy[np.abs(gy - y) <= fmax]
+            cx = gx[np.abs(gx - x) <= fmax]
+            e = 16 * ((T[np.ix_(cy, cx)] - q) ** 2).sum(axis=(2, 3, 4))
+            lin = cy[:, None] * W + cx[None, :]
+            order = np.lexsort((lin.ravel(), e.ravel()))[:leaves]
+            d0, eS = row_argmin(S[y], q, lambda d: x - s * d)
+            best = None
+            for k in order:
+                ty, tx = cy[k // len(cx)], cx[k % len(cx)]
+                u, v = tx - x, ty - y
+                d1, eX = row_argmin(X[y + v], q, lambda d: x + u - s * d)
+                tot = e.ravel()[k] + eS + eX
+                if best is None or tot < best[0]:
+                    best = (tot, (u, v, d0, d1))
+            joint[i, j] = best[0]
+            hyp[i, j] = best[1]
+    return hyp, joint
