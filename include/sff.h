@@ -134,6 +134,21 @@ sff_status sff_init_nn(const sff_params* p, int32_t batch, int32_t dir, const in
                        int16_t* hyp, uint32_t* cost, void* workspace, size_t workspace_bytes,
                        void* stream);
 
+/* The same initialisation with several leaves of the temporal search
+ * (Section 3.1, "Initialization": all combinations of the leaves compared by
+ * the data term).  The `leaves` temporal targets of smallest descriptor
+ * distance (ties to the smaller target index) are each paired with their own
+ * cross partner (argmin on row y + v) and with the stereo partner; the
+ * combination with the smallest eq. (1) cost wins, ties to the earlier
+ * temporal leaf.  (Eq. (1) is a sum over the three views, so more stereo or
+ * cross leaves could not change the winner.)  leaves = 1 is sff_init_nn.
+ * leaves: 1, 2 or 4.  Other arguments as sff_init_nn.
+ * Errors: as sff_init_nn; SFF_ERR_INVALID_ARG for leaves < 1,
+ *   SFF_ERR_UNSUPPORTED for other values. */
+sff_status sff_init_nn_leaves(const sff_params* p, int32_t batch, int32_t dir, int32_t leaves,
+                              const int16_t* desc, int16_t* hyp, uint32_t* cost, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
 /* Propagation and random search at one level (Section 3.1, "Multi-Scale
  * Propagation"), eq. (1) cost: sum over the temporal (x + u, y + v), stereo
  * (x - s d0, y) and cross (x + u - s d1, y + v) partners of the squared

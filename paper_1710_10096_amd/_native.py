@@ -28,7 +28,7 @@ class SffParams(ctypes.Structure):
 
 
 EXPORTS = ("sff_status_string", "sff_version", "sff_desc_channels", "sff_lanczos_q14", "sff_wht_workspace_bytes",
-           "sff_wht_features", "sff_init_workspace_bytes", "sff_init_nn", "sff_match_level",
+           "sff_wht_features", "sff_init_workspace_bytes", "sff_init_nn", "sff_init_nn_leaves", "sff_match_level",
            "sff_consistency", "sff_region_workspace_bytes", "sff_region_filter", "sff_sparsify",
            "sff_cost_f32_fwd", "sff_cost_f32_bwd_workspace_bytes",
            "sff_cost_f32_bwd", "sff_conv3x3_bf16_fwd", "sff_conv3x3_bf16_bwd_workspace_bytes",
@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
     L.sff_init_workspace_bytes.restype = ctypes.c_size_t
     L.sff_init_nn.argtypes = [PP, i32, i32, P, P, P, P, ctypes.c_size_t, P]
     L.sff_init_nn.restype = i32
+    L.sff_init_nn_leaves.argtypes = [PP, i32, i32, i32, P, P, P, P, ctypes.c_size_t, P]
+    L.sff_init_nn_leaves.restype = i32
     L.sff_match_level.argtypes = [PP, i32, i32, i32, P, P, P, P, P, P]
     L.sff_match_level.restype = i32
     L.sff_consistency.argtypes = [PP, i32, P, P, P, P, P]

@@ -129,8 +129,9 @@ def sff_init_workspace_bytes(p, batch: int) -> int:
 
 
 def sff_init_nn(p, desc: torch.Tensor, dir: int = DIR_BOTH, hyp=None, cost=None,
-                workspace: torch.Tensor | None = None, stream=None):
-    """desc int16 [batch][4][H][W][Cp][16] at the coarsest level -> (hyp, cost)."""
+                workspace: torch.Tensor | None = None, stream=None, leaves: int = 1):
+    """desc int16 [batch][4][H][W][Cp][16] at the coarsest level -> (hyp, cost).
+    ``leaves`` (1, 2, 4): temporal leaves whose combinations are compared."""
     pp = _params(p)
     _check_pair_desc(pp, desc)
     batch = desc.shape[0]
@@ -140,9 +141,10 @@ def sff_init_nn(p, desc: torch.Tensor, dir: int = DIR_BOTH, hyp=None, cost=None,
         workspace = torch.empty(sff_init_workspace_bytes(pp, batch), dtype=torch.uint8,
                                 device=desc.device)
     ws_bytes = workspace.numel() * workspace.element_size()
-    _check(lib().sff_init_nn(ctypes.byref(pp), batch, dir, _ptr(desc, torch.int16, "desc"),
-                             _ptr(hyp, torch.int16, "hyp"), _ptr(cost, torch.int32, "cost"),
-                             _ptr(workspace, None, "workspace"), ws_bytes, _stream(stream)),
+    _check(lib().sff_init_nn_leaves(ctypes.byref(pp), batch, dir, int(leaves),
+                                    _ptr(desc, torch.int16, "desc"), _ptr(hyp, torch.int16, "hyp"),
+                                    _ptr(cost, torch.int32, "cost"),
+                                    _ptr(workspace, None, "workspace"), ws_bytes, _stream(stream)),
            "sff_init_nn")
     return hyp, cost
 

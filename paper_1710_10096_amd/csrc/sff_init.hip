@@ -103,12 +103,20 @@ __device__ __forceinline__ v4i load16(const int8_t* p) {
 // with the same K bytes for lane group l / 16, so each product sums over all 64
 // K values.  Lane l receives C[4 (l / 16) + e][l % 16], e = 0..3: candidates
 // 4 g + e of the tile against its own query.
-template <int C>
+//
+// K > 1 (initialisation with K temporal leaves): each lane keeps its K best
+// (key, target index) per query, sorted (a candidate enters after kept ones of
+// equal key, which have smaller indices); the lists are merged per query in
+// LDS, each leaf gets its own cross-row search, and the combination with the
+// smallest T + S + X distance wins (the earlier leaf on ties).
+template <int C, int K>
 __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P) {
-    __shared__ unsigned long long red[kWaves * 4][kQRows][16];
-    __shared__ int res_u[kQRows][16], res_v[kQRows][16];
-    __shared__ uint32_t res_t[kQRows][16];
+    __shared__ unsigned long long red[kWaves * 4][kQRows][16][K];
+    __shared__ int res_u[kQRows][16][K], res_v[kQRows][16][K];
+    __shared__ uint32_t res_t[kQRows][16][K];
+    __shared__ int res_n[kQRows][16];
     __shared__ unsigned long long red2[4][kQRows][16];
+    __shared__ unsigned long long redx[K][4][kQRows][16];
     const int lane = threadIdx.x & 63, w = wave_id();
     const int nq = lane & 15, g = lane >> 4;
     const int j0 = blockIdx.x * 16, i0 = blockIdx.y * kQRows;
@@ -127,7 +135,8 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
 
     // queries (B operands, negated), one 16-column tile per query row
     v4i qh[kQRows], ql[kQRows];
-    int best[kQRows], btile[kQRows];
+    int best[kQRows], btile[kQRows];   // K = 1: minimum key and its first tile
+    int tk[kQRows][K], ti[kQRows][K];  // K > 1: sorted keys and target indices
     const int jq = min(j0 + nq, Wk - 1);
 #pragma unroll
     for (int t = 0; t < kQRows; ++t) {
@@ -136,6 +145,11 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
         ql[t] = load16(P.nlo + o * kKBytes + 16 * g);
         best[t] = INT_MAX;
         btile[t] = 0;
+#pragma unroll
+        for (int l = 0; l < K; ++l) {
+            tk[t][l] = INT_MAX;
+            ti[t][l] = 0;
+        }
     }
     // Scan: per query only the minimum key over this lane's candidates and the
     // first tile (in increasing target index) that reaches it are kept; the
@@ -218,10 +232,27 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
                     k[e] = (int)key;
                     if constexpr (!kInterior) k[e] = ok[e] ? k[e] : INT_MAX;
                 }
-                const int m = min(min(k[0], k[1]), min(k[2], k[3]));
-                const bool better = m < best[t];
-                btile[t] = better ? tile_id : btile[t];
-                best[t] = better ? m : best[t];
+                if constexpr (K == 1) {
+                    const int m = min(min(k[0], k[1]), min(k[2], k[3]));
+                    const bool better = m < best[t];
+                    btile[t] = better ? tile_id : btile[t];
+                    best[t] = better ? m : best[t];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (!__any(k[e] < tk[t][K - 1])) continue;  // wave-uniform
+                        int nk = k[e], ni = r * Wk + c0 + 4 * g + e;
+#pragma unroll
+                        for (int l = 0; l < K; ++l) {
+                            const bool lt = nk < tk[t][l];
+                            const int ok_ = tk[t][l], oi = ti[t][l];
+                            tk[t][l] = lt ? nk : ok_;
+                            ti[t][l] = lt ? ni : oi;
+                            nk = lt ? ok_ : nk;
+                            ni = lt ? oi : ni;
+                        }
+                    }
+                }
             }
         };
         const bool interior = c0 >= 0 && c0 + 15 < Wk && c0 >= j0 + 15 - F && c0 + 15 <= j0 + F;
@@ -247,6 +278,16 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
     const int16_t* Rm = base + (size_t)vR * mapsz;
 #pragma unroll 1
     for (int t = 0; t < kQRows; ++t) {
+        if constexpr (K > 1) {
+            const uint32_t asq = P.sq[zR + (size_t)min(i0 + t, Hk - 1) * Wk + jq];
+#pragma unroll
+            for (int l = 0; l < K; ++l)
+                red[w * 4 + g][t][nq][l] =
+                    tk[t][l] == INT_MAX
+                        ? ~0ull
+                        : ((unsigned long long)((uint32_t)tk[t][l] + asq) << 32) | (uint32_t)ti[t][l];
+            continue;
+        }
         uint32_t bssd = 0xFFFFFFFFu, bidx = 0;
         if (best[t] != INT_MAX) {
             const int r = btile[t] >> 16, c0 = j0 - F + 16 * (btile[t] & 0xFFFF);
@@ -267,20 +308,34 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
                 }
             }
         }
-        red[w * 4 + g][t][nq] = ((unsigned long long)bssd << 32) | bidx;
+        red[w * 4 + g][t][nq][0] = ((unsigned long long)bssd << 32) | bidx;
     }
     __syncthreads();
-    // combine the 16 partial minima (waves x lane groups) of each query
+    // combine the 16 partial lists (waves x lane groups) of each query: the K
+    // smallest (ssd, index) keys, by K selection passes (indices are distinct)
     if (threadIdx.x < kQRows * 16) {
         const int t = threadIdx.x >> 4, q = threadIdx.x & 15;
-        unsigned long long m = red[0][t][q];
+        unsigned long long prev = 0;
+        int nl = 0;
+#pragma unroll 1
+        for (int l = 0; l < K; ++l) {
+            unsigned long long m = ~0ull;
+            for (int k = 0; k < kWaves * 4; ++k)
 #pragma unroll
-        for (int k = 1; k < kWaves * 4; ++k) m = red[k][t][q] < m ? red[k][t][q] : m;
-        const uint32_t idx = (uint32_t)m;
-        const int ri = (int)(idx / (uint32_t)Wk), rj = (int)(idx % (uint32_t)Wk);
-        res_v[t][q] = n * (ri - (i0 + t));
-        res_u[t][q] = n * (rj - min(j0 + q, Wk - 1));
-        res_t[t][q] = (uint32_t)(m >> 32);
+                for (int e = 0; e < K; ++e) {
+                    const unsigned long long v = red[k][t][q][e];
+                    if ((l == 0 || v > prev) && v < m) m = v;
+                }
+            if (m == ~0ull) break;
+            const uint32_t idx = (uint32_t)m;
+            const int ri = (int)(idx / (uint32_t)Wk), rj = (int)(idx % (uint32_t)Wk);
+            res_v[t][q][l] = n * (ri - (i0 + t));
+            res_u[t][q][l] = n * (rj - min(j0 + q, Wk - 1));
+            res_t[t][q][l] = (uint32_t)(m >> 32);
+            prev = m;
+            nl = l + 1;
+        }
+        res_n[t][q] = nl;
     }
     __syncthreads();
 
@@ -309,34 +364,59 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
 #pragma unroll
     for (int k = 1; k < 4; ++k) mS = red2[k][t][q] < mS ? red2[k][t][q] : mS;
     __syncthreads();
-    // cross partner on row y + v*: target tx = x + u* - s d1, increasing tx
-    const int bu = live ? res_u[t][q] : 0, bv = live ? res_v[t][q] : 0;
-    unsigned long long kX = ~0ull;
-    if (live) {
-        const int xc = x + bu, yc = y + bv;
-        const int txlo = s > 0 ? xc - min(a.dm, xc) : xc;
-        const int txhi = s > 0 ? xc : xc + min(a.dm, ((W - 1 - xc) / n) * n);
-        for (int tx = txlo + n * part; tx <= txhi; tx += 4 * n) {
-            const uint32_t e = desc_ssd<C>(qd, load_desc<C>(Xm, (size_t)yc * W + tx));
-            const unsigned long long k = ((unsigned long long)e << 32) | (uint32_t)tx;
-            kX = k < kX ? k : kX;
+    // cross partner of each temporal leaf on row y + v: target tx = x + u - s d1,
+    // increasing tx
+    const int nl = live ? res_n[t][q] : 0;
+#pragma unroll 1
+    for (int l = 0; l < K; ++l) {
+        unsigned long long kX = ~0ull;
+        if (l < nl) {
+            const int xc = x + res_u[t][q][l], yc = y + res_v[t][q][l];
+            const int txlo = s > 0 ? xc - min(a.dm, xc) : xc;
+            const int txhi = s > 0 ? xc : xc + min(a.dm, ((W - 1 - xc) / n) * n);
+            for (int tx = txlo + n * part; tx <= txhi; tx += 4 * n) {
+                const uint32_t e = desc_ssd<C>(qd, load_desc<C>(Xm, (size_t)yc * W + tx));
+                const unsigned long long k = ((unsigned long long)e << 32) | (uint32_t)tx;
+                kX = k < kX ? k : kX;
+            }
         }
+        redx[l][part][t][q] = kX;
     }
-    red2[part][t][q] = kX;
     __syncthreads();
     if (part != 0 || !live) return;
-    unsigned long long mX = red2[0][t][q];
+    // the cheapest combination (every target lies inside the image, so its
+    // eq. (1) cost is the sum of the three distances); the earlier leaf on ties
+    const uint32_t eS = (uint32_t)(mS >> 32);
+    uint64_t bestJ = ~0ull;
+    int bu = 0, bv = 0, bd1 = 0;
+    for (int l = 0; l < nl; ++l) {
+        unsigned long long mX = redx[l][0][t][q];
 #pragma unroll
-    for (int k = 1; k < 4; ++k) mX = red2[k][t][q] < mX ? red2[k][t][q] : mX;
+        for (int k = 1; k < 4; ++k) mX = redx[l][k][t][q] < mX ? redx[l][k][t][q] : mX;
+        const uint64_t joint = (uint64_t)res_t[t][q][l] + eS + (uint32_t)(mX >> 32);
+        if (joint < bestJ) {
+            bestJ = joint;
+            bu = res_u[t][q][l];
+            bv = res_v[t][q][l];
+            bd1 = s * (x + bu - (int)(uint32_t)mX);
+        }
+    }
     const int bd0 = s * (x - (int)(uint32_t)mS);
-    const int bd1 = s * (x + bu - (int)(uint32_t)mX);
     const size_t o = ((size_t)z * Hk + iq) * Wk + jqq;
     uint2 hv;
     hv.x = (uint32_t)(uint16_t)(int16_t)bu | ((uint32_t)(uint16_t)(int16_t)bv << 16);
     hv.y = (uint32_t)(uint16_t)(int16_t)bd0 | ((uint32_t)(uint16_t)(int16_t)bd1 << 16);
     reinterpret_cast<uint2*>(a.hyp)[o] = hv;
-    // all three targets lie inside the image, so no clamping enters the cost
-    a.cost[o] = res_t[t][q] + (uint32_t)(mS >> 32) + (uint32_t)(mX >> 32);
+    a.cost[o] = (uint32_t)bestJ;
+}
+
+template <int C>
+void launch_init(int leaves, dim3 grid, hipStream_t st, const InitArgs& a, const SplitPlanes& P) {
+    switch (leaves) {
+        case 1: hipLaunchKernelGGL((init_nn_kernel<C, 1>), grid, dim3(256), 0, st, a, P); break;
+        case 2: hipLaunchKernelGGL((init_nn_kernel<C, 2>), grid, dim3(256), 0, st, a, P); break;
+        default: hipLaunchKernelGGL((init_nn_kernel<C, 4>), grid, dim3(256), 0, st, a, P); break;
+    }
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -368,12 +448,14 @@ extern "C" size_t sff_init_workspace_bytes(const sff_params* p, int32_t batch) {
     return init_ws(*p, batch).total;
 }
 
-extern "C" sff_status sff_init_nn(const sff_params* p, int32_t batch, int32_t dir,
-                                  const int16_t* desc, int16_t* hyp, uint32_t* cost,
-                                  void* workspace, size_t workspace_bytes, void* stream) {
+extern "C" sff_status sff_init_nn_leaves(const sff_params* p, int32_t batch, int32_t dir,
+                                         int32_t leaves, const int16_t* desc, int16_t* hyp,
+                                         uint32_t* cost, void* workspace, size_t workspace_bytes,
+                                         void* stream) {
     if (!params_ok(p) || batch < 1 || batch > 32767 || (dir != 1 && dir != -1 && dir != 0) ||
-        !desc || !hyp || !cost)
+        !desc || !hyp || !cost || leaves < 1)
         return SFF_ERR_INVALID_ARG;
+    if (leaves != 1 && leaves != 2 && leaves != 4) return SFF_ERR_UNSUPPORTED;
     if ((reinterpret_cast<uintptr_t>(desc) & 15) != 0 || (reinterpret_cast<uintptr_t>(hyp) & 7) != 0 ||
         (reinterpret_cast<uintptr_t>(cost) & 3) != 0)
         return SFF_ERR_INVALID_ARG;
@@ -410,20 +492,26 @@ extern "C" sff_status sff_init_nn(const sff_params* p, int32_t batch, int32_t di
     switch (p->C) {
         case 1:
             hipLaunchKernelGGL(split_kernel<1>, sgrid, dim3(256), 0, st, desc, P, a.H, a.W, a.n, a.Hk, a.Wk, nz4);
-            hipLaunchKernelGGL(init_nn_kernel<1>, grid, dim3(256), 0, st, a, P);
+            launch_init<1>(leaves, grid, st, a, P);
             break;
         case 2:
             hipLaunchKernelGGL(split_kernel<2>, sgrid, dim3(256), 0, st, desc, P, a.H, a.W, a.n, a.Hk, a.Wk, nz4);
-            hipLaunchKernelGGL(init_nn_kernel<2>, grid, dim3(256), 0, st, a, P);
+            launch_init<2>(leaves, grid, st, a, P);
             break;
         case 3:
             hipLaunchKernelGGL(split_kernel<3>, sgrid, dim3(256), 0, st, desc, P, a.H, a.W, a.n, a.Hk, a.Wk, nz4);
-            hipLaunchKernelGGL(init_nn_kernel<3>, grid, dim3(256), 0, st, a, P);
+            launch_init<3>(leaves, grid, st, a, P);
             break;
         default:
             hipLaunchKernelGGL(split_kernel<4>, sgrid, dim3(256), 0, st, desc, P, a.H, a.W, a.n, a.Hk, a.Wk, nz4);
-            hipLaunchKernelGGL(init_nn_kernel<4>, grid, dim3(256), 0, st, a, P);
+            launch_init<4>(leaves, grid, st, a, P);
             break;
     }
     return launch_status();
+}
+
+extern "C" sff_status sff_init_nn(const sff_params* p, int32_t batch, int32_t dir,
+                                  const int16_t* desc, int16_t* hyp, uint32_t* cost,
+                                  void* workspace, size_t workspace_bytes, void* stream) {
+    return sff_init_nn_leaves(p, batch, dir, 1, desc, hyp, cost, workspace, workspace_bytes, stream);
 }

@@ -19,7 +19,7 @@ from ._native import SffParams
 
 class PairMatcher:
     def __init__(self, params, batch: int = 1, device: str | torch.device = "cuda",
-                 s_c: int | None = None):
+                 s_c: int | None = None, leaves: int = 1):
         self.p = params if isinstance(params, SffParams) else SffParams.from_dict(params)
         self.batch = int(batch)
         p, B = self.p, self.batch
@@ -37,6 +37,7 @@ class PairMatcher:
         self.valid = torch.empty((B, p.H, p.W), dtype=torch.uint8, device=dev)
         self.err = torch.empty((B, p.H, p.W), dtype=torch.int32, device=dev)
         self.s_c = s_c
+        self.leaves = int(leaves)
         if s_c is not None:
             self.keep = torch.empty((B, p.H, p.W), dtype=torch.uint8, device=dev)
             self.seeds = torch.empty((B, (p.H + 2) // 3, (p.W + 2) // 3), dtype=torch.int32,
@@ -61,7 +62,7 @@ class PairMatcher:
             mk(f"features:L{k}")
             if k == top:
                 api.sff_init_nn(p, self.desc, api.DIR_BOTH, self.hyp[k], self.cost[k], self.ws,
-                                stream)
+                                stream, leaves=self.leaves)
                 mk(f"init:L{k}")
                 api.sff_match_level(p, self.desc, api.DIR_BOTH, k, seeds, self.hyp[k],
                                     self.cost[k], None, stream)

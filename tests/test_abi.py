@@ -112,6 +112,11 @@ def test_invalid_arguments_rejected():
     assert L.sff_match_level(P, 1, 0, 1, f, f, None, f, f, None) == 1      # level >= levels
     assert L.sff_match_level(P, 1, 0, 0, f, f, f, f, f, None) == 1         # hand-off at top
     assert L.sff_wht_features(P, 1, 1, f, f, None, 0, None) == 1          # level >= levels
+    # temporal leaves: 1, 2 or 4
+    need_i = L.sff_init_workspace_bytes(P, 1)
+    assert L.sff_init_nn_leaves(P, 1, 0, 0, f, f, f, f, need_i, None) == 1
+    assert L.sff_init_nn_leaves(P, 1, 0, 3, f, f, f, f, need_i, None) == 2
+    assert L.sff_init_nn_leaves(P, 1, 0, 8, f, f, f, f, need_i, None) == 2
     # misaligned descriptor pointer
     assert L.sff_init_nn(P, 1, 0, ctypes.c_void_p(0x1002), f, f, f, 1 << 30, None) == 1
     # init workspace missing, too small or misaligned

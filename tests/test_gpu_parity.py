@@ -97,8 +97,9 @@ INIT_CASES = [
 ]
 
 
+@pytest.mark.parametrize("leaves", [1, 2, 4])
 @pytest.mark.parametrize("case", INIT_CASES, ids=[c[0] for c in INIT_CASES])
-def test_init_nn_parity(sff, case):
+def test_init_nn_parity(sff, case, leaves):
     name, H, W, C, levels, fmax, dmax, seed = case
     sc = make_scene(small_spec(H, W, C, seed, flow_max=min(fmax, 10), d_range=(0, min(dmax, 10))))
     p = params_dict(H, W, C, levels=levels, iters=1, fmax=fmax, dmax=dmax)
@@ -106,16 +107,16 @@ def test_init_nn_parity(sff, case):
     imgs = sc.stack()
     desc = sff.sff_wht_features(p, dev(imgs), top).view(1, 4, H, W, sff.desc_channels(C), 16)
     D = _oracle_descs(imgs, top)
-    _say("init", name, "both directions")
-    hyp, cost = sff.sff_init_nn(p, desc, sff.DIR_BOTH)
+    _say("init", name, "leaves", leaves, "both directions")
+    hyp, cost = sff.sff_init_nn(p, desc, sff.DIR_BOTH, leaves=leaves)
     h, c = host(hyp), host(cost, u32=True)
     for di, s in enumerate((1, -1)):
-        oh, oc = oracle.init_nn(D, top, s, fmax, dmax)
+        oh, oc = oracle.init_nn(D, top, s, fmax, dmax, leaves=leaves)
         assert np.array_equal(h[di, 0], oh), (name, s)
         assert np.array_equal(c[di, 0], oc), (name, s)
-    _say("init", name, "single directions")
+    _say("init", name, "leaves", leaves, "single directions")
     for s in (1, -1):
-        hyp1, cost1 = sff.sff_init_nn(p, desc, s)
+        hyp1, cost1 = sff.sff_init_nn(p, desc, s, leaves=leaves)
         assert np.array_equal(host(hyp1)[0, 0], h[0 if s > 0 else 1, 0])
         assert np.array_equal(host(cost1, u32=True)[0, 0], c[0 if s > 0 else 1, 0])
 
@@ -307,3 +308,18 @@ def test_pipeline_kitti_batch16(sff):
     scenes = [make_scene(s) for s in specs]
     _say("pipeline kitti batch 16")
     _check_pipeline(sff, scenes, kitti_params(), [s.seed for s in specs])
+
+
+def test_pipeline_kitti_leaves4(sff):
+    """The whole stage with four temporal leaves at the KITTI size."""
+    import torch
+    sc = make_scene(kitti_spec())
+    p = kitti_params()
+    _say("pipeline kitti leaves 4")
+    out = sff.PairMatcher(p, 1, leaves=4).run(dev(sc.stack()[None]), dev(np.array([2], np.int64)))
+    torch.cuda.synchronize()
+    ref = oracle.match_pair(sc.stack(), p, 2, leaves=4)
+    assert np.array_equal(host(out["hyp"])[:, 0], ref["hyp"])
+    assert np.array_equal(host(out["cost"], u32=True)[:, 0], ref["cost"])
+    assert np.array_equal(host(out["valid"])[0], ref["valid"])
+
