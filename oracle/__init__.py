@@ -20,6 +20,9 @@ Each wrapper names the passage its C function follows:
 * ``region_filter`` -- region filter, Section 3.1 (second step of the
   consistency check) and s_c of Section 5.
 * ``sparsify`` -- best match per 3x3 block, Section 3.2 "Sparsification".
+* ``grey``, ``census``, ``sgm_cost``, ``sgm_path``, ``sgm``,
+  ``disparity_fill`` -- the disparity fill by semi-global matching, Section 3.1
+  (last paragraph of "Consistency Check").
 * ``match_pair`` -- the whole stage for one pair, Section 3 overview
   (``schedule="scan"``: the paper's sequential four-corner propagation,
   ``match_level_scan``, CPU only, to measure the red-black schedule).
@@ -56,6 +59,12 @@ def lib():
         L.orc_match_level.argtypes = ([P, P, P, P] + [i32] * 5 + [ctypes.c_uint64]
                                       + [i32] * 5 + [P, i32, i32, P, P])
         L.orc_consistency.argtypes = [P, P, i32, i32, i32, P, P]
+        L.orc_grey.argtypes = [P, i32, i32, i32, P]
+        L.orc_census.argtypes = [P, i32, i32, P]
+        L.orc_sgm_cost.argtypes = [P, P, i32, i32, i32, P]
+        L.orc_sgm_path.argtypes = [P, i32, i32, i32, i32, i32, i32, i32, P]
+        L.orc_sgm.argtypes = [P, P, i32, i32, i32, i32, i32, i32, P]
+        L.orc_disparity_fill.argtypes = [P, P, P, i32, i32, i32, P]
         L.orc_region_filter.argtypes = [P, P, i32, i32, i32, i32, P]
         L.orc_sparsify.argtypes = [P, P, i32, i32, P]
         L.orc_match_pair.argtypes = ([P] + [i32] * 10 + [ctypes.c_uint64, i32] + [P] * 4)
@@ -195,6 +204,62 @@ def consistency(hyp_fwd, hyp_inv, tau: int):
     err = np.zeros((H, W), np.uint32)
     assert lib().orc_consistency(_p(hf), _p(hi), H, W, tau, _p(valid), _p(err)) == 0
     return valid, err
+
+
+def grey(img):
+    """Rounded channel mean, uint8 [H][W] (disparity fill reading)."""
+    im = _c(img, np.uint8)
+    H, W, C = im.shape
+    out = np.zeros((H, W), np.uint8)
+    assert lib().orc_grey(_p(im), H, W, C, _p(out)) == 0
+    return out
+
+
+def census(grey_img):
+    """5x5 census words uint32 [H][W]."""
+    g = _c(grey_img, np.uint8)
+    H, W = g.shape
+    out = np.zeros((H, W), np.uint32)
+    assert lib().orc_census(_p(g), H, W, _p(out)) == 0
+    return out
+
+
+def sgm_cost(cl, cr, D: int):
+    """Hamming cost volume uint8 [H][W][D]."""
+    a, b = _c(cl, np.uint32), _c(cr, np.uint32)
+    H, W = a.shape
+    out = np.zeros((H, W, D), np.uint8)
+    assert lib().orc_sgm_cost(_p(a), _p(b), H, W, D, _p(out)) == 0
+    return out
+
+
+def sgm_path(cost, P1: int, P2: int, dx: int, dy: int):
+    """Aggregated cost int32 [H][W][D] along one path direction."""
+    c = _c(cost, np.uint8)
+    H, W, D = c.shape
+    out = np.zeros((H, W, D), np.int32)
+    assert lib().orc_sgm_path(_p(c), H, W, D, P1, P2, dx, dy, _p(out)) == 0
+    return out
+
+
+def sgm(left, right, D: int, P1: int, P2: int):
+    """SGM disparity int16 [H][W] of a rectified pair (Section 3.1, last
+    paragraph of "Consistency Check"; Hirschmueller 2008)."""
+    l, r = _c(left, np.uint8), _c(right, np.uint8)
+    H, W, C = l.shape
+    out = np.zeros((H, W), np.int16)
+    assert lib().orc_sgm(_p(l), _p(r), H, W, C, D, P1, P2, _p(out)) == 0
+    return out
+
+
+def disparity_fill(hyp_fwd, valid, disp, tau: int):
+    """1 where the joint check kept the match or its d0 agrees with the SGM
+    disparity within tau."""
+    hf, va, dp = _c(hyp_fwd, np.int16), _c(valid, np.uint8), _c(disp, np.int16)
+    H, W, _ = hf.shape
+    out = np.zeros((H, W), np.uint8)
+    assert lib().orc_disparity_fill(_p(hf), _p(va), _p(dp), H, W, tau, _p(out)) == 0
+    return out
 
 
 def region_filter(hyp_fwd, valid, tau: int, s_c: int):

@@ -752,6 +752,150 @@ int orc_sparsify(const uint8_t* keep, const uint32_t* err, int H, int W, int32_t
 }
 
 /* ------------------------------------------------------------------------- */
+/* Disparity fill (Section 3.1, "Consistency Check", last paragraph): a second */
+/* disparity map by semi-global matching (Hirschmueller, TPAMI 2008) and a    */
+/* check of the disparity matches alone against it with the same tau.        */
+/* Readings (the paper only cites SGM): grey = rounded mean of the channels;  */
+/* 5 x 5 census (bit k set when neighbour k, row-major without the centre, is */
+/* darker than the centre; replicated border); matching cost = Hamming        */
+/* distance of the census words of (x, y) in the left and (x - d, y) in the   */
+/* right image, x - d clamped to the image, d = 0..D-1; aggregation along 8   */
+/* paths with penalties P1 (|change| = 1) and P2 (larger changes); the        */
+/* disparity minimises the summed path costs, ties to the smaller d.          */
+/* ------------------------------------------------------------------------- */
+static uint32_t census5(const uint8_t* g, int H, int W, int x, int y) {
+    const int c = g[(size_t)y * W + x];
+    uint32_t w = 0;
+    int k = 0;
+    for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            const int v = g[(size_t)clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1)];
+            if (v < c) w |= 1u << k;
+            ++k;
+        }
+    return w;
+}
+
+static int popcount32(uint32_t v) {
+    int n = 0;
+    while (v) { v &= v - 1; ++n; }
+    return n;
+}
+
+/* grey: uint8 [H][W] from an image [H][W][C]. */
+int orc_grey(const uint8_t* img, int H, int W, int C, uint8_t* grey) {
+    for (size_t p = 0; p < (size_t)H * W; ++p) {
+        int sum = 0;
+        for (int c = 0; c < C; ++c) sum += img[p * C + c];
+        grey[p] = (uint8_t)((sum + C / 2) / C);
+    }
+    return ORC_OK;
+}
+
+/* census: uint32 [H][W] of a grey image. */
+int orc_census(const uint8_t* grey, int H, int W, uint32_t* out) {
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) out[(size_t)y * W + x] = census5(grey, H, W, x, y);
+    return ORC_OK;
+}
+
+/* cost: uint8 [H][W][D], Hamming distance of the census words. */
+int orc_sgm_cost(const uint32_t* cl, const uint32_t* cr, int H, int W, int D, uint8_t* cost) {
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int d = 0; d < D; ++d)
+                cost[((size_t)y * W + x) * D + d] =
+                    (uint8_t)popcount32(cl[(size_t)y * W + x] ^ cr[(size_t)y * W + clampi(x - d, 0, W - 1)]);
+    return ORC_OK;
+}
+
+/* Aggregated cost along one path direction (dx, dy) (each in -1..1, not both
+ * 0): L(p, d) = C(p, d) + min(L(q, d), L(q, d - 1) + P1, L(q, d + 1) + P1,
+ * min_k L(q, k) + P2) - min_k L(q, k) with q = p - (dx, dy); L(p, d) = C(p, d)
+ * where q lies outside the image.  L: int32 [H][W][D]. */
+int orc_sgm_path(const uint8_t* cost, int H, int W, int D, int P1, int P2, int dx, int dy,
+                 int32_t* L) {
+    /* visit pixels so that q = p - (dx, dy) is always done before p */
+    for (int yy = 0; yy < H; ++yy) {
+        const int y = dy >= 0 ? yy : H - 1 - yy;
+        for (int xx = 0; xx < W; ++xx) {
+            const int x = dx >= 0 ? xx : W - 1 - xx;
+            const uint8_t* c = cost + ((size_t)y * W + x) * D;
+            int32_t* l = L + ((size_t)y * W + x) * D;
+            const int qx = x - dx, qy = y - dy;
+            if (qx < 0 || qx >= W || qy < 0 || qy >= H) {
+                for (int d = 0; d < D; ++d) l[d] = c[d];
+                continue;
+            }
+            const int32_t* lq = L + ((size_t)qy * W + qx) * D;
+            int32_t m = lq[0];
+            for (int d = 1; d < D; ++d) m = lq[d] < m ? lq[d] : m;
+            for (int d = 0; d < D; ++d) {
+                int32_t best = lq[d];
+                if (d > 0 && lq[d - 1] + P1 < best) best = lq[d - 1] + P1;
+                if (d + 1 < D && lq[d + 1] + P1 < best) best = lq[d + 1] + P1;
+                if (m + P2 < best) best = m + P2;
+                l[d] = c[d] + best - m;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* SGM disparity of a rectified pair (left, right images [H][W][C]): disp
+ * int16 [H][W] in 0..D-1. */
+int orc_sgm(const uint8_t* left, const uint8_t* right, int H, int W, int C, int D, int P1, int P2,
+            int16_t* disp) {
+    const size_t npx = (size_t)H * W;
+    uint8_t* gl = (uint8_t*)malloc(npx);
+    uint8_t* gr = (uint8_t*)malloc(npx);
+    uint32_t* cl = (uint32_t*)malloc(sizeof(uint32_t) * npx);
+    uint32_t* cr = (uint32_t*)malloc(sizeof(uint32_t) * npx);
+    uint8_t* cost = (uint8_t*)malloc(npx * D);
+    int32_t* L = (int32_t*)malloc(sizeof(int32_t) * npx * D);
+    int32_t* S = (int32_t*)calloc(npx * D, sizeof(int32_t));
+    int rc = ORC_ERR;
+    if (gl && gr && cl && cr && cost && L && S) {
+        orc_grey(left, H, W, C, gl);
+        orc_grey(right, H, W, C, gr);
+        orc_census(gl, H, W, cl);
+        orc_census(gr, H, W, cr);
+        orc_sgm_cost(cl, cr, H, W, D, cost);
+        static const int DIRS[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1},
+                                       {1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
+        for (int r = 0; r < 8; ++r) {
+            orc_sgm_path(cost, H, W, D, P1, P2, DIRS[r][0], DIRS[r][1], L);
+            for (size_t k = 0; k < npx * D; ++k) S[k] += L[k];
+        }
+        for (size_t p = 0; p < npx; ++p) {
+            int best = 0;
+            for (int d = 1; d < D; ++d)
+                if (S[p * D + d] < S[p * D + best]) best = d;
+            disp[p] = (int16_t)best;
+        }
+        rc = ORC_OK;
+    }
+    free(gl); free(gr); free(cl); free(cr); free(cost); free(L); free(S);
+    return rc;
+}
+
+/* Disparity fill: fill[p] = 1 where the joint check kept the match, or where
+ * it removed it but the match's own disparity d0 lies inside the image target
+ * and within tau of the SGM disparity.  hyp: forward field [H][W][4]. */
+int orc_disparity_fill(const int16_t* hyp, const uint8_t* valid, const int16_t* disp, int H,
+                       int W, int tau, uint8_t* fill) {
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const size_t p = (size_t)y * W + x;
+            const int d0 = hyp[p * 4 + 2];
+            const int e = d0 - disp[p];
+            fill[p] = (valid[p] || (x - d0 >= 0 && e <= tau && e >= -tau)) ? 1 : 0;
+        }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Whole stage for one pair (Section 3 overview up to the consistency check): */
 /* descriptors of the four images at every level, then for the forward        */
 /* (s = +1) and inverse (s = -1) fields: exact-NN initialisation at the       */
