@@ -150,6 +150,32 @@ def region_stage(p, B, m, steps: int) -> dict:
             "seeds": int((seeds >= 0).sum().item())}
 
 
+def fill_stage(m, imgs, steps: int) -> dict:
+    """SGM disparity of the stereo pair at t0 and the disparity-only check of
+    the last step's matches (after the headline step, timed separately)."""
+    import torch
+    st = torch.cuda.current_stream()
+    m.disparity_fill(imgs)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_s = t_f = 0.0
+    for _ in range(steps):
+        marks = []
+
+        def mark(name):
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(st)
+            marks.append(e)
+
+        ev[0].record(st)
+        m.disparity_fill(imgs, mark=mark)
+        marks[-1].synchronize()
+        t_s += ev[0].elapsed_time(marks[0])
+        t_f += marks[0].elapsed_time(marks[1])
+    return {"sgm_ms": t_s / steps, "fill_ms": t_f / steps,
+            "consistent": int(m.valid.sum().item()), "filled": int(m.fill.sum().item())}
+
+
 def with_upload(m, imgs, seeds, steps: int) -> dict:
     """The same step preceded by the upload of the batch's images from pinned
     host memory (PCIe-inclusive rate; the library itself takes device
@@ -307,6 +333,7 @@ def main():
     }
     out["with_upload"] = with_upload(m, imgs, seeds_t, args.steps)
     out["region_sparsify"] = region_stage(p, B, m, args.steps)
+    out["disparity_fill"] = fill_stage(m, imgs, args.steps)
     if not args.no_probes:
         out["probes"] = probes()
     if not args.no_cpu_baseline:

@@ -221,6 +221,43 @@ sff_status sff_region_filter(const sff_params* p, int32_t batch, int32_t s_c,
 sff_status sff_sparsify(const sff_params* p, int32_t batch, const uint8_t* keep,
                         const uint32_t* err, int32_t* seeds, void* stream);
 
+/* Device workspace (bytes) that sff_sgm_disparity needs for `batch` pairs
+ * (about 10 + 1024 / W + 8 (dmax + 1) bytes per pixel); 0 for invalid
+ * arguments. */
+size_t sff_sgm_workspace_bytes(const sff_params* p, int32_t batch);
+
+/* Disparity by semi-global matching (Hirschmueller, TPAMI 2008), the second
+ * disparity map of the disparity fill (Section 3.1, last paragraph of
+ * "Consistency Check").  Grey = rounded channel mean; cost = Hamming distance
+ * of 5 x 5 census words (bit k: neighbour k, row-major without the centre,
+ * darker than the centre; replicated border) of left pixel x and right pixel
+ * x - d (clamped), d = 0..dmax; aggregation along 8 paths with penalties P1
+ * (disparity change 1) and P2 (larger changes); disparity = argmin over d of
+ * the summed path costs, the smallest d on ties.
+ * left, right: image pairs [H][W][C] uint8, pair b at byte offset
+ *   b * pair_stride of each pointer (pair_stride >= H W C when batch > 1).
+ * disp: [batch][H][W] int16, written.  P1 >= 0, P1 <= P2 <= 231 (path costs
+ *   are stored in 8 bits).
+ * workspace: at least sff_sgm_workspace_bytes(p, batch) bytes, 256-byte
+ *   aligned; contents on entry are ignored.
+ * Errors: SFF_ERR_INVALID_ARG, SFF_ERR_UNSUPPORTED (dmax + 1 > 256),
+ *   SFF_ERR_WORKSPACE. */
+sff_status sff_sgm_disparity(const sff_params* p, int32_t batch, const uint8_t* left,
+                             const uint8_t* right, size_t pair_stride, int32_t P1, int32_t P2,
+                             int16_t* disp, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Disparity fill (Section 3.1, last paragraph of "Consistency Check"):
+ * fill = 1 where the joint check kept the match (valid), or where it removed
+ * it but the match's disparity d0 keeps the stereo target in the image
+ * (x - d0 >= 0) and |d0 - disp| <= p->tau (the check of the disparity match
+ * alone against the SGM map).
+ * hyp_fwd: level-0 forward field [batch][H][W][4]; valid: [batch][H][W] uint8;
+ * disp: [batch][H][W] int16 (sff_sgm_disparity); fill: [batch][H][W] uint8.
+ * Errors: SFF_ERR_INVALID_ARG. */
+sff_status sff_disparity_fill(const sff_params* p, int32_t batch, const int16_t* hyp_fwd,
+                              const uint8_t* valid, const int16_t* disp, uint8_t* fill,
+                              void* stream);
+
 /* ---------------------------------------------------------------------------
  * Window form of the matching cost on real-valued feature maps (eq. (1),
  * Section 3.1: feature distances summed over a window around the pixel for the

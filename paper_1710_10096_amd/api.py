@@ -237,6 +237,61 @@ def sff_sparsify(p, keep: torch.Tensor, err: torch.Tensor, seeds=None, stream=No
     return seeds
 
 
+SGM_P1, SGM_P2 = 3, 24  # census 5x5 (costs 0..24)
+
+
+def sff_sgm_workspace_bytes(p, batch: int) -> int:
+    pp = _params(p)
+    return int(lib().sff_sgm_workspace_bytes(ctypes.byref(pp), batch))
+
+
+def sff_sgm_disparity(p, left: torch.Tensor, right: torch.Tensor, P1: int = SGM_P1,
+                      P2: int = SGM_P2, disp=None, workspace=None, stream=None) -> torch.Tensor:
+    """SGM disparity of rectified pairs: left/right uint8 views [batch][H][W][C]
+    (may be strided along the batch, e.g. imgs[:, 0] and imgs[:, 2] of a
+    [batch][4][H][W][C] tensor) -> int16 [batch][H][W] in 0..dmax."""
+    pp = _params(p)
+    batch = left.shape[0]
+    for t, nm in ((left, "left"), (right, "right")):
+        _check_shape(t, (batch, pp.H, pp.W, pp.C), nm)
+        if not t.is_cuda or t.dtype != torch.uint8 or not t[0].is_contiguous():
+            raise ValueError(f"{nm} must be GPU uint8 with contiguous images")
+    if left.stride(0) != right.stride(0):
+        raise ValueError("left and right must have the same batch stride")
+    if disp is None:
+        disp = torch.empty((batch, pp.H, pp.W), dtype=torch.int16, device=left.device)
+    _check_shape(disp, (batch, pp.H, pp.W), "disp")
+    if workspace is None:
+        workspace = torch.empty(sff_sgm_workspace_bytes(pp, batch), dtype=torch.uint8,
+                                device=left.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(lib().sff_sgm_disparity(ctypes.byref(pp), batch, ctypes.c_void_p(left.data_ptr()),
+                                   ctypes.c_void_p(right.data_ptr()), left.stride(0), int(P1),
+                                   int(P2), _ptr(disp, torch.int16, "disp"),
+                                   _ptr(workspace, None, "workspace"), ws_bytes, _stream(stream)),
+           "sff_sgm_disparity")
+    return disp
+
+
+def sff_disparity_fill(p, hyp_fwd: torch.Tensor, valid: torch.Tensor, disp: torch.Tensor,
+                       fill=None, stream=None) -> torch.Tensor:
+    """1 where the joint check kept the match or its d0 agrees with the SGM
+    disparity within tau: uint8 [batch][H][W]."""
+    pp = _params(p)
+    batch = hyp_fwd.shape[0]
+    _check_shape(hyp_fwd, (batch, pp.H, pp.W, 4), "hyp_fwd")
+    _check_shape(valid, (batch, pp.H, pp.W), "valid")
+    _check_shape(disp, (batch, pp.H, pp.W), "disp")
+    if fill is None:
+        fill = torch.empty((batch, pp.H, pp.W), dtype=torch.uint8, device=hyp_fwd.device)
+    _check_shape(fill, (batch, pp.H, pp.W), "fill")
+    _check(lib().sff_disparity_fill(ctypes.byref(pp), batch, _ptr(hyp_fwd, torch.int16, "hyp_fwd"),
+                                    _ptr(valid, torch.uint8, "valid"), _ptr(disp, torch.int16, "disp"),
+                                    _ptr(fill, torch.uint8, "fill"), _stream(stream)),
+           "sff_disparity_fill")
+    return fill
+
+
 def sff_cost_f32_fwd(feat: torch.Tensor, hyp: torch.Tensor, dir: int, cost=None, stream=None):
     """feat float32 [batch][4][H][W][cf], hyp int16 [batch][H][W][4] -> cost [batch][H][W]."""
     B, four, H, W, cf = feat.shape

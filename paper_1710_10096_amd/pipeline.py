@@ -78,6 +78,25 @@ class PairMatcher:
             out.update(keep=self.keep, seeds=self.seeds)
         return out
 
+    def disparity_fill(self, imgs: torch.Tensor, stream=None, mark=None) -> dict:
+        """Disparity fill of the last run's result (Section 3.1, last paragraph
+        of "Consistency Check"): SGM disparity of the stereo pair at t0 and the
+        check of the matched d0 alone against it.  imgs as given to run()."""
+        mk = mark if mark is not None else (lambda name: None)
+        p, B = self.p, self.batch
+        if not hasattr(self, "ws_sgm"):
+            dev = self.valid.device
+            self.ws_sgm = torch.empty(api.sff_sgm_workspace_bytes(p, B), dtype=torch.uint8,
+                                      device=dev)
+            self.disp = torch.empty((B, p.H, p.W), dtype=torch.int16, device=dev)
+            self.fill = torch.empty((B, p.H, p.W), dtype=torch.uint8, device=dev)
+        api.sff_sgm_disparity(p, imgs[:, 0], imgs[:, 2], disp=self.disp, workspace=self.ws_sgm,
+                              stream=stream)
+        mk("sgm:L0")
+        api.sff_disparity_fill(p, self.hyp[0][0], self.valid, self.disp, self.fill, stream)
+        mk("fill:L0")
+        return dict(disp=self.disp, fill=self.fill)
+
     def filter_and_sparsify(self, stream=None, mark=None):
         """Region filter and 3x3 sparsification of the last run's result."""
         mk = mark if mark is not None else (lambda name: None)

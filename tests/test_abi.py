@@ -145,6 +145,17 @@ def test_invalid_arguments_rejected():
     assert L.sff_sparsify(P, 1, f, f, None, None) == 1
     assert L.sff_sparsify(P, 0, f, f, f, None) == 1
     assert L.sff_sparsify(P, 1, f, ctypes.c_void_p(0x1002), f, None) == 1
+    # SGM disparity and fill
+    need_s = L.sff_sgm_workspace_bytes(P, 1)
+    assert need_s > 0
+    assert L.sff_sgm_disparity(P, 1, f, f, 0, 5, 3, f, f, need_s, None) == 1      # P2 < P1
+    assert L.sff_sgm_disparity(P, 1, f, f, 0, 3, 232, f, f, need_s, None) == 1    # P2 > 231
+    assert L.sff_sgm_disparity(P, 2, f, f, 16, 3, 24, f, f, need_s, None) == 1   # stride < image
+    assert L.sff_sgm_disparity(P, 1, f, f, 0, 3, 24, f, f, need_s - 1, None) == 4
+    p4 = _good()
+    p4.dmax = 300
+    assert L.sff_sgm_disparity(ctypes.byref(p4), 1, f, f, 0, 3, 24, f, f, 1 << 40, None) == 2
+    assert L.sff_disparity_fill(P, 1, f, f, None, f, None) == 1
     # overlapping hand-off buffers
     p3 = _good()
     p3.levels = 2
