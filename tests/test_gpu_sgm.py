@@ -31,6 +31,7 @@ def dev(a):
 CASES = [  # H, W, C, dmax, P1, P2, batch
     (9, 13, 3, 5, 3, 24, 1), (1, 40, 1, 7, 2, 9, 2), (40, 1, 2, 3, 3, 24, 1), (31, 57, 3, 12, 0, 0, 1),
     (24, 70, 4, 30, 5, 60, 3), (17, 300, 1, 255, 3, 24, 1), (6, 6, 3, 0, 3, 24, 1),
+    (20, 90, 3, 64, 10, 231, 1), (12, 100, 3, 191, 3, 24, 2),  # largest P2; dmax + 1 > W
 ]
 
 
@@ -51,6 +52,20 @@ def test_sgm_parity(sff, case):
     d = disp.cpu().numpy()
     for b in range(B):
         assert np.array_equal(d[b], oracle.sgm(imgs[b, 0], imgs[b, 2], dmax + 1, P1, P2)), (case, b)
+
+
+def test_sgm_constant_images(sff):
+    """Every cost is zero: all disparities tie and the smallest, 0, wins."""
+    import torch
+    H, W = 33, 170
+    imgs = np.full((1, 4, H, W, 3), 77, np.uint8)
+    p = params_dict(H, W, 3, levels=1, iters=1, dmax=100)
+    _say("sgm constant")
+    g = dev(imgs)
+    disp = sff.sff_sgm_disparity(p, g[:, 0], g[:, 2])
+    torch.cuda.synchronize()
+    assert not disp.cpu().numpy().any()
+    assert not oracle.sgm(imgs[0, 0], imgs[0, 2], 101, sff.api.SGM_P1, sff.api.SGM_P2).any()
 
 
 def test_sgm_and_fill_on_matching_output(sff):
