@@ -176,6 +176,36 @@ def fill_stage(m, imgs, steps: int) -> dict:
             "consistent": int(m.valid.sum().item()), "filled": int(m.fill.sum().item())}
 
 
+def sift_stage(p, m, imgs, steps: int) -> dict:
+    """The paper's own matching cost (dense SIFT, PCA-3, 7x7 window of eq. (1)):
+    features of the pair and one cost evaluation of the matched level-0
+    forward field per pixel (after the headline step, timed separately)."""
+    import torch
+    import paper_1710_10096_amd as sff
+    st = torch.cuda.current_stream()
+    B = imgs.shape[0]
+    ws = torch.empty(sff.sff_sift_workspace_bytes(p, 4 * B), dtype=torch.uint8, device=imgs.device)
+    out = sff.sff_sift_pca(p, imgs, workspace=ws)
+    hyp = m.hyp[0][0]
+    cost = sff.sff_cost_sift(p, out["phi"], hyp)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_f = t_c = 0.0
+    for _ in range(steps):
+        ev[0].record(st)
+        sff.sff_sift_pca(p, imgs, out=out, workspace=ws)
+        ev[1].record(st)
+        sff.sff_cost_sift(p, out["phi"], hyp, cost=cost)
+        ev[2].record(st)
+        ev[2].synchronize()
+        t_f += ev[0].elapsed_time(ev[1])
+        t_c += ev[1].elapsed_time(ev[2])
+    t_f, t_c = t_f / steps, t_c / steps
+    npx = B * p["H"] * p["W"]
+    return {"features_ms": t_f, "cost_ms": t_c, "cost_evals_per_s": npx / (t_c * 1e-3),
+            "eigval": [round(float(v), 6) for v in out["eigval"][0].tolist()]}
+
+
 def with_upload(m, imgs, seeds, steps: int) -> dict:
     """The same step preceded by the upload of the batch's images from pinned
     host memory (PCIe-inclusive rate; the library itself takes device
@@ -334,6 +364,7 @@ def main():
     out["with_upload"] = with_upload(m, imgs, seeds_t, args.steps)
     out["region_sparsify"] = region_stage(p, B, m, args.steps)
     out["disparity_fill"] = fill_stage(m, imgs, args.steps)
+    out["sift_pca_cost"] = sift_stage(p, m, imgs, args.steps)
     if not args.no_probes:
         out["probes"] = probes()
     if not args.no_cpu_baseline:

@@ -259,6 +259,64 @@ sff_status sff_disparity_fill(const sff_params* p, int32_t batch, const int16_t*
                               void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The paper's own matching cost (Section 3.1, "Matching Cost", eq. (1)): the
+ * Euclidean distances between the first three principal components of dense
+ * SIFT features, summed over a 7 x 7 window and the temporal, stereo and
+ * cross correspondences; the principal axes are those of the SIFT features of
+ * all four images of the pair; boundary pixels replicated.  FP32 features,
+ * FP64 statistics.
+ *
+ * Dense SIFT (SIFT flow, Liu et al. 2011; Lowe 2004): central-difference
+ * gradients of the grey (channel mean) image with clamped neighbours, 8
+ * orientation bins of 45 degrees (bin b centred at b * 45 degrees, y down),
+ * magnitude split linearly between the two nearest centres; 4 x 4 cells of
+ * 3 x 3 pixels over rows and columns -6 .. +5 around the pixel, pixels outside
+ * clamped; entry (4 i + j) * 8 + b for cell row i, cell column j, bin b;
+ * normalised to unit length, clamped at 0.2, normalised again (zero stays
+ * zero). */
+
+/* Device workspace (bytes) of sff_dense_sift for nimg images and of
+ * sff_sift_pca for nimg = 4 * batch images: orientation and cell-sum planes
+ * (about 64 bytes per pixel and image) plus FP64 partial sums (up to 34 MB
+ * per pair); 0 for invalid arguments. */
+size_t sff_sift_workspace_bytes(const sff_params* p, int32_t nimg);
+
+/* Dense SIFT of nimg images [nimg][H][W][C] uint8 (C = p->C) into
+ * sift [nimg][H][W][128] float32 (16-byte aligned).
+ * Errors: SFF_ERR_INVALID_ARG, SFF_ERR_WORKSPACE. */
+sff_status sff_dense_sift(const sff_params* p, int32_t nimg, const uint8_t* img, float* sift,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* Features of eq. (1) for batch pairs imgs [batch][4][H][W][C] uint8 (views
+ * l0, l1, r0, r1): per pair the mean [128] and covariance [128][128] (1/N,
+ * N = 4 H W) of the SIFT features of its four images, the three largest
+ * eigenvalues [3] and their unit eigenvectors axes [3][128] (each signed so
+ * that its component of largest magnitude is positive), and
+ * phi [batch][4][H][W][4] float32 = (axes (f - mean), 0) per pixel.
+ * FP64 outputs 8-byte aligned, phi 16-byte aligned; all caller-owned.
+ * workspace: sff_sift_workspace_bytes(p, 4 * batch) bytes, 256-byte aligned.
+ * The eigenvectors come from a subspace iteration that stops when the
+ * residuals of the three leading pairs fall below 1e-12 of the largest
+ * eigenvalue (at most 4000 iterations); for a zero covariance the axes are
+ * arbitrary unit vectors and phi is zero.
+ * Errors: SFF_ERR_INVALID_ARG, SFF_ERR_WORKSPACE. */
+sff_status sff_sift_pca(const sff_params* p, int32_t batch, const uint8_t* imgs, double* mean,
+                        double* cov, double* eigval, double* axes, float* phi, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
+/* Eq. (1) per pixel at fixed full-resolution vectors hyp [batch][H][W][4]
+ * int16 (u, v, d0, d1), from phi [batch][4][H][W][4] float32 (first three
+ * components used):
+ *   cost(p) = sum_{w in {-3..3}^2} sum_{corr in T, S, X}
+ *             || phi_R(clamp(p + w)) - phi_corr(clamp(p + w + o_corr)) ||_2,
+ *   o_T = (u, v), o_S = (-s d0, 0), o_X = (u - s d1, v), s = dir, with
+ *   (R, T, S, X) = (l0, l1, r0, r1) for SFF_DIR_FORWARD and (r1, r0, l1, l0)
+ *   for SFF_DIR_INVERSE.  cost: [batch][H][W] float32.
+ * Errors: SFF_ERR_INVALID_ARG (shapes, alignment, dir). */
+sff_status sff_cost_sift(const sff_params* p, int32_t batch, int32_t dir, const float* phi,
+                         const int16_t* hyp, float* cost, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Window form of the matching cost on real-valued feature maps (eq. (1),
  * Section 3.1: feature distances summed over a window around the pixel for the
  * temporal, stereo and cross correspondences, replicated borders), FP32:

@@ -31,6 +31,7 @@ EXPORTS = ("sff_status_string", "sff_version", "sff_desc_channels", "sff_lanczos
            "sff_wht_features", "sff_init_workspace_bytes", "sff_init_nn", "sff_init_nn_leaves", "sff_match_level",
            "sff_consistency", "sff_region_workspace_bytes", "sff_region_filter", "sff_sparsify",
            "sff_sgm_workspace_bytes", "sff_sgm_disparity", "sff_disparity_fill",
+           "sff_sift_workspace_bytes", "sff_dense_sift", "sff_sift_pca", "sff_cost_sift",
            "sff_cost_f32_fwd", "sff_cost_f32_bwd_workspace_bytes",
            "sff_cost_f32_bwd", "sff_conv3x3_bf16_fwd", "sff_conv3x3_bf16_bwd_workspace_bytes",
            "sff_conv3x3_bf16_dgrad", "sff_conv3x3_bf16_wgrad", "sff_smooth_level",
@@ -85,6 +86,14 @@ def lib() -> ctypes.CDLL:
     L.sff_sgm_disparity.restype = i32
     L.sff_disparity_fill.argtypes = [PP, i32, P, P, P, P, P]
     L.sff_disparity_fill.restype = i32
+    L.sff_sift_workspace_bytes.argtypes = [PP, i32]
+    L.sff_sift_workspace_bytes.restype = ctypes.c_size_t
+    L.sff_dense_sift.argtypes = [PP, i32, P, P, P, ctypes.c_size_t, P]
+    L.sff_dense_sift.restype = i32
+    L.sff_sift_pca.argtypes = [PP, i32, P, P, P, P, P, P, P, ctypes.c_size_t, P]
+    L.sff_sift_pca.restype = i32
+    L.sff_cost_sift.argtypes = [PP, i32, i32, P, P, P, P]
+    L.sff_cost_sift.restype = i32
     L.sff_cost_f32_fwd.argtypes = [i32] * 5 + [P, P, P, P]
     L.sff_cost_f32_fwd.restype = i32
     L.sff_cost_f32_bwd_workspace_bytes.argtypes = [i32] * 3

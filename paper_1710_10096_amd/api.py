@@ -292,6 +292,72 @@ def sff_disparity_fill(p, hyp_fwd: torch.Tensor, valid: torch.Tensor, disp: torc
     return fill
 
 
+def sff_sift_workspace_bytes(p, nimg: int) -> int:
+    pp = _params(p)
+    return int(lib().sff_sift_workspace_bytes(ctypes.byref(pp), nimg))
+
+
+def sff_dense_sift(p, img: torch.Tensor, sift=None, workspace=None, stream=None) -> torch.Tensor:
+    """Dense SIFT of uint8 images [nimg][H][W][C] -> float32 [nimg][H][W][128]."""
+    pp = _params(p)
+    nimg = img.shape[0]
+    _check_shape(img, (nimg, pp.H, pp.W, pp.C), "img")
+    if sift is None:
+        sift = torch.empty((nimg, pp.H, pp.W, 128), dtype=torch.float32, device=img.device)
+    _check_shape(sift, (nimg, pp.H, pp.W, 128), "sift")
+    if workspace is None:
+        workspace = torch.empty(sff_sift_workspace_bytes(pp, nimg), dtype=torch.uint8, device=img.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(lib().sff_dense_sift(ctypes.byref(pp), nimg, _ptr(img, torch.uint8, "img"),
+                                _ptr(sift, torch.float32, "sift"), _ptr(workspace, None, "workspace"),
+                                ws_bytes, _stream(stream)), "sff_dense_sift")
+    return sift
+
+
+def sff_sift_pca(p, imgs: torch.Tensor, out=None, workspace=None, stream=None) -> dict:
+    """SIFT-PCA features of eq. (1) for pairs imgs uint8 [batch][4][H][W][C]:
+    dict of mean [batch][128], cov [batch][128][128], eigval [batch][3],
+    axes [batch][3][128] (float64) and phi float32 [batch][4][H][W][4]."""
+    pp = _params(p)
+    batch = imgs.shape[0]
+    _check_shape(imgs, (batch, 4, pp.H, pp.W, pp.C), "imgs")
+    dev = imgs.device
+    if out is None:
+        f64 = dict(dtype=torch.float64, device=dev)
+        out = {"mean": torch.empty((batch, 128), **f64), "cov": torch.empty((batch, 128, 128), **f64),
+               "eigval": torch.empty((batch, 3), **f64), "axes": torch.empty((batch, 3, 128), **f64),
+               "phi": torch.empty((batch, 4, pp.H, pp.W, 4), dtype=torch.float32, device=dev)}
+    for k, shp in (("mean", (batch, 128)), ("cov", (batch, 128, 128)), ("eigval", (batch, 3)),
+                   ("axes", (batch, 3, 128)), ("phi", (batch, 4, pp.H, pp.W, 4))):
+        _check_shape(out[k], shp, k)
+    if workspace is None:
+        workspace = torch.empty(sff_sift_workspace_bytes(pp, 4 * batch), dtype=torch.uint8, device=dev)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(lib().sff_sift_pca(ctypes.byref(pp), batch, _ptr(imgs, torch.uint8, "imgs"),
+                              _ptr(out["mean"], torch.float64, "mean"), _ptr(out["cov"], torch.float64, "cov"),
+                              _ptr(out["eigval"], torch.float64, "eigval"),
+                              _ptr(out["axes"], torch.float64, "axes"), _ptr(out["phi"], torch.float32, "phi"),
+                              _ptr(workspace, None, "workspace"), ws_bytes, _stream(stream)), "sff_sift_pca")
+    return out
+
+
+def sff_cost_sift(p, phi: torch.Tensor, hyp: torch.Tensor, dir: int = DIR_FORWARD, cost=None,
+                  stream=None) -> torch.Tensor:
+    """Eq. (1) with SIFT-PCA features: phi float32 [batch][4][H][W][4], hyp int16
+    [batch][H][W][4] -> float32 [batch][H][W]."""
+    pp = _params(p)
+    batch = phi.shape[0]
+    _check_shape(phi, (batch, 4, pp.H, pp.W, 4), "phi")
+    _check_shape(hyp, (batch, pp.H, pp.W, 4), "hyp")
+    if cost is None:
+        cost = torch.empty((batch, pp.H, pp.W), dtype=torch.float32, device=phi.device)
+    _check_shape(cost, (batch, pp.H, pp.W), "cost")
+    _check(lib().sff_cost_sift(ctypes.byref(pp), batch, int(dir), _ptr(phi, torch.float32, "phi"),
+                               _ptr(hyp, torch.int16, "hyp"), _ptr(cost, torch.float32, "cost"),
+                               _stream(stream)), "sff_cost_sift")
+    return cost
+
+
 def sff_cost_f32_fwd(feat: torch.Tensor, hyp: torch.Tensor, dir: int, cost=None, stream=None):
     """feat float32 [batch][4][H][W][cf], hyp int16 [batch][H][W][4] -> cost [batch][H][W]."""
     B, four, H, W, cf = feat.shape

@@ -156,6 +156,22 @@ def test_invalid_arguments_rejected():
     p4.dmax = 300
     assert L.sff_sgm_disparity(ctypes.byref(p4), 1, f, f, 0, 3, 24, f, f, 1 << 40, None) == 2
     assert L.sff_disparity_fill(P, 1, f, f, None, f, None) == 1
+    # SIFT-PCA features and cost
+    need_f = L.sff_sift_workspace_bytes(P, 4)
+    assert need_f > L.sff_sift_workspace_bytes(P, 1) > 0
+    assert L.sff_sift_workspace_bytes(P, 0) == 0
+    assert L.sff_dense_sift(P, 0, f, f, f, need_f, None) == 1
+    assert L.sff_dense_sift(P, 1, f, ctypes.c_void_p(0x1004), f, need_f, None) == 1   # sift not 16-B aligned
+    assert L.sff_dense_sift(P, 4, f, f, f, need_f - 1, None) == 4
+    assert L.sff_dense_sift(P, 4, f, f, ctypes.c_void_p(0x1010), need_f, None) == 4
+    assert L.sff_sift_pca(P, 1, f, f, f, f, None, f, f, need_f, None) == 1
+    assert L.sff_sift_pca(P, 1, f, f, f, f, f, ctypes.c_void_p(0x1008), f, need_f, None) == 1
+    assert L.sff_sift_pca(P, 1, f, ctypes.c_void_p(0x1004), f, f, f, f, f, need_f, None) == 1
+    assert L.sff_sift_pca(P, 1, f, f, f, f, f, f, f, need_f - 1, None) == 4
+    assert L.sff_sift_pca(P, 2, f, f, f, f, f, f, f, need_f, None) == 4          # sized for one pair
+    assert L.sff_cost_sift(P, 1, 0, f, f, f, None) == 1                          # dir 0
+    assert L.sff_cost_sift(P, 1, 1, ctypes.c_void_p(0x1008), f, f, None) == 1    # phi not 16-B aligned
+    assert L.sff_cost_sift(P, 0, 1, f, f, f, None) == 1
     # overlapping hand-off buffers
     p3 = _good()
     p3.levels = 2
