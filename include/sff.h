@@ -170,7 +170,8 @@ sff_status sff_init_nn_leaves(const sff_params* p, int32_t batch, int32_t dir, i
  * hyp/cost: level-k field, read and written in place.
  * Two kernels with identical results gather the descriptors: one lane per
  *   pixel for small levels, wave-cooperative loads otherwise; the environment
- *   variable SFF_MATCH_EVAL=lane|coop forces one (testing and timing).
+ *   variable SFF_MATCH_EVAL=lane|coop|coop-narrow|coop-wide forces one (testing
+ *   and timing).
  * Errors: SFF_ERR_INVALID_ARG (also for level >= levels - 1 with a non-NULL
  *   hyp_coarse, and for overlapping hyp/hyp_coarse). */
 sff_status sff_match_level(const sff_params* p, int32_t batch, int32_t dir, int32_t level,

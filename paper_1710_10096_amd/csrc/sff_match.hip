@@ -109,6 +109,35 @@ struct Coop {
         wave_sync();
         return c;
     }
+
+    // ssd for N targets per owner at once (all gathers in flight together);
+    // needs a slice of N * 64 P words.
+    template <int N>
+    __device__ __forceinline__ void ssdN(const uint4* __restrict__ M, const int (&tp)[N], uint32_t (&c)[N]) {
+        int t[N][P];
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+#pragma unroll
+            for (int k = 0; k < P; ++k) t[m][k] = __shfl(tp[m], owner(k, lane));
+        uint4 v[N][P];
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+#pragma unroll
+            for (int k = 0; k < P; ++k) v[m][k] = M[(size_t)max(t[m][k], 0) * RS + piece(k, lane)];
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+#pragma unroll
+            for (int k = 0; k < P; ++k)
+                part[64 * (m * P + k) + lane] = t[m][k] >= 0 ? (uint32_t)piece_ssd(refp[k], v[m][k], 0) : 0u;
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            c[m] = 0;
+#pragma unroll
+            for (int w = 0; w < P; ++w) c[m] += part[64 * P * m + lane * P + w];
+        }
+        wave_sync();
+    }
 };
 
 // eq. (1): temporal (x+u, y+v), stereo (x - s d0, y), cross (x+u - s d1, y+v),
@@ -130,6 +159,8 @@ struct Coop {
 template <int C>
 struct LaneEval {
     static constexpr int kLdsWords = 1;
+    static constexpr int kPG = 1, kRG = 1;
+    static constexpr bool kCoop = false;
     const uint4 *T, *S, *X;
     int H, W, s;
     Desc<C> ref;
@@ -155,9 +186,15 @@ struct LaneEval {
     }
 };
 
-template <int C>
+// PG neighbour candidates and RG random-search samples are scored together
+// (their gathers in flight at once); the LDS slice holds the partials of the
+// larger group.
+template <int C, int PG, int RG>
 struct CoopEval {
-    static constexpr int kLdsWords = 64 * Coop<C>::P;
+    static constexpr int kPG = PG, kRG = RG;
+    static constexpr int kGroup = PG > RG ? PG : RG;
+    static constexpr int kLdsWords = kGroup * 64 * Coop<C>::P;
+    static constexpr bool kCoop = true;
     const uint4 *T, *S, *X;
     int H, W, s;
     Coop<C> cp;
@@ -185,6 +222,44 @@ struct CoopEval {
             }
         }
         return c;
+    }
+
+    // cost_below for N candidates of each lane, their gathers issued together
+    // view by view; same results as N calls with the same bound.
+    template <int N>
+    __device__ __forceinline__ void cost_belowN(const bool (&w)[N], const Hyp (&h)[N], int x, int y,
+                                                uint32_t bound, uint32_t (&c)[N]) {
+        static_assert(N <= kGroup, "LDS slice sized for kGroup candidates");
+        int ty[N], tp[N];
+        bool al[N];
+        bool any = false;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            ty[m] = clampi(y + h[m].v, 0, H - 1);
+            tp[m] = w[m] ? ty[m] * W + clampi(x + h[m].u - s * h[m].d1, 0, W - 1) : -1;
+        }
+        cp.template ssdN<N>(X, tp, c);
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            al[m] = w[m] && c[m] < bound;
+            any = any || al[m];
+            tp[m] = al[m] ? ty[m] * W + clampi(x + h[m].u, 0, W - 1) : -1;
+        }
+        if (!__any(any)) return;
+        uint32_t d[N];
+        cp.template ssdN<N>(T, tp, d);
+        any = false;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            c[m] += d[m];
+            al[m] = al[m] && c[m] < bound;
+            any = any || al[m];
+            tp[m] = al[m] ? y * W + clampi(x - s * h[m].d0, 0, W - 1) : -1;
+        }
+        if (!__any(any)) return;
+        cp.template ssdN<N>(S, tp, d);
+#pragma unroll
+        for (int m = 0; m < N; ++m) c[m] += d[m];
     }
 };
 
@@ -275,25 +350,59 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
                 nh[q] = mode == 1 ? coarse[(size_t)(ni[q] >> 1) * a.Wc + (nj[q] >> 1)]
                                   : field[(size_t)ni[q] * a.Wk + nj[q]];
         }
+        bool want[4];
+        Hyp hq[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             bool dup = nh[q].x == own.x && nh[q].y == own.y;
 #pragma unroll
             for (int p = 0; p < q; ++p) dup = dup || (in[p] && nh[q].x == nh[p].x && nh[q].y == nh[p].y);
-            const bool want = in[q] && !dup;
-            if (!__any(want)) continue;
-            const Hyp h = unpack(nh[q]);
-            const uint32_t c = V.cost_below(want, x, y, h, bestc);
-            if (want && c < bestc) {
+            want[q] = in[q] && !dup;
+            hq[q] = unpack(nh[q]);
+        }
+        // Candidates are accepted one after the other in their order.  The
+        // cooperative evaluator scores a group at a time against the bound
+        // from before the group: a later candidate rejected against that bound
+        // is at least as costly as the updated best, and one scored below it
+        // has its exact cost, so the results are those of one at a time, and
+        // the group's gathers are in flight together instead of in sequence.
+        auto take = [&](bool w, const Hyp& h, uint32_t c) {
+            if (w && c < bestc) {
                 bestc = c;
                 best = h;
+            }
+        };
+        constexpr int kPropGroup = E::kPG;
+        if constexpr (E::kCoop) {
+#pragma unroll
+            for (int q0 = 0; q0 < 4; q0 += kPropGroup) {
+                bool wg[kPropGroup];
+                Hyp hg[kPropGroup];
+                bool any = false;
+#pragma unroll
+                for (int m = 0; m < kPropGroup; ++m) {
+                    wg[m] = want[q0 + m];
+                    hg[m] = hq[q0 + m];
+                    any = any || wg[m];
+                }
+                if (!__any(any)) continue;
+                uint32_t c[kPropGroup];
+                V.template cost_belowN<kPropGroup>(wg, hg, x, y, bestc, c);
+#pragma unroll
+                for (int m = 0; m < kPropGroup; ++m) take(wg[m], hg[m], c[m]);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (!__any(want[q])) continue;
+                take(want[q], hq[q], V.cost_below(want[q], x, y, hq[q], bestc));
             }
         }
         // random search around the propagated vector
         const Hyp centre = best;
         const uint64_t seed = a.seeds[b];
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-        for (int t = 0; t < a.rs_samples; ++t) {
+        auto sample = [&](int t) {
             const int r = max(1, a.rs_r0 >> t) * n;
             U4 ctr;
             ctr.x = (uint32_t)(i * a.Wk + jj);
@@ -306,12 +415,32 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
             c.v = clampi(centre.v + uniform_offset(rnd.y, r), -a.fmax, a.fmax);
             c.d0 = clampi(centre.d0 + uniform_offset(rnd.z, r), 0, a.dmax);
             c.d1 = clampi(centre.d1 + uniform_offset(rnd.w, r), 0, a.dmax);
-            const bool want = act && !same(c, centre);
-            if (!__any(want)) continue;
-            const uint32_t cc = V.cost_below(want, x, y, c, bestc);
-            if (want && cc < bestc) {
-                bestc = cc;
-                best = c;
+            return c;
+        };
+        constexpr int kRS = E::kRG;
+        for (int t = 0; t < a.rs_samples; t += kRS) {
+            if (kRS > 1 && t + kRS <= a.rs_samples) {
+                Hyp cg[kRS];
+                bool wg[kRS];
+                bool any = false;
+#pragma unroll
+                for (int m = 0; m < kRS; ++m) {
+                    cg[m] = sample(t + m);
+                    wg[m] = act && !same(cg[m], centre);
+                    any = any || wg[m];
+                }
+                if (!__any(any)) continue;
+                uint32_t cc[kRS];
+                if constexpr (E::kCoop) V.template cost_belowN<kRS>(wg, cg, x, y, bestc, cc);
+#pragma unroll
+                for (int m = 0; m < kRS; ++m) take(wg[m], cg[m], cc[m]);
+            } else {
+                for (int u = t; u < min(t + kRS, a.rs_samples); ++u) {
+                    const Hyp c0 = sample(u);
+                    const bool w0 = act && !same(c0, centre);
+                    if (!__any(w0)) continue;
+                    take(w0, c0, V.cost_below(w0, x, y, c0, bestc));
+                }
             }
         }
     }
@@ -348,18 +477,29 @@ sff_status launch_level(const MatchArgs& a, int iters, hipStream_t st) {
     return launch_status();
 }
 
-// SFF_MATCH_EVAL = "lane" or "coop" forces an evaluator (both give identical
-// results; the switch exists to test and time each one); anything else: auto.
+// From this many pixel updates per launch the wider groups (4 neighbours,
+// 3 samples) pay off; below it their registers cost more occupancy than the
+// extra gathers in flight gain (measured at level 0 and 1 of the KITTI-size
+// pair: 4/3 takes 1.48 vs 1.53 ms at level 0 and 0.49 vs 0.48 ms at level 1
+// against 2/3; one candidate at a time 1.71 and 0.47 ms).
+constexpr long kWideMinUpdates = 262144;
+
+// SFF_MATCH_EVAL = "lane", "coop" (group sizes by size), "coop-narrow" or
+// "coop-wide" forces an evaluator (all give identical results; the switch
+// exists to test and time each one); anything else: auto.
 template <int C>
 sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
     const long updates = (long)a.ndir * a.batch * a.Hk * ((a.Wk + 1) / 2);
-    bool coop = updates >= kCoopMinUpdates;
+    bool coop = updates >= kCoopMinUpdates, wide = updates >= kWideMinUpdates;
     if (const char* e = std::getenv("SFF_MATCH_EVAL")) {
         if (std::strcmp(e, "lane") == 0) coop = false;
         if (std::strcmp(e, "coop") == 0) coop = true;
+        if (std::strcmp(e, "coop-narrow") == 0) coop = true, wide = false;
+        if (std::strcmp(e, "coop-wide") == 0) coop = true, wide = true;
     }
     if (!coop) return launch_level<C, LaneEval<C>>(a, iters, st);
-    return launch_level<C, CoopEval<C>>(a, iters, st);
+    if (wide) return launch_level<C, CoopEval<C, 4, 3>>(a, iters, st);
+    return launch_level<C, CoopEval<C, 2, 3>>(a, iters, st);
 }
 
 }  // namespace

@@ -152,11 +152,12 @@ LEVEL_CASES = [
 ]
 
 
-@pytest.mark.parametrize("evaluator", ["lane", "coop"])
+@pytest.mark.parametrize("evaluator", ["lane", "coop-narrow", "coop-wide"])
 @pytest.mark.parametrize("case", LEVEL_CASES, ids=[c[0] for c in LEVEL_CASES])
 def test_match_level_parity(sff, case, evaluator, monkeypatch):
-    """Both descriptor-gather kernels (per-lane and wave-cooperative) against
-    the oracle; SFF_MATCH_EVAL forces one of them."""
+    """Every descriptor-gather kernel (per-lane; wave-cooperative scoring 2
+    neighbours and 3 samples, or 4 and 3, at a time) against the oracle;
+    SFF_MATCH_EVAL forces one of them."""
     import torch
     monkeypatch.setenv("SFF_MATCH_EVAL", evaluator)
     name, H, W, C, levels, level, iters, rs, B = case
@@ -269,7 +270,7 @@ def test_pipeline_ragged_batch_on_side_stream(sff):
         _check_pipeline(sff, scenes, p, [5, 6, 7], stream=st)
 
 
-@pytest.mark.parametrize("evaluator", ["auto", "lane", "coop"])
+@pytest.mark.parametrize("evaluator", ["auto", "lane", "coop-narrow", "coop-wide"])
 def test_pipeline_kitti_full(sff, evaluator, monkeypatch):
     monkeypatch.setenv("SFF_MATCH_EVAL", evaluator)
     _say("pipeline kitti 1242x375", evaluator)
