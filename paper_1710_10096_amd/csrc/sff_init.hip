@@ -182,11 +182,12 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
         for (int e = 0; e < 4; ++e) T.bsq[e] = (int)P.sq[rowT + clampi(c0 + 4 * g + e, 0, Wk - 1)];
         return T;
     };
-    Tile cur{};
+    // The scan alternates between two tile buffers (scan_one(a, b) scores a
+    // and loads the next tile into b), so no tile is copied between steps.
+    Tile ta{}, tb{};
     int r = rlo + w, ct = ct_lo;
-    if (total > 0) cur = load_tile(r, ct);
-    for (int q = 0; q < total; ++q) {
-        Tile nxt{};
+    if (total > 0) ta = load_tile(r, ct);
+    auto scan_one = [&](const Tile& cur, Tile& nxt, int q) {
         int rn = r, ctn = ct + 1;
         if (ctn > ct_hi) {
             ctn = ct_lo;
@@ -226,9 +227,11 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
                 int k[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    // |b|^2 + 2 (-a.b), -a.b = 256 (256 hh + cr) + ll  (mod 2^32)
-                    const uint32_t key = (uint32_t)cur.bsq[e] + ((uint32_t)ll[e] << 1) +
-                                         ((uint32_t)cr[e] << 9) + ((uint32_t)hh[e] << 17);
+                    // |b|^2 + 2 (-a.b), -a.b = 256 (256 hh + cr) + ll  (mod 2^32),
+                    // nested so that each step is one shift-add
+                    const uint32_t hc = ((uint32_t)hh[e] << 8) + (uint32_t)cr[e];
+                    const uint32_t ab = (hc << 8) + (uint32_t)ll[e];
+                    const uint32_t key = (ab << 1) + (uint32_t)cur.bsq[e];
                     k[e] = (int)key;
                     if constexpr (!kInterior) k[e] = ok[e] ? k[e] : INT_MAX;
                 }
@@ -267,9 +270,12 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
             else
                 score(std::false_type{}, std::false_type{});
         }
-        cur = nxt;
         r = rn;
         ct = ctn;
+    };
+    for (int q = 0; q < total; q += 2) {
+        scan_one(ta, tb, q);
+        if (q + 1 < total) scan_one(tb, ta, q + 1);
     }
     // the smallest target index of the winning tile that reaches the minimum
     // (exact squared distances from the int16 descriptors, equal to the MFMA
