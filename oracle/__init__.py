@@ -56,6 +56,8 @@ def lib():
         L.orc_cost.restype = ctypes.c_uint32
         L.orc_init_nn.argtypes = [P, P, P, P] + [i32] * 8 + [P, P]
         L.orc_init_nn_leaves.argtypes = [P] * 4 + [i32] * 9 + [P, P]
+        L.orc_cost_sift.argtypes = [P, i32, i32, i32, P, P]
+        L.orc_match_sift.argtypes = ([P, i32, i32, i32, ctypes.c_uint64] + [i32] * 7 + [P, P])
         L.orc_match_level.argtypes = ([P, P, P, P] + [i32] * 5 + [ctypes.c_uint64]
                                       + [i32] * 5 + [P, i32, i32, P, P])
         L.orc_consistency.argtypes = [P, P, i32, i32, i32, P, P]
@@ -320,3 +322,34 @@ def match_pair(imgs, params: dict, seed: int, nthreads: int = 0, schedule: str =
                                          nthreads, scan, leaves, _p(hyp), _p(cst), _p(valid),
                                          _p(err)) == 0
     return dict(hyp=hyp, cost=cst, valid=valid, err=err)
+
+
+def cost_sift(phi, hyp, s: int = 1):
+    """Eq. (1) with SIFT-PCA features phi [4][H][W][3 or 4] (rounded to float32),
+    FP32 as the oracle's matcher computes it: float32 [H][W]."""
+    ph = _phi4(phi)
+    _, H, W, _ = ph.shape
+    h = _c(hyp, np.int16)
+    out = np.zeros((H, W), np.float32)
+    assert lib().orc_cost_sift(_p(ph), H, W, s, _p(h), _p(out)) == 0
+    return out
+
+
+def match_sift(phi, hyp, s: int, seed: int, iters: int, rs_r0: int, rs_samples: int, fmax: int,
+               dmax: int, order: int = 0, nthreads: int = 0):
+    """Full-resolution propagation and random search with the SIFT-PCA cost
+    from the field hyp [H][W][4]; returns (hyp, cost float32)."""
+    ph = _phi4(phi)
+    _, H, W, _ = ph.shape
+    h = np.array(hyp, dtype=np.int16, copy=True, order="C")
+    c = np.zeros((H, W), np.float32)
+    assert lib().orc_match_sift(_p(ph), H, W, s, seed, iters, rs_r0, rs_samples, fmax, dmax, order,
+                                nthreads, _p(h), _p(c)) == 0
+    return h, c
+
+
+def _phi4(phi):
+    ph = np.asarray(phi)
+    out = np.zeros(ph.shape[:3] + (4,), np.float32)
+    out[..., :3] = ph[..., :3]
+    return np.ascontiguousarray(out)

@@ -969,3 +969,135 @@ int orc_match_pair_schedule(const uint8_t* imgs, int H, int W, int C, int levels
     free(desc); free(hyp_c);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Full-resolution matching with the paper's own cost (Section 3.1,          */
+/* "Matching Cost", eq. (1), and "Multi-Scale Propagation" at the finest      */
+/* scale), starting from a given field.  Features phi [4][H][W][4] float      */
+/* (first three principal components of the SIFT features, views l0, l1, r0, */
+/* r1; the fourth component is ignored).  Cost of h at (x, y), in FP32 with   */
+/* every operation rounded as written (the library computes the same sums in  */
+/* the same order):                                                          */
+/*   for wy = -3..3, wx = -3..3, for the temporal, stereo, cross partners in  */
+/*   that order: sum += sqrt(e0^2 + e1^2 + e2^2), e = phi_R(clamp(p + w)) -   */
+/*   phi_corr(clamp(p + w + o_corr)), squares added left to right.            */
+/* Schedule, tie rule and random search as in orc_match_level at level 0,     */
+/* with its own random stream: the counter's level field is 16 (no image      */
+/* level reaches it) and the radii are R0 >> t (n = 1).                       */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    const float *R, *T, *S, *X;
+    int H, W, s;
+} orc_fviews;
+
+static float fdist3(const float* a, const float* b) {
+    const float e0 = a[0] - b[0], e1 = a[1] - b[1], e2 = a[2] - b[2];
+    float q = e0 * e0;
+    const float q1 = e1 * e1;
+    q = q + q1;
+    const float q2 = e2 * e2;
+    q = q + q2;
+    return sqrtf(q);
+}
+
+static float cost_sift(const orc_fviews* V, int x, int y, const int16_t h[4]) {
+    const int H = V->H, W = V->W, s = V->s;
+    const int u = h[0], v = h[1], d0 = h[2], d1 = h[3];
+    float sum = 0.f;
+    for (int wy = -3; wy <= 3; ++wy)
+        for (int wx = -3; wx <= 3; ++wx) {
+            const int py = y + wy, px = x + wx;
+            const float* r = V->R + ((size_t)clampi(py, 0, H - 1) * W + clampi(px, 0, W - 1)) * 4;
+            const float* t = V->T + ((size_t)clampi(py + v, 0, H - 1) * W + clampi(px + u, 0, W - 1)) * 4;
+            const float* sv = V->S + ((size_t)clampi(py, 0, H - 1) * W + clampi(px - s * d0, 0, W - 1)) * 4;
+            const float* xv =
+                V->X + ((size_t)clampi(py + v, 0, H - 1) * W + clampi(px + u - s * d1, 0, W - 1)) * 4;
+            sum = sum + fdist3(r, t);
+            sum = sum + fdist3(r, sv);
+            sum = sum + fdist3(r, xv);
+        }
+    return sum;
+}
+
+/* Exposed for tests: eq. (1) with SIFT-PCA features at every pixel. */
+int orc_cost_sift(const float* phi, int H, int W, int s, const int16_t* hyp, float* cost) {
+    const size_t npx = (size_t)H * W;
+    orc_fviews V = {phi + (size_t)(s > 0 ? 0 : 3) * npx * 4, phi + (size_t)(s > 0 ? 1 : 2) * npx * 4,
+                    phi + (size_t)(s > 0 ? 2 : 1) * npx * 4, phi + (size_t)(s > 0 ? 3 : 0) * npx * 4,
+                    H, W, s};
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) cost[(size_t)y * W + x] = cost_sift(&V, x, y, hyp + ((size_t)y * W + x) * 4);
+    return ORC_OK;
+}
+
+#define ORC_SIFT_LEVEL_TAG 16
+
+static void update_pixel_sift(const orc_fviews* V, int i, int j, int it, uint64_t seed,
+                              const orc_level_params* P, int16_t* hyp, float* cost) {
+    const int H = V->H, W = V->W;
+    int16_t* own = hyp + ((size_t)i * W + j) * 4;
+    int16_t best[4];
+    hyp_copy(best, own);
+    float bestc = cost[(size_t)i * W + j];
+    const int di[4] = {0, -1, 0, 1};
+    const int dj[4] = {-1, 0, 1, 0};
+    for (int q = 0; q < 4; ++q) {
+        const int ni = i + di[q], nj = j + dj[q];
+        if (ni < 0 || ni >= H || nj < 0 || nj >= W) continue;
+        const int16_t* nh = hyp + ((size_t)ni * W + nj) * 4;
+        const float c = cost_sift(V, j, i, nh);
+        if (c < bestc) { bestc = c; hyp_copy(best, nh); }
+    }
+    int16_t centre[4];
+    hyp_copy(centre, best);
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int t = 0; t < P->rs_samples; ++t) {
+        int r = P->rs_r0 >> t;
+        if (r < 1) r = 1;
+        const uint32_t ctr[4] = {(uint32_t)(i * W + j), (uint32_t)it,
+                                 ((uint32_t)ORC_SIFT_LEVEL_TAG << 16) | ((uint32_t)t << 8) |
+                                     (V->s < 0 ? 1u : 0u),
+                                 0u};
+        uint32_t rnd[4];
+        orc_philox4x32_10(ctr, key, rnd);
+        int off[4];
+        for (int c = 0; c < 4; ++c) off[c] = (int)(((uint64_t)rnd[c] * (uint64_t)(2 * r + 1)) >> 32) - r;
+        int16_t cand[4];
+        cand[0] = (int16_t)clampi(centre[0] + off[0], -P->fmax, P->fmax);
+        cand[1] = (int16_t)clampi(centre[1] + off[1], -P->fmax, P->fmax);
+        cand[2] = (int16_t)clampi(centre[2] + off[2], 0, P->dmax);
+        cand[3] = (int16_t)clampi(centre[3] + off[3], 0, P->dmax);
+        const float c = cost_sift(V, j, i, cand);
+        if (c < bestc) { bestc = c; hyp_copy(best, cand); }
+    }
+    hyp_copy(own, best);
+    cost[(size_t)i * W + j] = bestc;
+}
+
+/* hyp [H][W][4] in/out (the starting field), cost [H][W] out. */
+int orc_match_sift(const float* phi, int H, int W, int s, uint64_t seed, int iters, int rs_r0,
+                   int rs_samples, int fmax, int dmax, int order, int nthreads, int16_t* hyp,
+                   float* cost) {
+    const size_t npx = (size_t)H * W;
+    orc_fviews V = {phi + (size_t)(s > 0 ? 0 : 3) * npx * 4, phi + (size_t)(s > 0 ? 1 : 2) * npx * 4,
+                    phi + (size_t)(s > 0 ? 2 : 1) * npx * 4, phi + (size_t)(s > 0 ? 3 : 0) * npx * 4,
+                    H, W, s};
+    orc_level_params P = {iters, rs_r0, rs_samples, fmax, dmax};
+    set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) cost[(size_t)y * W + x] = cost_sift(&V, x, y, hyp + ((size_t)y * W + x) * 4);
+    for (int it = 0; it < iters; ++it)
+        for (int colour = 0; colour < 2; ++colour) {
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int ii = 0; ii < H; ++ii) {
+                const int i = order ? (H - 1 - ii) : ii;
+                for (int jj = 0; jj < W; ++jj) {
+                    const int j = order ? (W - 1 - jj) : jj;
+                    if (((i + j) & 1) != colour) continue;
+                    update_pixel_sift(&V, i, j, it, seed, &P, hyp, cost);
+                }
+            }
+        }
+    return ORC_OK;
+}
