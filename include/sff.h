@@ -317,6 +317,25 @@ sff_status sff_sift_pca(const sff_params* p, int32_t batch, const uint8_t* imgs,
 sff_status sff_cost_sift(const sff_params* p, int32_t batch, int32_t dir, const float* phi,
                          const int16_t* hyp, float* cost, void* stream);
 
+/* Full-resolution matching with the cost above (Section 3.1, "Multi-Scale
+ * Propagation" at the finest scale, with the eq. (1) of "Matching Cost"),
+ * starting from the field in hyp: the cost of every pixel's vector, then
+ * `iters` iterations of red-black propagation (left, up, right, down) and
+ * p->rs_samples random-search samples (radius p->rs_r0 >> t, Philox4x32-10
+ * with key = seeds[b] and counter (y W + x, it, (16 << 16) | (t << 8) |
+ * (s < 0), 0)), strict improvement, vectors clamped to p->fmax / p->dmax.
+ * Costs in FP32 summed in a fixed order (window rows, columns, then the
+ * temporal, stereo and cross distances ((e0^2 + e1^2) + e2^2, correctly
+ * rounded root), each operation rounded), so results are reproducible bit for
+ * bit; sff_cost_sift uses the same arithmetic.
+ * phi: [batch][4][H][W][4] float32 (sff_sift_pca); seeds: [batch] uint64;
+ * hyp: [ndir][batch][H][W][4] int16, read and written (ndir = 2 for
+ * SFF_DIR_BOTH, forward first); cost: [ndir][batch][H][W] float32, written.
+ * Errors: SFF_ERR_INVALID_ARG. */
+sff_status sff_match_sift(const sff_params* p, int32_t batch, int32_t dir, const float* phi,
+                          const uint64_t* seeds, int32_t iters, int16_t* hyp, float* cost,
+                          void* stream);
+
 /* ---------------------------------------------------------------------------
  * Window form of the matching cost on real-valued feature maps (eq. (1),
  * Section 3.1: feature distances summed over a window around the pixel for the

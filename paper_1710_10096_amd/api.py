@@ -358,6 +358,27 @@ def sff_cost_sift(p, phi: torch.Tensor, hyp: torch.Tensor, dir: int = DIR_FORWAR
     return cost
 
 
+def sff_match_sift(p, phi: torch.Tensor, seeds: torch.Tensor, hyp: torch.Tensor, dir: int = DIR_BOTH,
+                   iters: int | None = None, cost=None, stream=None) -> torch.Tensor:
+    """Full-resolution propagation and random search with the SIFT-PCA cost of
+    eq. (1), in place on hyp int16 [ndir][batch][H][W][4] (the starting field);
+    returns cost float32 [ndir][batch][H][W]."""
+    pp = _params(p)
+    batch = phi.shape[0]
+    ndir = 2 if dir == DIR_BOTH else 1
+    _check_shape(phi, (batch, 4, pp.H, pp.W, 4), "phi")
+    _check_shape(hyp, (ndir, batch, pp.H, pp.W, 4), "hyp")
+    _check_shape(seeds, (batch,), "seeds")
+    if cost is None:
+        cost = torch.empty((ndir, batch, pp.H, pp.W), dtype=torch.float32, device=phi.device)
+    _check_shape(cost, (ndir, batch, pp.H, pp.W), "cost")
+    it = pp.iters if iters is None else int(iters)
+    _check(lib().sff_match_sift(ctypes.byref(pp), batch, int(dir), _ptr(phi, torch.float32, "phi"),
+                                _ptr(seeds, torch.int64, "seeds"), it, _ptr(hyp, torch.int16, "hyp"),
+                                _ptr(cost, torch.float32, "cost"), _stream(stream)), "sff_match_sift")
+    return cost
+
+
 def sff_cost_f32_fwd(feat: torch.Tensor, hyp: torch.Tensor, dir: int, cost=None, stream=None):
     """feat float32 [batch][4][H][W][cf], hyp int16 [batch][H][W][4] -> cost [batch][H][W]."""
     B, four, H, W, cf = feat.shape

@@ -699,47 +699,187 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
 
 // ------------------------------------------------------------------ cost --
 
-// Eq. (1): one thread per pixel of a 16 x 16 tile, the reference features of
-// the tile plus the window margin staged in LDS, target features gathered.
+// Euclidean distance of the first three components, every operation rounded
+// as written (no contraction), so that sums agree bit for bit with the FP32
+// definition: ((e0^2 + e1^2) + e2^2), correctly rounded square root.  sqrtf
+// is correctly rounded in this toolchain's default FP32 mode (checked against
+// the host on 2^20 inputs); __fsqrt_rn is not (15% of them differ by an ulp).
+// HIP contracts multiply-adds by default (the __f*_rn helpers included):
+// switched off here, with plain operators under the pragma.
+__device__ __forceinline__ float fdist3(float4 a, float4 b) {
+#pragma clang fp contract(off)
+    const float e0 = a.x - b.x, e1 = a.y - b.y, e2 = a.z - b.z;
+    float q = e0 * e0;
+    q = q + e1 * e1;
+    q = q + e2 * e2;
+    return sqrtf(q);
+}
+
+// Views of one field: (R, T, S, X) = (l0, l1, r0, r1) for s = +1 and
+// (r1, r0, l1, l0) for s = -1.
+struct SiftViews {
+    const float4 *R, *T, *S, *X;
+    int H, W, s;
+};
+
+__device__ __forceinline__ SiftViews sift_views(const float4* phi_pair, int H, int W, int s) {
+    const size_t npx = (size_t)H * W;
+    SiftViews V;
+    V.R = phi_pair + (size_t)(s > 0 ? 0 : 3) * npx;
+    V.T = phi_pair + (size_t)(s > 0 ? 1 : 2) * npx;
+    V.S = phi_pair + (size_t)(s > 0 ? 2 : 1) * npx;
+    V.X = phi_pair + (size_t)(s > 0 ? 3 : 0) * npx;
+    V.H = H;
+    V.W = W;
+    V.s = s;
+    return V;
+}
+
+// Eq. (1) of (u, v, d0, d1) at (x, y): window rows wy = -3..3, columns wx, and
+// for each window pixel the temporal, stereo and cross distances, added in
+// that order.  The terms are non-negative, so the partial sum only grows: once
+// it reaches `bound` after a window row the remaining rows are skipped and a
+// value >= bound is returned; below `bound` the exact sum is returned.
+__device__ __forceinline__ float sift_cost_below(const SiftViews& V, int x, int y, int u, int v, int d0,
+                                                 int d1, float bound) {
+    const int H = V.H, W = V.W, s = V.s;
+    float sum = 0.f;
+    for (int wy = -kWinR; wy <= kWinR; ++wy) {
+        const int py = y + wy;
+        const size_t rr = (size_t)clampi(py, 0, H - 1) * W, rv = (size_t)clampi(py + v, 0, H - 1) * W;
+#pragma unroll
+        for (int wx = -kWinR; wx <= kWinR; ++wx) {
+            const int px = x + wx;
+            const float4 r = V.R[rr + clampi(px, 0, W - 1)];
+            const float4 t = V.T[rv + clampi(px + u, 0, W - 1)];
+            const float4 sv = V.S[rr + clampi(px - s * d0, 0, W - 1)];
+            const float4 xv = V.X[rv + clampi(px + u - s * d1, 0, W - 1)];
+            sum = sum + fdist3(r, t);
+            sum = sum + fdist3(r, sv);
+            sum = sum + fdist3(r, xv);
+        }
+        if (sum >= bound) return sum;
+    }
+    return sum;
+}
+
+// Eq. (1) at fixed vectors: one thread per pixel of a 16 x 16 tile.
 __global__ void __launch_bounds__(256) cost_sift_kernel(const float4* __restrict__ phi,
                                                         const int16_t* __restrict__ hyp,
                                                         float* __restrict__ cost, int H, int W, int dir) {
-    constexpr int kT = kCT + 2 * kWinR;
-    __shared__ float4 ref[kT][kT];
     const int b = blockIdx.z;
     const size_t npx = (size_t)H * W;
-    const float4* views = phi + (size_t)b * 4 * npx;
-    const int iR = dir > 0 ? 0 : 3, iT = dir > 0 ? 1 : 2, iS = dir > 0 ? 2 : 1, iX = dir > 0 ? 3 : 0;
-    const float4* R = views + iR * npx;
-    const int y0 = blockIdx.y * kCT, x0 = blockIdx.x * kCT;
-    for (int i = threadIdx.x; i < kT * kT; i += 256) {
-        const int yy = clampi(y0 - kWinR + i / kT, 0, H - 1), xx = clampi(x0 - kWinR + i % kT, 0, W - 1);
-        ref[i / kT][i % kT] = R[(size_t)yy * W + xx];
-    }
-    __syncthreads();
-    const int ty = threadIdx.x / kCT, tx = threadIdx.x % kCT;
-    const int y = y0 + ty, x = x0 + tx;
+    const SiftViews V = sift_views(phi + (size_t)b * 4 * npx, H, W, dir);
+    const int y = blockIdx.y * kCT + threadIdx.x / kCT, x = blockIdx.x * kCT + threadIdx.x % kCT;
     if (y >= H || x >= W) return;
     const short4 h = reinterpret_cast<const short4*>(hyp)[(size_t)b * npx + (size_t)y * W + x];
-    const int u = h.x, v = h.y, d0 = h.z, d1 = h.w;
-    const int oT[2] = {u, v}, oS[2] = {-dir * d0, 0}, oX[2] = {u - dir * d1, v};
-    const float4* Tv = views + iT * npx;
-    const float4* Sv = views + iS * npx;
-    const float4* Xv = views + iX * npx;
-    auto dist = [](float4 a, float4 c) {
-        const float e0 = a.x - c.x, e1 = a.y - c.y, e2 = a.z - c.z;
-        return sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
-    };
-    float s = 0.f;
-    for (int wy = -kWinR; wy <= kWinR; ++wy)
-        for (int wx = -kWinR; wx <= kWinR; ++wx) {
-            const float4 r = ref[ty + kWinR + wy][tx + kWinR + wx];
-            const int py = y + wy, px = x + wx;
-            s += dist(r, Tv[(size_t)clampi(py + oT[1], 0, H - 1) * W + clampi(px + oT[0], 0, W - 1)]);
-            s += dist(r, Sv[(size_t)clampi(py + oS[1], 0, H - 1) * W + clampi(px + oS[0], 0, W - 1)]);
-            s += dist(r, Xv[(size_t)clampi(py + oX[1], 0, H - 1) * W + clampi(px + oX[0], 0, W - 1)]);
+    cost[(size_t)b * npx + (size_t)y * W + x] = sift_cost_below(V, x, y, h.x, h.y, h.z, h.w, INFINITY);
+}
+
+// Full-resolution matching with eq. (1) (Section 3.1, "Multi-Scale
+// Propagation" at the finest scale): one red-black half-step of both fields.
+// Block = 4 image rows x 64 pixels of the half-step's colour; each lane scores
+// its own candidates (left, up, right, down, then the random-search samples,
+// one at a time, strict improvement).  Random stream: Philox4x32-10 with the
+// counter's level field 16 and radii R0 >> t.
+struct SiftMatchArgs {
+    const float4* phi;       // [batch][4][H][W]
+    const uint64_t* seeds;   // [batch]
+    int16_t* hyp;            // [ndir][batch][H][W][4]
+    float* cost;             // [ndir][batch][H][W]
+    int H, W, rs_r0, rs_samples, fmax, dmax, batch, ndir, dir0;
+};
+
+constexpr uint32_t kSiftLevelTag = 16;
+
+__global__ void __launch_bounds__(256) sift_cost_init_kernel(SiftMatchArgs a) {
+    const int z = blockIdx.y, di = z / a.batch, b = z - di * a.batch;
+    const int s = a.ndir == 2 ? (di == 0 ? 1 : -1) : a.dir0;
+    const size_t npx = (size_t)a.H * a.W;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if ((size_t)p >= npx) return;
+    const SiftViews V = sift_views(a.phi + (size_t)b * 4 * npx, a.H, a.W, s);
+    const short4 h = reinterpret_cast<const short4*>(a.hyp)[(size_t)z * npx + p];
+    a.cost[(size_t)z * npx + p] = sift_cost_below(V, p % a.W, p / a.W, h.x, h.y, h.z, h.w, INFINITY);
+}
+
+__global__ void __launch_bounds__(256) sift_half_step_kernel(SiftMatchArgs a, int it, int colour, int tiles_x,
+                                                             int tiles_y) {
+    const int per_field = tiles_x * tiles_y;
+    const int z = blockIdx.x / per_field;
+    const int tr = blockIdx.x - z * per_field;
+    const int ty = tr / tiles_x, tx = tr - ty * tiles_x;
+    const int lane = threadIdx.x & 63;
+    const int i = ty * 4 + wave_id();
+    if (i >= a.H) return;  // whole wave
+    const int j = 2 * (tx * 64 + lane) + ((i + colour) & 1);
+    const bool act = j < a.W;
+    const int jj = min(j, a.W - 1);
+    const int di = z / a.batch, b = z - di * a.batch;
+    const int s = a.ndir == 2 ? (di == 0 ? 1 : -1) : a.dir0;
+    const size_t npx = (size_t)a.H * a.W;
+    const SiftViews V = sift_views(a.phi + (size_t)b * 4 * npx, a.H, a.W, s);
+    short4* field = reinterpret_cast<short4*>(a.hyp) + (size_t)z * npx;
+    float* cost = a.cost + (size_t)z * npx;
+    const size_t o = (size_t)i * a.W + jj;
+    short4 best = field[o];
+    float bestc = cost[o];
+    const short4 own = best;
+    const int ni[4] = {i, i - 1, i, i + 1};
+    const int nj[4] = {jj - 1, jj, jj + 1, jj};
+    short4 nh[4];
+    bool in[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        in[q] = act && ni[q] >= 0 && ni[q] < a.H && nj[q] >= 0 && nj[q] < a.W;
+        nh[q] = in[q] ? field[(size_t)ni[q] * a.W + nj[q]] : own;
+    }
+    auto eq = [](short4 p, short4 q) { return p.x == q.x && p.y == q.y && p.z == q.z && p.w == q.w; };
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        // a vector equal to one already scored has the same cost: no strict improvement
+        bool dup = eq(nh[q], own);
+#pragma unroll
+        for (int p = 0; p < q; ++p) dup = dup || (in[p] && eq(nh[q], nh[p]));
+        const bool want = in[q] && !dup;
+        if (!__any(want)) continue;
+        if (want) {
+            const float c = sift_cost_below(V, jj, i, nh[q].x, nh[q].y, nh[q].z, nh[q].w, bestc);
+            if (c < bestc) {
+                bestc = c;
+                best = nh[q];
+            }
         }
-    cost[(size_t)b * npx + (size_t)y * W + x] = s;
+    }
+    const short4 centre = best;
+    const uint64_t seed = a.seeds[b];
+    for (int t = 0; t < a.rs_samples; ++t) {
+        const int r = max(1, a.rs_r0 >> t);
+        U4 ctr;
+        ctr.x = (uint32_t)(i * a.W + jj);
+        ctr.y = (uint32_t)it;
+        ctr.z = (kSiftLevelTag << 16) | ((uint32_t)t << 8) | (s < 0 ? 1u : 0u);
+        ctr.w = 0u;
+        const U4 rnd = philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+        short4 c;
+        c.x = (short)clampi(centre.x + uniform_offset(rnd.x, r), -a.fmax, a.fmax);
+        c.y = (short)clampi(centre.y + uniform_offset(rnd.y, r), -a.fmax, a.fmax);
+        c.z = (short)clampi(centre.z + uniform_offset(rnd.z, r), 0, a.dmax);
+        c.w = (short)clampi(centre.w + uniform_offset(rnd.w, r), 0, a.dmax);
+        const bool want = act && !eq(c, centre);
+        if (!__any(want)) continue;
+        if (want) {
+            const float cc = sift_cost_below(V, jj, i, c.x, c.y, c.z, c.w, bestc);
+            if (cc < bestc) {
+                bestc = cc;
+                best = c;
+            }
+        }
+    }
+    if (act) {
+        field[o] = best;
+        cost[o] = bestc;
+    }
 }
 
 bool sift_shape_ok(const sff_params* p, int64_t nimg) {
@@ -834,5 +974,42 @@ extern "C" sff_status sff_cost_sift(const sff_params* p, int32_t batch, int32_t 
     hipLaunchKernelGGL(cost_sift_kernel, dim3((p->W + kCT - 1) / kCT, (p->H + kCT - 1) / kCT, batch),
                        dim3(256), 0, as_stream(stream), reinterpret_cast<const float4*>(phi), hyp, cost,
                        p->H, p->W, dir == SFF_DIR_FORWARD ? 1 : -1);
+    return launch_status();
+}
+
+extern "C" sff_status sff_match_sift(const sff_params* p, int32_t batch, int32_t dir, const float* phi,
+                                     const uint64_t* seeds, int32_t iters, int16_t* hyp, float* cost,
+                                     void* stream) {
+    if (!params_ok(p) || batch < 1 || batch > 32767 || (dir != SFF_DIR_FORWARD && dir != SFF_DIR_INVERSE &&
+                                                         dir != SFF_DIR_BOTH) ||
+        !phi || !seeds || !hyp || !cost || iters < 0 || iters > 64 ||
+        (int64_t)batch * 4 * p->H * p->W >= (int64_t(1) << 31))
+        return SFF_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(phi) & 15) != 0 || (reinterpret_cast<uintptr_t>(hyp) & 7) != 0 ||
+        (reinterpret_cast<uintptr_t>(cost) & 3) != 0 || (reinterpret_cast<uintptr_t>(seeds) & 7) != 0)
+        return SFF_ERR_INVALID_ARG;
+    SiftMatchArgs a;
+    a.phi = reinterpret_cast<const float4*>(phi);
+    a.seeds = seeds;
+    a.hyp = hyp;
+    a.cost = cost;
+    a.H = p->H;
+    a.W = p->W;
+    a.rs_r0 = p->rs_r0;
+    a.rs_samples = p->rs_samples;
+    a.fmax = p->fmax;
+    a.dmax = p->dmax;
+    a.batch = batch;
+    a.ndir = dir == SFF_DIR_BOTH ? 2 : 1;
+    a.dir0 = dir == SFF_DIR_BOTH ? 1 : dir;
+    const int nz = a.ndir * batch;
+    hipStream_t st = as_stream(stream);
+    const size_t npx = (size_t)p->H * p->W;
+    hipLaunchKernelGGL(sift_cost_init_kernel, dim3((unsigned)((npx + 255) / 256), nz), dim3(256), 0, st, a);
+    const int tiles_x = ((p->W + 1) / 2 + 63) / 64, tiles_y = (p->H + 3) / 4;
+    for (int it = 0; it < iters; ++it)
+        for (int colour = 0; colour < 2; ++colour)
+            hipLaunchKernelGGL(sift_half_step_kernel, dim3(tiles_x * tiles_y * nz), dim3(256), 0, st, a, it,
+                               colour, tiles_x, tiles_y);
     return launch_status();
 }

@@ -97,6 +97,29 @@ class PairMatcher:
         mk("fill:L0")
         return dict(disp=self.disp, fill=self.fill)
 
+    def refine_sift(self, imgs: torch.Tensor, seeds: torch.Tensor, iters: int | None = None,
+                    stream=None, mark=None) -> dict:
+        """Matching with the paper's own cost (Section 3.1, eq. (1) on SIFT-PCA
+        features) at full resolution, starting from the last run's level-0
+        fields, then the consistency check again."""
+        mk = mark if mark is not None else (lambda name: None)
+        p, B = self.p, self.batch
+        if not hasattr(self, "ws_sift"):
+            self.ws_sift = torch.empty(api.sff_sift_workspace_bytes(p, 4 * B), dtype=torch.uint8,
+                                       device=self.valid.device)
+            self.sift_out = None
+            self.cost_sift = torch.empty((2, B, p.H, p.W), dtype=torch.float32,
+                                         device=self.valid.device)
+        self.sift_out = api.sff_sift_pca(p, imgs, out=self.sift_out, workspace=self.ws_sift,
+                                         stream=stream)
+        mk("sift_features:L0")
+        api.sff_match_sift(p, self.sift_out["phi"], seeds, self.hyp[0], api.DIR_BOTH, iters,
+                           self.cost_sift, stream)
+        mk("sift_match:L0")
+        api.sff_consistency(p, self.hyp[0][0], self.hyp[0][1], self.valid, self.err, stream)
+        mk("sift_consistency:L0")
+        return dict(hyp=self.hyp[0], cost=self.cost_sift, valid=self.valid, err=self.err)
+
     def filter_and_sparsify(self, stream=None, mark=None):
         """Region filter and 3x3 sparsification of the last run's result."""
         mk = mark if mark is not None else (lambda name: None)

@@ -172,6 +172,10 @@ def test_invalid_arguments_rejected():
     assert L.sff_cost_sift(P, 1, 0, f, f, f, None) == 1                          # dir 0
     assert L.sff_cost_sift(P, 1, 1, ctypes.c_void_p(0x1008), f, f, None) == 1    # phi not 16-B aligned
     assert L.sff_cost_sift(P, 0, 1, f, f, f, None) == 1
+    assert L.sff_match_sift(P, 1, 2, f, f, 1, f, f, None) == 1                   # dir 2
+    assert L.sff_match_sift(P, 1, 0, f, f, -1, f, f, None) == 1                  # iters < 0
+    assert L.sff_match_sift(P, 1, 0, f, None, 1, f, f, None) == 1                # no seeds
+    assert L.sff_match_sift(P, 1, 0, ctypes.c_void_p(0x1004), f, 1, f, f, None) == 1
     # overlapping hand-off buffers
     p3 = _good()
     p3.levels = 2

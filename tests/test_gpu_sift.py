@@ -23,6 +23,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 from oracle import sift_pca as sp
 from sff_inputs import kitti_params, kitti_spec, make_scene, params_dict, small_spec
 from sff_inputs.scenes import smoothed_noise
@@ -172,6 +173,8 @@ def test_cost_kernel_on_oracle_features(sff, s):
     want = _cost_fp32_ref(phi32, hyp, s)
     got = c.cpu().numpy()[0].astype(np.float64)
     assert np.all(np.abs(got - want) <= 150 * U32 * want + 1e-6)
+    # the same FP32 operations in the same order as the oracle's matcher: equal bits
+    assert np.array_equal(c.cpu().numpy()[0], oracle.cost_sift(phi32, hyp, s))
     # ground truth of the scene: lower cost than a shifted vector on average
     if s == 1:
         gt = sff.sff_cost_sift(p, dev(phi32[None]), dev(sc.gt_fwd[None]), 1).cpu().numpy()[0]
@@ -232,3 +235,100 @@ def _cost_at(phi, hyp, y, x):
                 t = phi[m, min(max(py + oy, 0), H - 1), min(max(px + ox, 0), W - 1)]
                 s += float(np.sqrt(((r - t) ** 2).sum()))
     return s
+
+
+# --------------------------------------------------------------------------
+# Full-resolution matching with the SIFT-PCA cost: bit-exact against the
+# oracle's FP32 matcher on the same features (the oracle's, rounded to FP32)
+# and the same starting fields.
+
+def _perturbed(rng, h, amount, fmax, dmax):
+    out = h.astype(np.int32) + rng.integers(-amount, amount + 1, h.shape)
+    out[..., :2] = np.clip(out[..., :2], -fmax, fmax)
+    out[..., 2:] = np.clip(out[..., 2:], 0, dmax)
+    return out.astype(np.int16)
+
+
+MATCH_CASES = [  # H, W, iters, rs_samples, rs_r0, fmax, dmax, batch
+    (40, 64, 3, 6, 8, 16, 16, 1), (23, 37, 2, 5, 4, 8, 12, 2), (1, 50, 2, 3, 4, 6, 6, 1),
+    (50, 1, 2, 3, 4, 6, 6, 1), (33, 130, 2, 6, 16, 20, 16, 1),
+]
+
+
+@pytest.mark.parametrize("case", MATCH_CASES, ids=[str(c) for c in MATCH_CASES])
+def test_match_sift_parity(sff, case):
+    import torch
+    H, W, iters, rs, r0, fmax, dmax, B = case
+    rng = np.random.default_rng(H * 13 + W)
+    phis, starts = [], []
+    for b in range(B):
+        sc = make_scene(small_spec(H, W, 3, seed=40 + b, flow_max=6, d_range=(0, 8)))
+        phis.append(sp.sift_pca_features(sc.stack())["phi"])
+        starts.append(np.stack([_perturbed(rng, sc.gt_fwd, 2, fmax, dmax),
+                                _perturbed(rng, sc.gt_inv, 2, fmax, dmax)]))
+    phi32 = np.zeros((B, 4, H, W, 4), np.float32)
+    phi32[..., :3] = np.stack(phis)
+    hyp0 = np.stack(starts, axis=1)                       # [2][B][H][W][4]
+    seeds = np.array([17 + 5 * b for b in range(B)], np.int64)
+    p = params_dict(H, W, 3, levels=1, iters=iters, rs_r0=r0, rs_samples=rs, fmax=fmax, dmax=dmax)
+    _say("match sift", case)
+    hyp = dev(hyp0)
+    cost = sff.sff_match_sift(p, dev(phi32), dev(seeds), hyp)
+    torch.cuda.synchronize()
+    hg, cg = hyp.cpu().numpy(), cost.cpu().numpy()
+    for di, s in enumerate((1, -1)):
+        for b in range(B):
+            h, c = oracle.match_sift(phi32[b], hyp0[di, b], s, int(seeds[b]), iters, r0, rs, fmax, dmax)
+            assert np.array_equal(hg[di, b], h), (case, s, b)
+            assert np.array_equal(cg[di, b], c), (case, s, b)
+
+
+def test_match_sift_kitti_size(sff):
+    """The KITTI-size pair: the oracle's features and its own WHT matching
+    result as the start, two iterations, both fields, bit-exact."""
+    import torch
+    sc = make_scene(kitti_spec())
+    p = dict(kitti_params())
+    p["iters"] = 2
+    imgs = sc.stack()
+    _say("match sift kitti: oracle features and start")
+    phi32 = np.zeros((1, 4, p["H"], p["W"], 4), np.float32)
+    phi32[0, ..., :3] = sp.sift_pca_features(imgs)["phi"]
+    ref = oracle.match_pair(imgs, kitti_params(), 2)
+    hyp0 = np.stack([ref["hyp"][0], ref["hyp"][1]])[:, None]
+    hyp = dev(hyp0)
+    _say("match sift kitti: gpu")
+    cost = sff.sff_match_sift(p, dev(phi32), dev(np.array([2], np.int64)), hyp)
+    torch.cuda.synchronize()
+    hg, cg = hyp.cpu().numpy(), cost.cpu().numpy()
+    for di, s in enumerate((1, -1)):
+        _say("match sift kitti: oracle", s)
+        h, c = oracle.match_sift(phi32[0], hyp0[di, 0], s, 2, 2, p["rs_r0"], p["rs_samples"], p["fmax"],
+                                 p["dmax"])
+        assert np.array_equal(hg[di, 0], h), s
+        assert np.array_equal(cg[di, 0], c), s
+
+
+def test_pipeline_refine_sift(sff):
+    """PairMatcher.refine_sift after a run: every pixel's cost is at most the
+    SIFT-PCA cost of its starting vector, and the stored cost is the cost of
+    the final field (same arithmetic as sff_cost_sift)."""
+    import torch
+    from sff_inputs import tiny_params, tiny_spec
+    sc = make_scene(tiny_spec())
+    p = tiny_params()
+    imgs = dev(sc.stack()[None])
+    seeds = dev(np.array([1], np.int64))
+    _say("pipeline refine sift")
+    m = sff.PairMatcher(p, 1)
+    m.run(imgs, seeds)
+    start = m.hyp[0].clone()
+    feats = sff.sff_sift_pca(p, imgs)
+    c0 = [sff.sff_cost_sift(p, feats["phi"], start[d], d_) for d, d_ in ((0, 1), (1, -1))]
+    out = m.refine_sift(imgs, seeds)
+    torch.cuda.synchronize()
+    for d, d_ in ((0, 1), (1, -1)):
+        c = out["cost"][d]
+        assert torch.all(c <= c0[d])
+        assert torch.equal(c, sff.sff_cost_sift(p, feats["phi"], out["hyp"][d], d_))
+    assert out["valid"].sum().item() > 0
