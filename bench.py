@@ -202,7 +202,22 @@ def sift_stage(p, m, imgs, steps: int) -> dict:
         t_c += ev[1].elapsed_time(ev[2])
     t_f, t_c = t_f / steps, t_c / steps
     npx = B * p["H"] * p["W"]
+    # one full-resolution iteration of matching with this cost (both fields),
+    # from the matched field (on a copy)
+    seeds = torch.arange(B, dtype=torch.int64, device=imgs.device) + 2
+    hyp2 = m.hyp[0].clone()
+    sff.sff_match_sift(p, out["phi"], seeds, hyp2, iters=1)
+    torch.cuda.synchronize()
+    t_m = 0.0
+    for _ in range(steps):
+        hyp2.copy_(m.hyp[0])
+        ev[0].record(st)
+        sff.sff_match_sift(p, out["phi"], seeds, hyp2, iters=1)
+        ev[1].record(st)
+        ev[1].synchronize()
+        t_m += ev[0].elapsed_time(ev[1])
     return {"features_ms": t_f, "cost_ms": t_c, "cost_evals_per_s": npx / (t_c * 1e-3),
+            "match_iter_ms": t_m / steps,
             "eigval": [round(float(v), 6) for v in out["eigval"][0].tolist()]}
 
 
