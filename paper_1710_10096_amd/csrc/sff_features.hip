@@ -135,25 +135,40 @@ __device__ __forceinline__ void wht4(int& x0, int& x1, int& x2, int& x3) {
 // (replicated border), is staged in LDS with coalesced loads; each thread
 // forms its pixel's bin sums from LDS; the coefficients are staged in LDS
 // again so every wave stores its row of 64 descriptors as one contiguous run.
-constexpr int kTW = 64, kTH = 4;
+constexpr int kTW = 64;
+// Output rows per block: 16 for n <= 4, so that the 7n-pixel halo of the
+// staged source region is shared by more rows; 4 beyond (the region would not
+// fit in LDS).
+template <int n>
+constexpr int wht_rows() { return n <= 4 ? 16 : 4; }
+inline int wht_rows_rt(int n) { return n <= 4 ? 16 : 4; }
+
+// Order LDS accesses of different lanes of one wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // n (the pyramid factor) is a template parameter so that every LDS offset
 // of the bin sums is an immediate.
 template <int C, int n>
 __global__ void __launch_bounds__(256) wht_kernel(const uint8_t* __restrict__ S,
                                                   int16_t* __restrict__ desc, int H, int W) {
+    constexpr int TH = wht_rows<n>();
     extern __shared__ uint8_t smem[];
-    const int RW = kTW + 7 * n, RH = kTH + 7 * n;
-    uint8_t* reg = smem;                                                   // [RH][RW][C]
-    int16_t* out = reinterpret_cast<int16_t*>(smem + ((RH * RW * C + 15) & ~15));  // [kTH][kTW][16C]
-    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH, m = blockIdx.z;
+    const int RW = kTW + 7 * n, RH = TH + 7 * n;
+    const int wv = wave_id(), ln = threadIdx.x & 63;
+    uint8_t* reg = smem;  // [RH][RW][C]
+    // this wave's row of 64 descriptors [kTW][16C]
+    int16_t* outw = reinterpret_cast<int16_t*>(smem + ((RH * RW * C + 15) & ~15)) + wv * kTW * 16 * C;
+    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * TH, m = blockIdx.z;
     const uint8_t* src = S + (size_t)m * H * W * C;
     const int gx0 = x0 - 3 * n, gy0 = y0 - 3 * n;
     const int rowb = RW * C;
     // wave w stages region rows w, w + 4, ...; lanes walk the row's bytes
     // (only divisions by the compile-time channel count)
     {
-        const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
         const bool inner = gx0 >= 0 && gx0 + RW <= W;  // no column clamping (block-uniform)
         for (int ry = wv; ry < RH; ry += 4) {
             const uint8_t* srow = src + (size_t)clampi(gy0 + ry, 0, H - 1) * W * C;
@@ -170,43 +185,48 @@ __global__ void __launch_bounds__(256) wht_kernel(const uint8_t* __restrict__ S,
         }
     }
     __syncthreads();
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    int16_t* o = out + (ty * kTW + tx) * 16 * C;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        int B[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const uint8_t* r0 = reg + ((ty + 2 * a * n) * RW + tx) * C + c;
-            const uint8_t* r1 = r0 + n * RW * C;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int c0 = 2 * b * n * C, c1 = c0 + n * C;
-                B[a][b] = (int)r0[c0] + (int)r0[c1] + (int)r1[c0] + (int)r1[c1];
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a) wht4(B[a][0], B[a][1], B[a][2], B[a][3]);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) wht4(B[0][b], B[1][b], B[2][b], B[3][b]);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) o[c * 16 + a * 4 + b] = (int16_t)B[a][b];
-    }
-    __syncthreads();
-    // wave ty stores row y0 + ty: 64 descriptors, 2 C 16-byte chunks each, at
-    // a record stride of 2 Cp chunks (padding chunks are not written)
-    const int y = y0 + ty;
-    if (y >= H) return;
     constexpr int P = 2 * C, RS = 2 * kRecC<C>;
+    const int tx = ln;
     const int npx = min(kTW, W - x0);
-    const int chunks = npx * P;
-    const uint4* srow = reinterpret_cast<const uint4*>(out + ty * kTW * 16 * C);
-    uint4* drow = reinterpret_cast<uint4*>(desc) + (((size_t)m * H + y) * W + x0) * RS;
-    for (int k = tx; k < chunks; k += 64) {
-        const int px = k / P;
-        drow[px * RS + (k - px * P)] = srow[k];
+    int16_t* o = outw + tx * 16 * C;
+    // wave w computes rows w, w + 4, ...: one descriptor per lane, staged in
+    // the wave's LDS row so that the wave stores a contiguous row
+    for (int ty = wv; ty < TH; ty += 4) {
+        const int y = y0 + ty;
+        if (y >= H) break;  // whole wave
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            int B[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const uint8_t* r0 = reg + ((ty + 2 * a * n) * RW + tx) * C + c;
+                const uint8_t* r1 = r0 + n * RW * C;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int c0 = 2 * b * n * C, c1 = c0 + n * C;
+                    B[a][b] = (int)r0[c0] + (int)r0[c1] + (int)r1[c0] + (int)r1[c1];
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) wht4(B[a][0], B[a][1], B[a][2], B[a][3]);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) wht4(B[0][b], B[1][b], B[2][b], B[3][b]);
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) o[c * 16 + a * 4 + b] = (int16_t)B[a][b];
+        }
+        wave_lds_sync();
+        // 64 descriptors, 2 C 16-byte chunks each, at a record stride of 2 Cp
+        // chunks (padding chunks are not written)
+        const int chunks = npx * P;
+        const uint4* srow = reinterpret_cast<const uint4*>(outw);
+        uint4* drow = reinterpret_cast<uint4*>(desc) + (((size_t)m * H + y) * W + x0) * RS;
+        for (int k = tx; k < chunks; k += 64) {
+            const int px = k / P;
+            drow[px * RS + (k - px * P)] = srow[k];
+        }
+        wave_lds_sync();
     }
 }
 
@@ -223,8 +243,8 @@ void launch_wht(int n, dim3 grid, size_t smem, hipStream_t st, const uint8_t* sr
 }
 
 inline size_t wht_smem(int n, int C) {
-    const int RW = kTW + 7 * n, RH = kTH + 7 * n;
-    return ((size_t)(RH * RW * C + 15) & ~(size_t)15) + (size_t)kTH * kTW * 16 * C * sizeof(int16_t);
+    const int RW = kTW + 7 * n, RH = wht_rows_rt(n) + 7 * n;
+    return ((size_t)(RH * RW * C + 15) & ~(size_t)15) + (size_t)4 * kTW * 16 * C * sizeof(int16_t);
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -296,7 +316,7 @@ extern "C" sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_
                       ws + L.s_off, st);
         src = ws + L.s_off;
     }
-    const dim3 grid((W + kTW - 1) / kTW, (H + kTH - 1) / kTH, nimg);
+    const dim3 grid((W + kTW - 1) / kTW, (H + wht_rows_rt(g.n) - 1) / wht_rows_rt(g.n), nimg);
     switch (C) {
         case 1: launch_wht<1>(g.n, grid, smem, st, src, desc, H, W); break;
         case 2: launch_wht<2>(g.n, grid, smem, st, src, desc, H, W); break;
