@@ -149,6 +149,9 @@ LEVEL_CASES = [
     ("odd_sizes", 17, 9, 2, 2, 1, 5, 6, 1),
     ("c4_handoff", 29, 53, 4, 2, 0, 2, 6, 1),
     ("wide_c3", 11, 300, 3, 1, 0, 2, 6, 1),
+    # sample counts that are not multiples of the cooperative group of three
+    ("rs5_c3", 33, 70, 3, 1, 0, 2, 5, 1),
+    ("rs1", 20, 40, 1, 2, 0, 2, 1, 2),
 ]
 
 
