@@ -1,0 +1,60 @@
+"""Host logic of bench.py: the algorithmic-byte and evaluation-count models
+against their closed forms for the KITTI-size workload, the counter-file
+lookup (reported only while the kernel sources hash the same), and the
+one-GPU guard."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from sff_inputs import kitti_params  # noqa: E402
+
+
+def test_algorithmic_bytes_kitti():
+    p = kitti_params()
+    b = bench.algorithmic_bytes(p)
+    H, W, C = 375, 1242, 3
+    N = [465750, 621 * 188, 311 * 94]                 # grid pixels of levels 0, 1, 2
+    assert b["features"] == 4 * 3 * H * W * 33 * C
+    assert b["iterations"] == 2 * sum(N) * 6 * (128 * C + 32)
+    assert b["handoff"] == 2 * (N[0] + N[1]) * (20 + 128 * C)
+    assert b["init"] == 2 * N[2] * (128 * C + 12)
+    assert b["consistency"] == H * W * 21
+    assert b["total"] == sum(v for k, v in b.items() if k != "total")
+    assert abs(b["total"] / 4.11e9 - 1) < 0.002
+
+
+def test_eval_count_kitti():
+    p = kitti_params()
+    per_dir = 0
+    for Hk, Wk in ((375, 1242), (188, 621), (94, 311)):
+        N = Hk * Wk
+        per_dir += 6 * ((4 * N - 2 * (Hk + Wk)) + 6 * N) + N
+    assert bench.eval_count(p) == 2 * per_dir
+    # 4 neighbours + 6 samples for every pixel and iteration, plus one joint cost
+    # per pixel, is 61 * sum N = 37,315,652; the grid border lacks
+    # 6 * 2 * sum (Hk + Wk) neighbours
+    assert per_dir == 37_315_652 - 6 * 2 * (375 + 1242 + 188 + 621 + 94 + 311)
+
+
+def test_measured_traffic_needs_matching_sources(tmp_path):
+    f = tmp_path / "c.txt"
+    h = bench.kernel_source_hash()
+    f.write_text(f"x\nTRAFFIC kernel=half_step_kernel workload=kitti bytes_per_launch=123 sources={h}\n")
+    assert bench.measured_traffic(str(f), "half_step_kernel", "kitti") == 123.0
+    assert bench.measured_traffic(str(f), "half_step_kernel", "tiny") is None
+    f.write_text("TRAFFIC kernel=half_step_kernel workload=kitti bytes_per_launch=123 sources=0000\n")
+    assert bench.measured_traffic(str(f), "half_step_kernel", "kitti") is None
+    assert bench.measured_traffic(str(tmp_path / "missing.txt"), "half_step_kernel", "kitti") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
