@@ -60,7 +60,7 @@ def test_status_strings_and_version():
     assert L.sff_status_string(0) == b"ok"
     assert L.sff_status_string(1) == b"invalid argument"
     assert L.sff_status_string(99) == b"unknown status"
-    assert L.sff_version() >= 200
+    assert L.sff_version() >= 300
 
 
 def test_descriptor_record_channels():
