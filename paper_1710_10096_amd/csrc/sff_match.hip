@@ -70,7 +70,11 @@ __device__ __forceinline__ void wave_sync() {
 // records (each inside one cache line) instead of 64 unrelated lines.  Each
 // lane keeps the reference pieces of its (o, w) slots in registers, forms the
 // piece's partial squared distance, and the P partials of an owner are summed
-// through the wave's LDS slice.
+// through the wave's LDS slice.  Gathers are buffer loads with 32-bit byte
+// offsets from the map's base (one add per load instead of 64-bit address
+// arithmetic), so a map must be smaller than 2 GiB.  Owners without a target
+// (tp < 0) gather record 0 and have their sum zeroed once, after the
+// reduction, instead of each piece being predicated.
 template <int C>
 struct Coop {
     static constexpr int P = 2 * C;
@@ -81,6 +85,21 @@ struct Coop {
 
     __device__ __forceinline__ static int owner(int k, int lane) { return (64 * k + lane) / P; }
     __device__ __forceinline__ static int piece(int k, int lane) { return (64 * k + lane) % P; }
+
+    // Raw buffer descriptor of a map (wave-uniform base; offsets below 2^31).
+    // The base words are zero-extended: readfirstlane returns int.
+    __device__ __forceinline__ static __amdgpu_buffer_rsrc_t map_rsrc(const uint4* M) {
+        const uint64_t p = reinterpret_cast<uint64_t>(M);
+        const uint64_t u = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)p) |
+                           ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(p >> 32)) << 32);
+        return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(u), (short)0, 0x7FFFFFFF, 0x00020000);
+    }
+
+    // Piece (k, lane) of the record at byte offset ob of the slot's owner.
+    __device__ __forceinline__ uint4 gather(__amdgpu_buffer_rsrc_t rs, int ob, int k) const {
+        const int off = __shfl(ob, owner(k, lane)) + piece(k, lane) * 16;
+        return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    }
 
     // Load the reference pieces; pix_of(o) is owner o's pixel in map R.
     template <class F>
@@ -93,48 +112,46 @@ struct Coop {
     // Squared distance between each owner's reference descriptor and the
     // descriptor of pixel tp in map M (0 for owners passing tp < 0).  Must be
     // called by all lanes of the wave.
-    __device__ __forceinline__ uint32_t ssd(const uint4* __restrict__ M, int tp) {
-        int t[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) t[k] = __shfl(tp, owner(k, lane));
+    __device__ __forceinline__ uint32_t ssd(const uint4* M, int tp) {
+        const __amdgpu_buffer_rsrc_t rs = map_rsrc(M);
+        const int ob = max(tp, 0) * (RS * 16);
         uint4 v[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) v[k] = M[(size_t)max(t[k], 0) * RS + piece(k, lane)];
+        for (int k = 0; k < P; ++k) v[k] = gather(rs, ob, k);
 #pragma unroll
-        for (int k = 0; k < P; ++k) part[64 * k + lane] = t[k] >= 0 ? (uint32_t)piece_ssd(refp[k], v[k], 0) : 0u;
+        for (int k = 0; k < P; ++k) part[64 * k + lane] = (uint32_t)piece_ssd(refp[k], v[k], 0);
         wave_sync();
         uint32_t c = 0;
 #pragma unroll
         for (int w = 0; w < P; ++w) c += part[lane * P + w];
         wave_sync();
-        return c;
+        return tp >= 0 ? c : 0u;
     }
 
     // ssd for N targets per owner at once (all gathers in flight together);
     // needs a slice of N * 64 P words.
     template <int N>
-    __device__ __forceinline__ void ssdN(const uint4* __restrict__ M, const int (&tp)[N], uint32_t (&c)[N]) {
-        int t[N][P];
+    __device__ __forceinline__ void ssdN(const uint4* M, const int (&tp)[N], uint32_t (&c)[N]) {
+        const __amdgpu_buffer_rsrc_t rs = map_rsrc(M);
+        int ob[N];
 #pragma unroll
-        for (int m = 0; m < N; ++m)
-#pragma unroll
-            for (int k = 0; k < P; ++k) t[m][k] = __shfl(tp[m], owner(k, lane));
+        for (int m = 0; m < N; ++m) ob[m] = max(tp[m], 0) * (RS * 16);
         uint4 v[N][P];
 #pragma unroll
         for (int m = 0; m < N; ++m)
 #pragma unroll
-            for (int k = 0; k < P; ++k) v[m][k] = M[(size_t)max(t[m][k], 0) * RS + piece(k, lane)];
+            for (int k = 0; k < P; ++k) v[m][k] = gather(rs, ob[m], k);
 #pragma unroll
         for (int m = 0; m < N; ++m)
 #pragma unroll
-            for (int k = 0; k < P; ++k)
-                part[64 * (m * P + k) + lane] = t[m][k] >= 0 ? (uint32_t)piece_ssd(refp[k], v[m][k], 0) : 0u;
+            for (int k = 0; k < P; ++k) part[64 * (m * P + k) + lane] = (uint32_t)piece_ssd(refp[k], v[m][k], 0);
         wave_sync();
 #pragma unroll
         for (int m = 0; m < N; ++m) {
             c[m] = 0;
 #pragma unroll
             for (int w = 0; w < P; ++w) c[m] += part[64 * P * m + lane * P + w];
+            c[m] = tp[m] >= 0 ? c[m] : 0u;
         }
         wave_sync();
     }
@@ -279,21 +296,23 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // hand-off (own from the coarse field, neighbours already at this level);
 // 3 = hand-off only (no propagation or search), used when iters == 0.
 //
-// Block = 4 waves, one grid row each, 64 pixels of the half-step's colour per
-// wave (all pixels for mode 3).  Lanes past the row's end stay in the wave
-// (for the cooperative gathers) without a pixel of their own.
+// Block = one wave: 64 pixels of the half-step's colour in one grid row (all
+// pixels for mode 3).  Lanes past the row's end stay in the wave (for the
+// cooperative gathers) without a pixel of their own.  One-wave blocks let a
+// finished wave's slot be refilled at once; the early-out makes wave times
+// uneven (level 0 of the KITTI-size pair: 1.459 vs 1.482 ms per step with
+// four-row blocks, level 2: 0.262 vs 0.286 ms).
 template <int C, class E>
-__global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int colour, int mode,
-                                                        int tiles_x, int tiles_y) {
-    __shared__ uint32_t part_lds[4][E::kLdsWords];
+__global__ void __launch_bounds__(64) half_step_kernel(MatchArgs a, int it, int colour, int mode,
+                                                       int tiles_x, int tiles_y) {
+    __shared__ uint32_t part_lds[E::kLdsWords];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int per_field = tiles_x * tiles_y;
     const int z = tile / per_field;
     const int tr = tile - z * per_field;
     const int tx = tr / tiles_y, ty = tr - tx * tiles_y;
-    const int lane = threadIdx.x & 63, wv = wave_id();
-    const int i = ty * 4 + wv;
-    if (i >= a.Hk) return;  // whole wave
+    const int lane = threadIdx.x;
+    const int i = ty;
     const int par = mode == 3 ? 0 : ((i + colour) & 1);
     const int step = mode == 3 ? 1 : 2;
     const int j = step * (tx * 64 + lane) + par;
@@ -314,7 +333,7 @@ __global__ void __launch_bounds__(256) half_step_kernel(MatchArgs a, int it, int
     const int x = n * min(j, a.Wk - 1), y = n * i;
     {
         const int j0 = step * tx * 64 + par, W = a.W, Wk1 = a.Wk - 1;
-        V.init(R, x, y, lane, part_lds[wv], [=](int o) { return y * W + n * min(j0 + step * o, Wk1); });
+        V.init(R, x, y, lane, part_lds, [=](int o) { return y * W + n * min(j0 + step * o, Wk1); });
     }
 
     const size_t field_off = (size_t)z * a.Hk * a.Wk;
@@ -458,8 +477,8 @@ constexpr long kCoopMinUpdates = 65536;
 template <int C, class E>
 sff_status launch_level(const MatchArgs& a, int iters, hipStream_t st) {
     const int nz = a.ndir * a.batch;
-    const int tiles_y = (a.Hk + 3) / 4;
-    const dim3 block(256);
+    const int tiles_y = a.Hk;
+    const dim3 block(64);
     if (a.hyp_coarse && iters == 0) {
         const int tiles_x = (a.Wk + 63) / 64;
         hipLaunchKernelGGL((half_step_kernel<C, E>), dim3(tiles_x * tiles_y * nz), block, 0, st, a,
@@ -484,6 +503,9 @@ sff_status launch_level(const MatchArgs& a, int iters, hipStream_t st) {
 // against 2/3; one candidate at a time 1.71 and 0.47 ms).
 constexpr long kWideMinUpdates = 262144;
 
+// Largest descriptor map (bytes) the cooperative evaluators address.
+constexpr size_t kMaxCoopMapBytes = 0x7FFFFFFF;
+
 // SFF_MATCH_EVAL = "lane", "coop" (group sizes by size), "coop-narrow" or
 // "coop-wide" forces an evaluator (all give identical results; the switch
 // exists to test and time each one); anything else: auto.
@@ -497,6 +519,8 @@ sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
         if (std::strcmp(e, "coop-narrow") == 0) coop = true, wide = false;
         if (std::strcmp(e, "coop-wide") == 0) coop = true, wide = true;
     }
+    // The cooperative gathers address a map with 32-bit offsets.
+    if ((size_t)a.H * a.W * Coop<C>::RS * 16 > kMaxCoopMapBytes) coop = false;
     if (!coop) return launch_level<C, LaneEval<C>>(a, iters, st);
     if (wide) return launch_level<C, CoopEval<C, 4, 3>>(a, iters, st);
     return launch_level<C, CoopEval<C, 2, 3>>(a, iters, st);
