@@ -169,9 +169,12 @@ sff_status sff_init_nn_leaves(const sff_params* p, int32_t batch, int32_t dir, i
  *   must not overlap hyp.
  * hyp/cost: level-k field, read and written in place.
  * Two kernels with identical results gather the descriptors: one lane per
- *   pixel for small levels, wave-cooperative loads otherwise; the environment
- *   variable SFF_MATCH_EVAL=lane|coop|coop-narrow|coop-wide forces one (testing
- *   and timing).
+ *   pixel below 20000 pixel updates per launch (ndir * batch * H(k) *
+ *   ceil(W(k) / 2)), wave-cooperative loads otherwise; the environment variable
+ *   SFF_MATCH_EVAL=lane|coop|coop-narrow|coop-wide forces one (testing and
+ *   timing).  The cooperative loads use 32-bit offsets: for descriptor maps of
+ *   2 GiB or more (H * W > 16.7 M at C = 3 or 4) the per-lane kernel runs
+ *   whatever the variable says.
  * Errors: SFF_ERR_INVALID_ARG (also for level >= levels - 1 with a non-NULL
  *   hyp_coarse, and for overlapping hyp/hyp_coarse). */
 sff_status sff_match_level(const sff_params* p, int32_t batch, int32_t dir, int32_t level,

@@ -469,10 +469,12 @@ __global__ void __launch_bounds__(64) half_step_kernel(MatchArgs a, int it, int 
     }
 }
 
-// Below this many pixel updates per launch (about one wave per SIMD) the chip
-// is not full and each wave's chain of dependent gathers sets the time; the
-// per-lane evaluator has the shorter chain there.
-constexpr long kCoopMinUpdates = 65536;
+// Below this many pixel updates per launch (about a third of a wave per SIMD)
+// each wave's chain of dependent gathers sets the time and the per-lane
+// evaluator has the shorter chain.  Above it the cooperative one wins even
+// with the chip far from full: level 2 of the KITTI-size pair (29,328 updates)
+// takes 0.232 ms per step with it and 0.261 ms per lane.
+constexpr long kCoopMinUpdates = 20000;
 
 template <int C, class E>
 sff_status launch_level(const MatchArgs& a, int iters, hipStream_t st) {
