@@ -170,9 +170,10 @@ sff_status sff_init_nn_leaves(const sff_params* p, int32_t batch, int32_t dir, i
  * hyp/cost: level-k field, read and written in place.
  * Two kernels with identical results gather the descriptors: one lane per
  *   pixel below 20000 pixel updates per launch (ndir * batch * H(k) *
- *   ceil(W(k) / 2)), wave-cooperative loads otherwise; the environment variable
- *   SFF_MATCH_EVAL=lane|coop|coop-narrow|coop-wide forces one (testing and
- *   timing).  The cooperative loads use 32-bit offsets: for descriptor maps of
+ *   ceil(W(k) / 2)), wave-cooperative loads otherwise (32 pixels per wave below
+ *   50000 updates, 64 above); the environment variable SFF_MATCH_EVAL=lane|
+ *   coop|coop-narrow|coop-wide|coop-narrow-32|coop-wide-32 forces one (testing
+ *   and timing).  The cooperative loads use 32-bit offsets: for descriptor maps of
  *   2 GiB or more (H * W > 16.7 M at C = 3 or 4) the per-lane kernel runs
  *   whatever the variable says.
  * Errors: SFF_ERR_INVALID_ARG (also for level >= levels - 1 with a non-NULL

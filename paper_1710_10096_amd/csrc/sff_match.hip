@@ -74,12 +74,17 @@ __device__ __forceinline__ void wave_sync() {
 // offsets from the map's base (one add per load instead of 64-bit address
 // arithmetic), so a map must be smaller than 2 GiB.  Owners without a target
 // (tp < 0) gather record 0 and have their sum zeroed once, after the
-// reduction, instead of each piece being predicated.
-template <int C>
+// reduction, instead of each piece being predicated.  A wave has O owners
+// (64, or 32 to put twice as many waves on a level too small to fill the chip;
+// lanes O..63 then only help gather), so a descriptor gather is K = O P / 64
+// wave-wide loads.
+template <int C, int O>
 struct Coop {
+    static_assert(O == 64 || O == 32, "owners per wave");
     static constexpr int P = 2 * C;
+    static constexpr int K = O * P / 64;
     static constexpr int RS = 2 * kRecC<C>;  // record stride in 16-byte pieces
-    uint4 refp[P];                          // reference piece of slot k
+    uint4 refp[K];                          // reference piece of slot k
     uint32_t* part;                         // this wave's LDS slice [64 P]
     int lane;
 
@@ -105,7 +110,7 @@ struct Coop {
     template <class F>
     __device__ __forceinline__ void load_ref(const uint4* __restrict__ R, F pix_of) {
 #pragma unroll
-        for (int k = 0; k < P; ++k)
+        for (int k = 0; k < K; ++k)
             refp[k] = R[(size_t)pix_of(owner(k, lane)) * RS + piece(k, lane)];
     }
 
@@ -115,42 +120,44 @@ struct Coop {
     __device__ __forceinline__ uint32_t ssd(const uint4* M, int tp) {
         const __amdgpu_buffer_rsrc_t rs = map_rsrc(M);
         const int ob = max(tp, 0) * (RS * 16);
-        uint4 v[P];
+        uint4 v[K];
 #pragma unroll
-        for (int k = 0; k < P; ++k) v[k] = gather(rs, ob, k);
+        for (int k = 0; k < K; ++k) v[k] = gather(rs, ob, k);
 #pragma unroll
-        for (int k = 0; k < P; ++k) part[64 * k + lane] = (uint32_t)piece_ssd(refp[k], v[k], 0);
+        for (int k = 0; k < K; ++k) part[64 * k + lane] = (uint32_t)piece_ssd(refp[k], v[k], 0);
         wave_sync();
         uint32_t c = 0;
+        const int ol = lane & (O - 1);  // lanes past the owners read a valid slot
 #pragma unroll
-        for (int w = 0; w < P; ++w) c += part[lane * P + w];
+        for (int w = 0; w < P; ++w) c += part[ol * P + w];
         wave_sync();
         return tp >= 0 ? c : 0u;
     }
 
     // ssd for N targets per owner at once (all gathers in flight together);
-    // needs a slice of N * 64 P words.
+    // needs a slice of N * 64 K words.
     template <int N>
     __device__ __forceinline__ void ssdN(const uint4* M, const int (&tp)[N], uint32_t (&c)[N]) {
         const __amdgpu_buffer_rsrc_t rs = map_rsrc(M);
         int ob[N];
 #pragma unroll
         for (int m = 0; m < N; ++m) ob[m] = max(tp[m], 0) * (RS * 16);
-        uint4 v[N][P];
+        uint4 v[N][K];
 #pragma unroll
         for (int m = 0; m < N; ++m)
 #pragma unroll
-            for (int k = 0; k < P; ++k) v[m][k] = gather(rs, ob[m], k);
+            for (int k = 0; k < K; ++k) v[m][k] = gather(rs, ob[m], k);
 #pragma unroll
         for (int m = 0; m < N; ++m)
 #pragma unroll
-            for (int k = 0; k < P; ++k) part[64 * (m * P + k) + lane] = (uint32_t)piece_ssd(refp[k], v[m][k], 0);
+            for (int k = 0; k < K; ++k) part[64 * (m * K + k) + lane] = (uint32_t)piece_ssd(refp[k], v[m][k], 0);
         wave_sync();
+        const int ol = lane & (O - 1);
 #pragma unroll
         for (int m = 0; m < N; ++m) {
             c[m] = 0;
 #pragma unroll
-            for (int w = 0; w < P; ++w) c[m] += part[64 * P * m + lane * P + w];
+            for (int w = 0; w < P; ++w) c[m] += part[64 * K * m + ol * P + w];
             c[m] = tp[m] >= 0 ? c[m] : 0u;
         }
         wave_sync();
@@ -175,6 +182,7 @@ struct Coop {
 // of the wave.
 template <int C>
 struct LaneEval {
+    static constexpr int kOwners = 64;
     static constexpr int kLdsWords = 1;
     static constexpr int kPG = 1, kRG = 1;
     static constexpr bool kCoop = false;
@@ -206,15 +214,16 @@ struct LaneEval {
 // PG neighbour candidates and RG random-search samples are scored together
 // (their gathers in flight at once); the LDS slice holds the partials of the
 // larger group.
-template <int C, int PG, int RG>
+template <int C, int PG, int RG, int O = 64>
 struct CoopEval {
+    static constexpr int kOwners = O;
     static constexpr int kPG = PG, kRG = RG;
     static constexpr int kGroup = PG > RG ? PG : RG;
-    static constexpr int kLdsWords = kGroup * 64 * Coop<C>::P;
+    static constexpr int kLdsWords = kGroup * 64 * Coop<C, O>::K;
     static constexpr bool kCoop = true;
     const uint4 *T, *S, *X;
     int H, W, s;
-    Coop<C> cp;
+    Coop<C, O> cp;
 
     template <class F>
     __device__ __forceinline__ void init(const uint4* R, int, int, int lane, uint32_t* part, F pix_of) {
@@ -315,11 +324,12 @@ __global__ void __launch_bounds__(64) half_step_kernel(MatchArgs a, int it, int 
     const int i = ty;
     const int par = mode == 3 ? 0 : ((i + colour) & 1);
     const int step = mode == 3 ? 1 : 2;
-    const int j = step * (tx * 64 + lane) + par;
-    const bool act = j < a.Wk;
+    constexpr int O = E::kOwners;
+    const int j = step * (tx * O + lane) + par;
+    const bool act = lane < O && j < a.Wk;
     const int di = z / a.batch, b = z - di * a.batch;
     const int s = (a.ndir == 2) ? (di == 0 ? 1 : -1) : a.dir0;
-    const size_t mapsz = (size_t)a.H * a.W * Coop<C>::RS;  // in 16-byte pieces
+    const size_t mapsz = (size_t)a.H * a.W * Coop<C, 64>::RS;  // in 16-byte pieces
     const uint4* base = reinterpret_cast<const uint4*>(a.desc) + (size_t)b * 4 * mapsz;
     E V;
     V.T = base + (size_t)(s > 0 ? 1 : 2) * mapsz;
@@ -332,7 +342,7 @@ __global__ void __launch_bounds__(64) half_step_kernel(MatchArgs a, int it, int 
     const int n = a.n;
     const int x = n * min(j, a.Wk - 1), y = n * i;
     {
-        const int j0 = step * tx * 64 + par, W = a.W, Wk1 = a.Wk - 1;
+        const int j0 = step * tx * O + par, W = a.W, Wk1 = a.Wk - 1;
         V.init(R, x, y, lane, part_lds, [=](int o) { return y * W + n * min(j0 + step * o, Wk1); });
     }
 
@@ -482,12 +492,12 @@ sff_status launch_level(const MatchArgs& a, int iters, hipStream_t st) {
     const int tiles_y = a.Hk;
     const dim3 block(64);
     if (a.hyp_coarse && iters == 0) {
-        const int tiles_x = (a.Wk + 63) / 64;
+        const int tiles_x = (a.Wk + E::kOwners - 1) / E::kOwners;
         hipLaunchKernelGGL((half_step_kernel<C, E>), dim3(tiles_x * tiles_y * nz), block, 0, st, a,
                            0, 0, 3, tiles_x, tiles_y);
         return launch_status();
     }
-    const int tiles_x = ((a.Wk + 1) / 2 + 63) / 64;
+    const int tiles_x = ((a.Wk + 1) / 2 + E::kOwners - 1) / E::kOwners;
     for (int it = 0; it < iters; ++it)
         for (int colour = 0; colour < 2; ++colour) {
             int mode = 0;
@@ -505,25 +515,39 @@ sff_status launch_level(const MatchArgs& a, int iters, hipStream_t st) {
 // against 2/3; one candidate at a time 1.71 and 0.47 ms).
 constexpr long kWideMinUpdates = 262144;
 
+// Below this many pixel updates per launch a cooperative wave has 32 owners:
+// twice the waves, half the gather registers (level 2 of the KITTI-size pair,
+// 29,328 updates, 564 waves with 64 owners: 0.203 vs 0.236 ms per step;
+// level 1, 116,936 updates: 0.471 vs 0.469 ms; level 0: 1.470 vs 1.442 ms).
+constexpr long kHalfOwnersMaxUpdates = 50000;
+
 // Largest descriptor map (bytes) the cooperative evaluators address.
 constexpr size_t kMaxCoopMapBytes = 0x7FFFFFFF;
 
-// SFF_MATCH_EVAL = "lane", "coop" (group sizes by size), "coop-narrow" or
-// "coop-wide" forces an evaluator (all give identical results; the switch
+// SFF_MATCH_EVAL = "lane", "coop" (group sizes and owners by size),
+// "coop-narrow", "coop-wide" (64 owners) or "coop-narrow-32", "coop-wide-32"
+// (32 owners) forces an evaluator (all give identical results; the switch
 // exists to test and time each one); anything else: auto.
 template <int C>
 sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
     const long updates = (long)a.ndir * a.batch * a.Hk * ((a.Wk + 1) / 2);
     bool coop = updates >= kCoopMinUpdates, wide = updates >= kWideMinUpdates;
+    bool half = updates < kHalfOwnersMaxUpdates;
     if (const char* e = std::getenv("SFF_MATCH_EVAL")) {
         if (std::strcmp(e, "lane") == 0) coop = false;
         if (std::strcmp(e, "coop") == 0) coop = true;
-        if (std::strcmp(e, "coop-narrow") == 0) coop = true, wide = false;
-        if (std::strcmp(e, "coop-wide") == 0) coop = true, wide = true;
+        if (std::strcmp(e, "coop-narrow") == 0) coop = true, wide = false, half = false;
+        if (std::strcmp(e, "coop-wide") == 0) coop = true, wide = true, half = false;
+        if (std::strcmp(e, "coop-narrow-32") == 0) coop = true, wide = false, half = true;
+        if (std::strcmp(e, "coop-wide-32") == 0) coop = true, wide = true, half = true;
     }
     // The cooperative gathers address a map with 32-bit offsets.
-    if ((size_t)a.H * a.W * Coop<C>::RS * 16 > kMaxCoopMapBytes) coop = false;
+    if ((size_t)a.H * a.W * Coop<C, 64>::RS * 16 > kMaxCoopMapBytes) coop = false;
     if (!coop) return launch_level<C, LaneEval<C>>(a, iters, st);
+    if (half) {
+        if (wide) return launch_level<C, CoopEval<C, 4, 3, 32>>(a, iters, st);
+        return launch_level<C, CoopEval<C, 2, 3, 32>>(a, iters, st);
+    }
     if (wide) return launch_level<C, CoopEval<C, 4, 3>>(a, iters, st);
     return launch_level<C, CoopEval<C, 2, 3>>(a, iters, st);
 }

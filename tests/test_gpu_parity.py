@@ -155,12 +155,13 @@ LEVEL_CASES = [
 ]
 
 
-@pytest.mark.parametrize("evaluator", ["lane", "coop-narrow", "coop-wide"])
+@pytest.mark.parametrize("evaluator", ["lane", "coop-narrow", "coop-wide", "coop-narrow-32",
+                                       "coop-wide-32"])
 @pytest.mark.parametrize("case", LEVEL_CASES, ids=[c[0] for c in LEVEL_CASES])
 def test_match_level_parity(sff, case, evaluator, monkeypatch):
     """Every descriptor-gather kernel (per-lane; wave-cooperative scoring 2
-    neighbours and 3 samples, or 4 and 3, at a time) against the oracle;
-    SFF_MATCH_EVAL forces one of them."""
+    neighbours and 3 samples, or 4 and 3, at a time, with 64 or 32 pixels per
+    wave) against the oracle; SFF_MATCH_EVAL forces one of them."""
     import torch
     monkeypatch.setenv("SFF_MATCH_EVAL", evaluator)
     name, H, W, C, levels, level, iters, rs, B = case
@@ -273,7 +274,8 @@ def test_pipeline_ragged_batch_on_side_stream(sff):
         _check_pipeline(sff, scenes, p, [5, 6, 7], stream=st)
 
 
-@pytest.mark.parametrize("evaluator", ["auto", "lane", "coop-narrow", "coop-wide"])
+@pytest.mark.parametrize("evaluator", ["auto", "lane", "coop-narrow", "coop-wide", "coop-narrow-32",
+                                       "coop-wide-32"])
 def test_pipeline_kitti_full(sff, evaluator, monkeypatch):
     monkeypatch.setenv("SFF_MATCH_EVAL", evaluator)
     _say("pipeline kitti 1242x375", evaluator)
