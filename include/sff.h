@@ -335,6 +335,10 @@ sff_status sff_cost_sift(const sff_params* p, int32_t batch, int32_t dir, const 
  * phi: [batch][4][H][W][4] float32 (sff_sift_pca); seeds: [batch] uint64;
  * hyp: [ndir][batch][H][W][4] int16, read and written (ndir = 2 for
  * SFF_DIR_BOTH, forward first); cost: [ndir][batch][H][W] float32, written.
+ * The window gathers are shared by the 64 pixels of a wave (each window
+ * column loaded by one lane, the owner adding its distances in the order
+ * above); SFF_SIFT_EVAL=lane runs the one-lane-per-pixel kernel instead (same
+ * results; testing and timing).
  * Errors: SFF_ERR_INVALID_ARG. */
 sff_status sff_match_sift(const sff_params* p, int32_t batch, int32_t dir, const float* phi,
                           const uint64_t* seeds, int32_t iters, int16_t* hyp, float* cost,

@@ -20,6 +20,8 @@
 // Descriptors are recomputed from the cell-sum planes in the Gram and the
 // projection pass instead of being stored (512 B per pixel).
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 
 #include "sff_internal.hpp"
 
@@ -882,6 +884,199 @@ __global__ void __launch_bounds__(256) sift_half_step_kernel(SiftMatchArgs a, in
     }
 }
 
+// The same half-step with the window gathers shared by the wave (one wave per
+// block, 64 pixels of the colour in one image row).  Per window row, slot
+// f = 64 k + lane (k < 7) serves owner f / 7 at window column f % 7 - 3: it
+// loads that column's R, T, S and X elements (the 7 columns of one owner are
+// consecutive lanes, so a load instruction reads a few contiguous runs instead
+// of 64 scattered elements) and writes the three distances to LDS; the owner
+// then adds its 21 distances in the per-lane kernel's order (column, then
+// temporal, stereo, cross), so every sum is the same FP32 value, and stops
+// after the first row whose partial sum reaches the bound.
+constexpr int kSiftSlots = 2 * kWinR + 1;           // slot loads per window row
+constexpr int kDistStride = 3 * kSiftSlots + 3;     // 24 floats per owner in LDS
+
+__device__ __forceinline__ void sift_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct SiftCoop {
+    SiftViews V;
+    float* dist;              // this wave's LDS [64][kDistStride]
+    int lane, y;
+    int so[kSiftSlots];       // owner of slot k
+    int sx[kSiftSlots];       // x of the slot's window column (owner's x + offset)
+    int sd[kSiftSlots];       // LDS word of the slot's first distance
+
+    // Eq. (1) of each owner's (u, v, d0, d1) at its pixel (x_o, y), the same
+    // value as sift_cost_below (>= bound once a row's partial sum reaches it).
+    // want = false: no candidate, result meaningless.  Called by all lanes.
+    __device__ __forceinline__ float cost_below(bool want, short4 h, float bound) const {
+        const int H = V.H, W = V.W, s = V.s;
+        const uint32_t uv = (uint32_t)(uint16_t)h.x | ((uint32_t)(uint16_t)h.y << 16);
+        const uint32_t dd = (uint32_t)(uint16_t)h.z | ((uint32_t)(uint16_t)h.w << 16);
+        int su[kSiftSlots], svv[kSiftSlots], sd0[kSiftSlots], sd1[kSiftSlots];
+#pragma unroll
+        for (int k = 0; k < kSiftSlots; ++k) {
+            const uint32_t a = (uint32_t)__shfl((int)uv, so[k]), b = (uint32_t)__shfl((int)dd, so[k]);
+            su[k] = (int)(int16_t)(a & 0xFFFFu);
+            svv[k] = (int)(int16_t)(a >> 16);
+            sd0[k] = (int)(int16_t)(b & 0xFFFFu);
+            sd1[k] = (int)(int16_t)(b >> 16);
+        }
+        float sum = 0.f;
+        bool alive = want;
+        for (int wy = -kWinR; wy <= kWinR; ++wy) {
+            if (!__any(alive)) break;
+            const int py = clampi(y + wy, 0, H - 1);
+#pragma unroll
+            for (int k = 0; k < kSiftSlots; ++k) {
+                if (__shfl((int)alive, so[k])) {
+                    const int pyv = clampi(y + wy + svv[k], 0, H - 1);
+                    const int px = sx[k];
+                    const float4 r = V.R[py * W + clampi(px, 0, W - 1)];
+                    const float4 t = V.T[pyv * W + clampi(px + su[k], 0, W - 1)];
+                    const float4 sv = V.S[py * W + clampi(px - s * sd0[k], 0, W - 1)];
+                    const float4 xv = V.X[pyv * W + clampi(px + su[k] - s * sd1[k], 0, W - 1)];
+                    dist[sd[k] + 0] = fdist3(r, t);
+                    dist[sd[k] + 1] = fdist3(r, sv);
+                    dist[sd[k] + 2] = fdist3(r, xv);
+                }
+            }
+            sift_wave_sync();
+            if (alive) {
+                const float* d = dist + lane * kDistStride;
+#pragma unroll
+                for (int e = 0; e < 3 * kSiftSlots; ++e) sum = sum + d[e];
+                alive = sum < bound;
+            }
+            sift_wave_sync();
+        }
+        return sum;
+    }
+};
+
+__global__ void __launch_bounds__(64) sift_half_step_coop_kernel(SiftMatchArgs a, int it, int colour,
+                                                                 int tiles_x) {
+    __shared__ float dist_lds[64 * kDistStride];
+    const int per_field = tiles_x * a.H;
+    const int z = blockIdx.x / per_field;
+    const int tr = blockIdx.x - z * per_field;
+    const int i = tr / tiles_x, tx = tr - i * tiles_x;
+    const int lane = threadIdx.x;
+    const int par = (i + colour) & 1;
+    const int j = 2 * (tx * 64 + lane) + par;
+    const bool act = j < a.W;
+    const int jj = min(j, a.W - 1);
+    const int di = z / a.batch, b = z - di * a.batch;
+    const int s = a.ndir == 2 ? (di == 0 ? 1 : -1) : a.dir0;
+    const size_t npx = (size_t)a.H * a.W;
+    SiftCoop E;
+    E.V = sift_views(a.phi + (size_t)b * 4 * npx, a.H, a.W, s);
+    E.dist = dist_lds;
+    E.lane = lane;
+    E.y = i;
+#pragma unroll
+    for (int k = 0; k < kSiftSlots; ++k) {
+        const int f = 64 * k + lane, o = f / kSiftSlots, c = f - kSiftSlots * o;
+        E.so[k] = o;
+        E.sx[k] = min(2 * (tx * 64 + o) + par, a.W - 1) + c - kWinR;
+        E.sd[k] = o * kDistStride + 3 * c;
+    }
+    short4* field = reinterpret_cast<short4*>(a.hyp) + (size_t)z * npx;
+    float* cost = a.cost + (size_t)z * npx;
+    const size_t o = (size_t)i * a.W + jj;
+    short4 best = field[o];
+    float bestc = cost[o];
+    const short4 own = best;
+    const int ni[4] = {i, i - 1, i, i + 1};
+    const int nj[4] = {jj - 1, jj, jj + 1, jj};
+    short4 nh[4];
+    bool in[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        in[q] = act && ni[q] >= 0 && ni[q] < a.H && nj[q] >= 0 && nj[q] < a.W;
+        nh[q] = in[q] ? field[(size_t)ni[q] * a.W + nj[q]] : own;
+    }
+    auto eq = [](short4 p, short4 q) { return p.x == q.x && p.y == q.y && p.z == q.z && p.w == q.w; };
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        bool dup = eq(nh[q], own);
+#pragma unroll
+        for (int p = 0; p < q; ++p) dup = dup || (in[p] && eq(nh[q], nh[p]));
+        const bool want = in[q] && !dup;
+        if (!__any(want)) continue;
+        const float c = E.cost_below(want, nh[q], bestc);
+        if (want && c < bestc) {
+            bestc = c;
+            best = nh[q];
+        }
+    }
+    const short4 centre = best;
+    const uint64_t seed = a.seeds[b];
+    for (int t = 0; t < a.rs_samples; ++t) {
+        const int r = max(1, a.rs_r0 >> t);
+        U4 ctr;
+        ctr.x = (uint32_t)(i * a.W + jj);
+        ctr.y = (uint32_t)it;
+        ctr.z = (kSiftLevelTag << 16) | ((uint32_t)t << 8) | (s < 0 ? 1u : 0u);
+        ctr.w = 0u;
+        const U4 rnd = philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+        short4 c;
+        c.x = (short)clampi(centre.x + uniform_offset(rnd.x, r), -a.fmax, a.fmax);
+        c.y = (short)clampi(centre.y + uniform_offset(rnd.y, r), -a.fmax, a.fmax);
+        c.z = (short)clampi(centre.z + uniform_offset(rnd.z, r), 0, a.dmax);
+        c.w = (short)clampi(centre.w + uniform_offset(rnd.w, r), 0, a.dmax);
+        const bool want = act && !eq(c, centre);
+        if (!__any(want)) continue;
+        const float cc = E.cost_below(want, c, bestc);
+        if (want && cc < bestc) {
+            bestc = cc;
+            best = c;
+        }
+    }
+    if (act) {
+        field[o] = best;
+        cost[o] = bestc;
+    }
+}
+
+// Eq. (1) at fixed vectors with the wave-shared gathers: 64 consecutive
+// pixels of one row per wave (block), every field z of hyp/cost ([ndir][batch]
+// or [batch]) in one launch; the same values as sift_cost_below.
+__global__ void __launch_bounds__(64) sift_cost_coop_kernel(SiftMatchArgs a, int tiles_x) {
+    __shared__ float dist_lds[64 * kDistStride];
+    const int per_field = tiles_x * a.H;
+    const int z = blockIdx.x / per_field;
+    const int tr = blockIdx.x - z * per_field;
+    const int i = tr / tiles_x, tx = tr - i * tiles_x;
+    const int lane = threadIdx.x;
+    const int j = tx * 64 + lane;
+    const bool act = j < a.W;
+    const int jj = min(j, a.W - 1);
+    const int di = z / a.batch, b = z - di * a.batch;
+    const int s = a.ndir == 2 ? (di == 0 ? 1 : -1) : a.dir0;
+    const size_t npx = (size_t)a.H * a.W;
+    SiftCoop E;
+    E.V = sift_views(a.phi + (size_t)b * 4 * npx, a.H, a.W, s);
+    E.dist = dist_lds;
+    E.lane = lane;
+    E.y = i;
+#pragma unroll
+    for (int k = 0; k < kSiftSlots; ++k) {
+        const int f = 64 * k + lane, o = f / kSiftSlots, c = f - kSiftSlots * o;
+        E.so[k] = o;
+        E.sx[k] = min(tx * 64 + o, a.W - 1) + c - kWinR;
+        E.sd[k] = o * kDistStride + 3 * c;
+    }
+    const size_t o = (size_t)z * npx + (size_t)i * a.W + jj;
+    const short4 h = reinterpret_cast<const short4*>(a.hyp)[o];
+    const float c = E.cost_below(act, h, INFINITY);
+    if (act) a.cost[o] = c;
+}
+
 bool sift_shape_ok(const sff_params* p, int64_t nimg) {
     if (!params_ok(p) || nimg < 1) return false;
     // flattened indices stay below 2^31 in every kernel
@@ -971,9 +1166,25 @@ extern "C" sff_status sff_cost_sift(const sff_params* p, int32_t batch, int32_t 
     if ((reinterpret_cast<uintptr_t>(phi) & 15) != 0 || (reinterpret_cast<uintptr_t>(hyp) & 7) != 0 ||
         (reinterpret_cast<uintptr_t>(cost) & 3) != 0)
         return SFF_ERR_INVALID_ARG;
-    hipLaunchKernelGGL(cost_sift_kernel, dim3((p->W + kCT - 1) / kCT, (p->H + kCT - 1) / kCT, batch),
-                       dim3(256), 0, as_stream(stream), reinterpret_cast<const float4*>(phi), hyp, cost,
-                       p->H, p->W, dir == SFF_DIR_FORWARD ? 1 : -1);
+    const char* e = std::getenv("SFF_SIFT_EVAL");
+    if (e && std::strcmp(e, "lane") == 0) {
+        hipLaunchKernelGGL(cost_sift_kernel, dim3((p->W + kCT - 1) / kCT, (p->H + kCT - 1) / kCT, batch),
+                           dim3(256), 0, as_stream(stream), reinterpret_cast<const float4*>(phi), hyp, cost,
+                           p->H, p->W, dir == SFF_DIR_FORWARD ? 1 : -1);
+        return launch_status();
+    }
+    SiftMatchArgs a{};
+    a.phi = reinterpret_cast<const float4*>(phi);
+    a.hyp = const_cast<int16_t*>(hyp);  // read only by this kernel
+    a.cost = cost;
+    a.H = p->H;
+    a.W = p->W;
+    a.batch = batch;
+    a.ndir = 1;
+    a.dir0 = dir == SFF_DIR_FORWARD ? 1 : -1;
+    const int tiles_x = (p->W + 63) / 64;
+    hipLaunchKernelGGL(sift_cost_coop_kernel, dim3(tiles_x * p->H * batch), dim3(64), 0, as_stream(stream), a,
+                       tiles_x);
     return launch_status();
 }
 
@@ -1005,11 +1216,23 @@ extern "C" sff_status sff_match_sift(const sff_params* p, int32_t batch, int32_t
     const int nz = a.ndir * batch;
     hipStream_t st = as_stream(stream);
     const size_t npx = (size_t)p->H * p->W;
-    hipLaunchKernelGGL(sift_cost_init_kernel, dim3((unsigned)((npx + 255) / 256), nz), dim3(256), 0, st, a);
+    // SFF_SIFT_EVAL=lane forces the per-lane kernels (same results; testing and timing)
+    const char* e = std::getenv("SFF_SIFT_EVAL");
+    const bool lane = e && std::strcmp(e, "lane") == 0;
+    if (lane)
+        hipLaunchKernelGGL(sift_cost_init_kernel, dim3((unsigned)((npx + 255) / 256), nz), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(sift_cost_coop_kernel, dim3(((p->W + 63) / 64) * p->H * nz), dim3(64), 0, st, a,
+                           (p->W + 63) / 64);
     const int tiles_x = ((p->W + 1) / 2 + 63) / 64, tiles_y = (p->H + 3) / 4;
     for (int it = 0; it < iters; ++it)
-        for (int colour = 0; colour < 2; ++colour)
-            hipLaunchKernelGGL(sift_half_step_kernel, dim3(tiles_x * tiles_y * nz), dim3(256), 0, st, a, it,
-                               colour, tiles_x, tiles_y);
+        for (int colour = 0; colour < 2; ++colour) {
+            if (lane)
+                hipLaunchKernelGGL(sift_half_step_kernel, dim3(tiles_x * tiles_y * nz), dim3(256), 0, st, a,
+                                   it, colour, tiles_x, tiles_y);
+            else
+                hipLaunchKernelGGL(sift_half_step_coop_kernel, dim3(tiles_x * p->H * nz), dim3(64), 0, st, a,
+                                   it, colour, tiles_x);
+        }
     return launch_status();
 }

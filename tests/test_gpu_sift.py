@@ -151,11 +151,22 @@ def _cost_fp32_ref(phi32, hyp, s):
     return sp.cost(phi32.astype(np.float64)[..., :3], hyp, s)
 
 
+def _sift_eval(monkeypatch, evaluator):
+    """SFF_SIFT_EVAL=lane forces the per-lane SIFT cost and matching kernels; unset,
+    the wave-shared ones run."""
+    if evaluator == "lane":
+        monkeypatch.setenv("SFF_SIFT_EVAL", "lane")
+    else:
+        monkeypatch.delenv("SFF_SIFT_EVAL", raising=False)
+
+
+@pytest.mark.parametrize("evaluator", ["coop", "lane"])
 @pytest.mark.parametrize("s", [1, -1])
-def test_cost_kernel_on_oracle_features(sff, s):
+def test_cost_kernel_on_oracle_features(sff, s, evaluator, monkeypatch):
     """The cost kernel alone: the oracle's phi rounded to FP32 feeds both sides;
     vectors random in range plus far out of the image."""
     import torch
+    _sift_eval(monkeypatch, evaluator)
     sc = make_scene(small_spec(40, 64, 3, seed=5))
     imgs = sc.stack()
     ref = sp.sift_pca_features(imgs)
@@ -255,9 +266,11 @@ MATCH_CASES = [  # H, W, iters, rs_samples, rs_r0, fmax, dmax, batch
 ]
 
 
+@pytest.mark.parametrize("evaluator", ["coop", "lane"])
 @pytest.mark.parametrize("case", MATCH_CASES, ids=[str(c) for c in MATCH_CASES])
-def test_match_sift_parity(sff, case):
+def test_match_sift_parity(sff, case, evaluator, monkeypatch):
     import torch
+    _sift_eval(monkeypatch, evaluator)
     H, W, iters, rs, r0, fmax, dmax, B = case
     rng = np.random.default_rng(H * 13 + W)
     phis, starts = [], []
@@ -271,7 +284,7 @@ def test_match_sift_parity(sff, case):
     hyp0 = np.stack(starts, axis=1)                       # [2][B][H][W][4]
     seeds = np.array([17 + 5 * b for b in range(B)], np.int64)
     p = params_dict(H, W, 3, levels=1, iters=iters, rs_r0=r0, rs_samples=rs, fmax=fmax, dmax=dmax)
-    _say("match sift", case)
+    _say("match sift", case, evaluator)
     hyp = dev(hyp0)
     cost = sff.sff_match_sift(p, dev(phi32), dev(seeds), hyp)
     torch.cuda.synchronize()
@@ -283,10 +296,12 @@ def test_match_sift_parity(sff, case):
             assert np.array_equal(cg[di, b], c), (case, s, b)
 
 
-def test_match_sift_kitti_size(sff):
+@pytest.mark.parametrize("evaluator", ["coop", "lane"])
+def test_match_sift_kitti_size(sff, evaluator, monkeypatch):
     """The KITTI-size pair: the oracle's features and its own WHT matching
     result as the start, two iterations, both fields, bit-exact."""
     import torch
+    _sift_eval(monkeypatch, evaluator)
     sc = make_scene(kitti_spec())
     p = dict(kitti_params())
     p["iters"] = 2
@@ -297,7 +312,7 @@ def test_match_sift_kitti_size(sff):
     ref = oracle.match_pair(imgs, kitti_params(), 2)
     hyp0 = np.stack([ref["hyp"][0], ref["hyp"][1]])[:, None]
     hyp = dev(hyp0)
-    _say("match sift kitti: gpu")
+    _say("match sift kitti: gpu", evaluator)
     cost = sff.sff_match_sift(p, dev(phi32), dev(np.array([2], np.int64)), hyp)
     torch.cuda.synchronize()
     hg, cg = hyp.cpu().numpy(), cost.cpu().numpy()
