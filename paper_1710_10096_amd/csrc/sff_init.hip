@@ -41,13 +41,23 @@ constexpr int kKBytes = 64;  // MFMA K: 16 C int8 values, zero padded (C <= 4)
 // Split planes of the coarsest-level grid of all four views:
 //   hi[z][p][64], lo[z][p][64] int8 (the split of desc), nhi, nlo (the split
 //   of -desc) and sq[z][p] = |desc|^2, z = pair * 4 + view, p = i * Wk + j.
+// sqx[z][i][wx] holds the same norms with column j at offx + j and the edge
+// values repeated over 16+ columns on either side, so the 4 candidates of a
+// lane (columns c0 + 4g .. c0 + 4g + 3, never beyond -15 .. Wk + 14) are one
+// aligned 16-byte load: offx = 16 + (F mod 4) makes offx + c0 + 4g a multiple
+// of 4 for every tile start c0 = j0 - F + 16 t (j0 a multiple of 16).
 struct SplitPlanes {
     int8_t* hi;
     int8_t* lo;
     int8_t* nhi;
     int8_t* nlo;
     uint32_t* sq;
+    uint32_t* sqx;
+    int wx, offx;
 };
+
+__host__ __device__ inline int sqx_offset(int F) { return 16 + (F & 3); }
+__host__ __device__ inline int sqx_width(int F, int Wk) { return (sqx_offset(F) + Wk + 16 + 3) & ~3; }
 
 template <int C>
 __global__ void __launch_bounds__(256) split_kernel(const int16_t* __restrict__ desc, SplitPlanes P,
@@ -88,6 +98,12 @@ __global__ void __launch_bounds__(256) split_kernel(const int16_t* __restrict__ 
             out[q] = make_uint4(src[4 * q], src[4 * q + 1], src[4 * q + 2], src[4 * q + 3]);
     }
     P.sq[o] = sq;
+    uint32_t* row = P.sqx + ((size_t)z * Hk + i) * P.wx;
+    row[P.offx + j] = sq;
+    if (j == 0)
+        for (int x = 0; x < P.offx; ++x) row[x] = sq;
+    if (j == Wk - 1)
+        for (int x = P.offx + Wk; x < P.wx; ++x) row[x] = sq;
 }
 
 __device__ __forceinline__ v4i load16(const int8_t* p) {
@@ -128,6 +144,7 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
     const int vR = s > 0 ? 0 : 3, vT = s > 0 ? 1 : 2, vS = s > 0 ? 2 : 1, vX = s > 0 ? 3 : 0;
     const size_t Nk = (size_t)Hk * Wk;
     const size_t zR = ((size_t)b * 4 + vR) * Nk, zT = ((size_t)b * 4 + vT) * Nk;
+    const size_t zTx = ((size_t)b * 4 + vT) * Hk;  // row index base in sqx
 
     const int W = a.W;
     const size_t mapsz = (size_t)a.H * W * 16 * kRecC<C>;
@@ -178,8 +195,11 @@ __global__ void __launch_bounds__(256) init_nn_kernel(InitArgs a, SplitPlanes P)
         const size_t oa = rowT + clampi(c0 + nq, 0, Wk - 1);
         T.ah = load16(P.hi + oa * kKBytes + 16 * g);
         T.al = load16(P.lo + oa * kKBytes + 16 * g);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) T.bsq[e] = (int)P.sq[rowT + clampi(c0 + 4 * g + e, 0, Wk - 1)];
+        const uint4 q = *reinterpret_cast<const uint4*>(P.sqx + (zTx + (size_t)r) * P.wx + P.offx + c0 + 4 * g);
+        T.bsq[0] = (int)q.x;
+        T.bsq[1] = (int)q.y;
+        T.bsq[2] = (int)q.z;
+        T.bsq[3] = (int)q.w;
         return T;
     };
     // The scan alternates between two tile buffers (scan_one(a, b) scores a
@@ -428,7 +448,8 @@ void launch_init(int leaves, dim3 grid, hipStream_t st, const InitArgs& a, const
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct InitWs {
-    size_t hi, lo, nhi, nlo, sq, total;
+    size_t hi, lo, nhi, nlo, sq, sqx, total;
+    int wx, offx;
 };
 
 InitWs init_ws(const sff_params& p, int batch) {
@@ -440,7 +461,11 @@ InitWs init_ws(const sff_params& p, int batch) {
     L.nhi = L.lo + align256(cnt * kKBytes);
     L.nlo = L.nhi + align256(cnt * kKBytes);
     L.sq = L.nlo + align256(cnt * kKBytes);
-    L.total = L.sq + align256(cnt * sizeof(uint32_t));
+    L.sqx = L.sq + align256(cnt * sizeof(uint32_t));
+    const int F = p.fmax / g.n;
+    L.offx = sqx_offset(F);
+    L.wx = sqx_width(F, g.Wk);
+    L.total = L.sqx + align256((size_t)batch * 4 * g.Hk * L.wx * sizeof(uint32_t));
     return L;
 }
 
@@ -491,6 +516,9 @@ extern "C" sff_status sff_init_nn_leaves(const sff_params* p, int32_t batch, int
     P.nhi = reinterpret_cast<int8_t*>(ws + L.nhi);
     P.nlo = reinterpret_cast<int8_t*>(ws + L.nlo);
     P.sq = reinterpret_cast<uint32_t*>(ws + L.sq);
+    P.sqx = reinterpret_cast<uint32_t*>(ws + L.sqx);
+    P.wx = L.wx;
+    P.offx = L.offx;
     const int nz4 = 4 * batch;
     const dim3 sgrid((g.Hk * g.Wk + 255) / 256, nz4);
     const dim3 grid((g.Wk + 15) / 16, (g.Hk + kQRows - 1) / kQRows, a.ndir * batch);
