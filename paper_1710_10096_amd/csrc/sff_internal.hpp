@@ -52,6 +52,17 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // ---------------------------------------------------------------- device --
 __device__ __forceinline__ int clampi(int a, int lo, int hi) { return min(max(a, lo), hi); }
 
+// Blocks are dealt to the 8 XCDs round-robin (block id mod 8).  Renumber them
+// so that each XCD receives one contiguous run of tiles (a bijection of
+// [0, nb)); with tiles numbered column-major within a field that run is a
+// vertical strip of the image, whose gather targets (shifted by locally
+// coherent vectors) stay compact and in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+    const int xcd = bid & 7, k = bid >> 3;
+    const int q = nb >> 3, rem = nb & 7;
+    return xcd * q + min(xcd, rem) + k;
+}
+
 // Index of the calling wave (64 lanes) in its block, as a scalar: lets the
 // compiler keep per-wave quantities and branches in scalar registers.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }

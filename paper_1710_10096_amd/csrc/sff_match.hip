@@ -289,17 +289,6 @@ struct CoopEval {
     }
 };
 
-// Blocks are dealt to the 8 XCDs round-robin (block id mod 8).  Renumber them
-// so that each XCD receives one contiguous run of tiles; tiles are numbered
-// column-major within a field, so that run is a vertical strip of the image,
-// whose targets (shifted by the locally coherent vectors) stay compact and in
-// that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int bid, int nb) {
-    const int xcd = bid & 7, k = bid >> 3;
-    const int q = nb >> 3, rem = nb & 7;
-    return xcd * q + min(xcd, rem) + k;
-}
-
 // mode: 0 = regular half-step; 1 = iteration-0 red half after a hand-off (own
 // and neighbours from the coarse field); 2 = iteration-0 black half after a
 // hand-off (own from the coarse field, neighbours already at this level);

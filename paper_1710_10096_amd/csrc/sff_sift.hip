@@ -892,7 +892,10 @@ __global__ void __launch_bounds__(256) sift_half_step_kernel(SiftMatchArgs a, in
 // of 64 scattered elements) and writes the three distances to LDS; the owner
 // then adds its 21 distances in the per-lane kernel's order (column, then
 // temporal, stereo, cross), so every sum is the same FP32 value, and stops
-// after the first row whose partial sum reaches the bound.
+// after the first row whose partial sum reaches the bound.  Tiles are
+// numbered column-major and dealt to the XCDs in vertical strips, which keeps
+// the window gathers of neighbouring tiles in one L2 (KITTI-size pair: one
+// matching iteration 1.72 vs 2.45 ms with tiles dealt in launch order).
 constexpr int kSiftSlots = 2 * kWinR + 1;           // slot loads per window row
 constexpr int kDistStride = 3 * kSiftSlots + 3;     // 24 floats per owner in LDS
 
@@ -962,9 +965,10 @@ __global__ void __launch_bounds__(64) sift_half_step_coop_kernel(SiftMatchArgs a
                                                                  int tiles_x) {
     __shared__ float dist_lds[64 * kDistStride];
     const int per_field = tiles_x * a.H;
-    const int z = blockIdx.x / per_field;
-    const int tr = blockIdx.x - z * per_field;
-    const int i = tr / tiles_x, tx = tr - i * tiles_x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);  // column-major tiles, a strip per XCD
+    const int z = tile / per_field;
+    const int tr = tile - z * per_field;
+    const int tx = tr / a.H, i = tr - tx * a.H;
     const int lane = threadIdx.x;
     const int par = (i + colour) & 1;
     const int j = 2 * (tx * 64 + lane) + par;
@@ -1049,9 +1053,10 @@ __global__ void __launch_bounds__(64) sift_half_step_coop_kernel(SiftMatchArgs a
 __global__ void __launch_bounds__(64) sift_cost_coop_kernel(SiftMatchArgs a, int tiles_x) {
     __shared__ float dist_lds[64 * kDistStride];
     const int per_field = tiles_x * a.H;
-    const int z = blockIdx.x / per_field;
-    const int tr = blockIdx.x - z * per_field;
-    const int i = tr / tiles_x, tx = tr - i * tiles_x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);  // column-major tiles, a strip per XCD
+    const int z = tile / per_field;
+    const int tr = tile - z * per_field;
+    const int tx = tr / a.H, i = tr - tx * a.H;
     const int lane = threadIdx.x;
     const int j = tx * 64 + lane;
     const bool act = j < a.W;
