@@ -487,7 +487,8 @@ __device__ double block_sum(double v, double* red) {
 // covariance has a flat spectrum (neighbouring eigenvalues within a few
 // percent), so plain subspace iteration converges slowly; the iteration runs
 // on M = A^(2^kSquare) instead (same eigenvectors, ratios raised to that
-// power), formed by squarings normalised by the trace.  Subspace iteration with
+// power), formed beforehand by square_kernel (squarings normalised by the
+// trace).  Subspace iteration with
 // kSub vectors: Z = M Q, Q = orth(Z) (Cholesky QR, twice).  Every kCheck-th
 // step multiplies by A itself and does a Rayleigh-Ritz step in span(Q): Ritz
 // pairs of A and their residuals ||A y - theta y|| (A y = Z s); it stops when
@@ -498,37 +499,31 @@ __device__ double block_sum(double v, double* red) {
 // the projection.
 constexpr int kSquare = 5;
 
-__device__ void mat_square(const double* __restrict__ B, double* __restrict__ C, double* red) {
-    // C = B B / trace(B B), thread t: the 8 x 8 block at rows 8 (t / 16), cols 8 (t % 16)
-    const int t = threadIdx.x, rb = 8 * (t >> 4), cb = 8 * (t & 15);
-    double acc[8][8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
-    for (int k = 0; k < kDesc; ++k) {
-        double a[8], b[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            a[i] = B[(size_t)k * kDesc + rb + i];  // B[rb + i][k], B symmetric
-            b[i] = B[(size_t)k * kDesc + cb + i];
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+// One 16 x 16 tile of C = B B / trace(B B) per block, for a symmetric B:
+// trace(B B) = |B|_F^2, summed by every block in the same order (so all tiles
+// share one scale), and C[r][c] = sum_k B[k][r] B[k][c] with the two factors
+// of a term commuting in fma, so C is exactly symmetric again.
+__global__ void __launch_bounds__(256) square_kernel(const double* __restrict__ B_all, size_t b_stride,
+                                                     double* __restrict__ C_all, size_t c_stride) {
+    __shared__ double colr[kDesc][16], colc[kDesc][16];
+    __shared__ double red[256];
+    const int t = threadIdx.x, ti = blockIdx.x >> 3, tj = blockIdx.x & 7;
+    const double* B = B_all + (size_t)blockIdx.y * b_stride;
+    double* C = C_all + (size_t)blockIdx.y * c_stride;
+    double f = 0.0;
+    for (int e = t; e < kDesc * kDesc; e += 256) f = fma(B[e], B[e], f);
+    f = block_sum(f, red);
+    for (int e = t; e < kDesc * 16; e += 256) {
+        const int k = e >> 4, c = e & 15;
+        colr[k][c] = B[(size_t)k * kDesc + 16 * ti + c];
+        colc[k][c] = B[(size_t)k * kDesc + 16 * tj + c];
     }
-    double tr = 0.0;
-    if (rb == cb)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) tr += acc[i][i];
-    tr = block_sum(tr, red);
-    const double sc = tr > 0.0 ? 1.0 / tr : 1.0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) C[(size_t)(rb + i) * kDesc + cb + j] = acc[i][j] * sc;
     __syncthreads();
+    const int r = t >> 4, c = t & 15;
+    double acc = 0.0;
+    for (int k = 0; k < kDesc; ++k) acc = fma(colr[k][r], colc[k][c], acc);
+    const double sc = f > 0.0 ? 1.0 / f : 1.0;
+    C[(size_t)(16 * ti + r) * kDesc + 16 * tj + c] = acc * sc;
 }
 
 __global__ void __launch_bounds__(256) eig_kernel(const double* __restrict__ cov_all,
@@ -544,13 +539,8 @@ __global__ void __launch_bounds__(256) eig_kernel(const double* __restrict__ cov
     double* sq = sq_all + (size_t)pair * 2 * kDesc * kDesc;
     const int r = t & (kDesc - 1), h = t >> 7;  // row and vector half (4 vectors)
 
-    // M = A^(2^kSquare), trace-normalised at each squaring
-    const double* M = A;
-    for (int i = 0; i < kSquare; ++i) {
-        double* C = sq + (size_t)(i & 1) * kDesc * kDesc;
-        mat_square(M, C, red);
-        M = C;
-    }
+    // M = A^(2^kSquare), trace-normalised at each squaring (square_kernel)
+    const double* M = sq + (size_t)((kSquare - 1) & 1) * kDesc * kDesc;
 
     // deterministic pseudo-random start
     for (int i = t; i < kSub * kDesc; i += 256) {
@@ -1155,8 +1145,14 @@ extern "C" sff_status sff_sift_pca(const sff_params* p, int32_t batch, const uin
                        gsum);
     hipLaunchKernelGGL(gram_cov_kernel, dim3(kDesc, batch), dim3(kDesc), 0, st, gsum,
                        1.0 / (4.0 * (double)g.npx), mean, cov);
-    hipLaunchKernelGGL(eig_kernel, dim3(batch), dim3(256), 0, st, cov, mean,
-                       reinterpret_cast<double*>(ws + L.sq), eigval, axes, ax32);
+    double* sqm = reinterpret_cast<double*>(ws + L.sq);  // [batch][2][kDesc][kDesc]
+    for (int i = 0; i < kSquare; ++i) {
+        const double* src = i == 0 ? cov : sqm + (size_t)((i - 1) & 1) * kDesc * kDesc;
+        const size_t src_stride = i == 0 ? (size_t)kDesc * kDesc : (size_t)2 * kDesc * kDesc;
+        hipLaunchKernelGGL(square_kernel, dim3(64, batch), dim3(256), 0, st, src, src_stride,
+                           sqm + (size_t)(i & 1) * kDesc * kDesc, (size_t)2 * kDesc * kDesc);
+    }
+    hipLaunchKernelGGL(eig_kernel, dim3(batch), dim3(256), 0, st, cov, mean, sqm, eigval, axes, ax32);
     const long total = 4L * (long)g.npx;
     hipLaunchKernelGGL(project_kernel, dim3((unsigned)((total + kGramPx - 1) / kGramPx), batch), dim3(256), 0,
                        st, Cs, ax32, reinterpret_cast<float4*>(phi), g.H, g.W);
