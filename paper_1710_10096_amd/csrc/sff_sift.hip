@@ -510,9 +510,14 @@ __global__ void __launch_bounds__(256) square_kernel(const double* __restrict__ 
     const int t = threadIdx.x, ti = blockIdx.x >> 3, tj = blockIdx.x & 7;
     const double* B = B_all + (size_t)blockIdx.y * b_stride;
     double* C = C_all + (size_t)blockIdx.y * c_stride;
-    double f = 0.0;
-    for (int e = t; e < kDesc * kDesc; e += 256) f = fma(B[e], B[e], f);
-    f = block_sum(f, red);
+    // four independent partial sums so the 64 loads of a thread are in flight together
+    double f4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = t; e < kDesc * kDesc; e += 1024)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) f4[u] = fma(B[e + 256 * u], B[e + 256 * u], f4[u]);
+    const double f = block_sum((f4[0] + f4[1]) + (f4[2] + f4[3]), red);
+#pragma unroll
     for (int e = t; e < kDesc * 16; e += 256) {
         const int k = e >> 4, c = e & 15;
         colr[k][c] = B[(size_t)k * kDesc + 16 * ti + c];
