@@ -294,9 +294,10 @@ struct CoopEval {
 // hand-off (own from the coarse field, neighbours already at this level);
 // 3 = hand-off only (no propagation or search), used when iters == 0.
 //
-// Block = one wave: 64 pixels of the half-step's colour in one grid row (all
-// pixels for mode 3).  Lanes past the row's end stay in the wave (for the
-// cooperative gathers) without a pixel of their own.  One-wave blocks let a
+// Block = one wave: E::kOwners (64, or 32 for the smallest launches) pixels of
+// the half-step's colour in one grid row (all pixels for mode 3).  Lanes past
+// the row's end or past the owners stay in the wave (for the cooperative
+// gathers) without a pixel of their own.  One-wave blocks let a
 // finished wave's slot be refilled at once; the early-out makes wave times
 // uneven (level 0 of the KITTI-size pair: 1.459 vs 1.482 ms per step with
 // four-row blocks, level 2: 0.262 vs 0.286 ms).

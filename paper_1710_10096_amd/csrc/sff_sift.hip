@@ -775,10 +775,11 @@ __global__ void __launch_bounds__(256) cost_sift_kernel(const float4* __restrict
 
 // Full-resolution matching with eq. (1) (Section 3.1, "Multi-Scale
 // Propagation" at the finest scale): one red-black half-step of both fields.
-// Block = 4 image rows x 64 pixels of the half-step's colour; each lane scores
-// its own candidates (left, up, right, down, then the random-search samples,
-// one at a time, strict improvement).  Random stream: Philox4x32-10 with the
-// counter's level field 16 and radii R0 >> t.
+// Per-lane form (SFF_SIFT_EVAL=lane; the wave-shared form follows further
+// down): block = 4 image rows x 64 pixels of the half-step's colour; each lane
+// scores its own candidates (left, up, right, down, then the random-search
+// samples, one at a time, strict improvement).  Random stream: Philox4x32-10
+// with the counter's level field 16 and radii R0 >> t.
 struct SiftMatchArgs {
     const float4* phi;       // [batch][4][H][W]
     const uint64_t* seeds;   // [batch]
