@@ -344,6 +344,13 @@ sff_status sff_match_sift(const sff_params* p, int32_t batch, int32_t dir, const
                           const uint64_t* seeds, int32_t iters, int16_t* hyp, float* cost,
                           void* stream);
 
+/* The square root that the cost above applies to each squared distance, over
+ * an array: out[i] = sqrt(in[i]) correctly rounded (IEEE round to nearest even)
+ * for finite in[i] >= +0 (other inputs: unspecified), i < n.  in/out: device,
+ * 4-byte aligned, n in [0, 2^31].  Exposed so that the rounding can be checked
+ * against the host.  Errors: SFF_ERR_INVALID_ARG. */
+sff_status sff_sift_sqrt(const float* in, float* out, int64_t n, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Window form of the matching cost on real-valued feature maps (eq. (1),
  * Section 3.1: feature distances summed over a window around the pixel for the

@@ -32,7 +32,7 @@ EXPORTS = ("sff_status_string", "sff_version", "sff_desc_channels", "sff_lanczos
            "sff_consistency", "sff_region_workspace_bytes", "sff_region_filter", "sff_sparsify",
            "sff_sgm_workspace_bytes", "sff_sgm_disparity", "sff_disparity_fill",
            "sff_sift_workspace_bytes", "sff_dense_sift", "sff_sift_pca", "sff_cost_sift",
-           "sff_match_sift",
+           "sff_match_sift", "sff_sift_sqrt",
            "sff_cost_f32_fwd", "sff_cost_f32_bwd_workspace_bytes",
            "sff_cost_f32_bwd", "sff_conv3x3_bf16_fwd", "sff_conv3x3_bf16_bwd_workspace_bytes",
            "sff_conv3x3_bf16_dgrad", "sff_conv3x3_bf16_wgrad", "sff_smooth_level",
@@ -97,6 +97,8 @@ def lib() -> ctypes.CDLL:
     L.sff_cost_sift.restype = i32
     L.sff_match_sift.argtypes = [PP, i32, i32, P, P, i32, P, P, P]
     L.sff_match_sift.restype = i32
+    L.sff_sift_sqrt.argtypes = [P, P, ctypes.c_int64, P]
+    L.sff_sift_sqrt.restype = i32
     L.sff_cost_f32_fwd.argtypes = [i32] * 5 + [P, P, P, P]
     L.sff_cost_f32_fwd.restype = i32
     L.sff_cost_f32_bwd_workspace_bytes.argtypes = [i32] * 3

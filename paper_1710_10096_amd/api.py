@@ -379,6 +379,18 @@ def sff_match_sift(p, phi: torch.Tensor, seeds: torch.Tensor, hyp: torch.Tensor,
     return cost
 
 
+def sff_sift_sqrt(x: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """The SIFT-PCA cost's correctly rounded square root of every element of
+    x (float32, finite, >= 0, contiguous on the device)."""
+    n = x.numel()
+    if out is None:
+        out = torch.empty_like(x)
+    _check_shape(out, tuple(x.shape), "out")
+    _check(lib().sff_sift_sqrt(_ptr(x, torch.float32, "x"), _ptr(out, torch.float32, "out"), n, _stream(stream)),
+           "sff_sift_sqrt")
+    return out
+
+
 def sff_cost_f32_fwd(feat: torch.Tensor, hyp: torch.Tensor, dir: int, cost=None, stream=None):
     """feat float32 [batch][4][H][W][cf], hyp int16 [batch][H][W][4] -> cost [batch][H][W]."""
     B, four, H, W, cf = feat.shape

@@ -699,10 +699,10 @@ __global__ void __launch_bounds__(256) project_kernel(const float* __restrict__ 
 // Euclidean distance of the first three components, every operation rounded
 // as written (no contraction), so that sums agree bit for bit with the FP32
 // definition: ((e0^2 + e1^2) + e2^2), correctly rounded square root.  sqrtf
-// is correctly rounded in this toolchain's default FP32 mode (checked against
-// the host on 2^20 inputs); __fsqrt_rn is not (15% of them differ by an ulp).
-// HIP contracts multiply-adds by default (the __f*_rn helpers included):
-// switched off here, with plain operators under the pragma.
+// is correctly rounded in this toolchain's default FP32 mode (a committed test
+// checks it against the host); __fsqrt_rn is not (15% of 2^20 inputs differ by
+// an ulp).  HIP contracts multiply-adds by default (the __f*_rn helpers
+// included): switched off here, with plain operators under the pragma.
 __device__ __forceinline__ float fdist3(float4 a, float4 b) {
 #pragma clang fp contract(off)
     const float e0 = a.x - b.x, e1 = a.y - b.y, e2 = a.z - b.z;
@@ -1078,6 +1078,13 @@ __global__ void __launch_bounds__(64) sift_cost_coop_kernel(SiftMatchArgs a, int
     if (act) a.cost[o] = c;
 }
 
+// The cost's square root (sqrtf) over an array, to check its rounding.
+__global__ void __launch_bounds__(256) sift_sqrt_kernel(const float* __restrict__ in, float* __restrict__ out,
+                                                        int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = sqrtf(in[i]);
+}
+
 bool sift_shape_ok(const sff_params* p, int64_t nimg) {
     if (!params_ok(p) || nimg < 1) return false;
     // flattened indices stay below 2^31 in every kernel
@@ -1241,5 +1248,15 @@ extern "C" sff_status sff_match_sift(const sff_params* p, int32_t batch, int32_t
                 hipLaunchKernelGGL(sift_half_step_coop_kernel, dim3(tiles_x * p->H * nz), dim3(64), 0, st, a,
                                    it, colour, tiles_x);
         }
+    return launch_status();
+}
+
+extern "C" sff_status sff_sift_sqrt(const float* in, float* out, int64_t n, void* stream) {
+    if (!in || !out || n < 0 || n > (int64_t(1) << 31)) return SFF_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(in) & 3) != 0 || (reinterpret_cast<uintptr_t>(out) & 3) != 0)
+        return SFF_ERR_INVALID_ARG;
+    if (n == 0) return SFF_OK;
+    hipLaunchKernelGGL(sift_sqrt_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, as_stream(stream), in,
+                       out, n);
     return launch_status();
 }

@@ -12,7 +12,7 @@ extern "C" const char* sff_status_string(int32_t status) {
     }
 }
 
-extern "C" int32_t sff_version(void) { return 300; }  // 0.3.0: SGM fill, SIFT-PCA cost and matching
+extern "C" int32_t sff_version(void) { return 301; }  // 0.3.1: sff_sift_sqrt
 
 extern "C" int32_t sff_desc_channels(int32_t C) {
     if (C < 1 || C > 4) return 0;

@@ -176,6 +176,11 @@ def test_invalid_arguments_rejected():
     assert L.sff_match_sift(P, 1, 0, f, f, -1, f, f, None) == 1                  # iters < 0
     assert L.sff_match_sift(P, 1, 0, f, None, 1, f, f, None) == 1                # no seeds
     assert L.sff_match_sift(P, 1, 0, ctypes.c_void_p(0x1004), f, 1, f, f, None) == 1
+    assert L.sff_sift_sqrt(None, f, 4, None) == 1
+    assert L.sff_sift_sqrt(f, f, -1, None) == 1
+    assert L.sff_sift_sqrt(ctypes.c_void_p(0x1002), f, 4, None) == 1            # in not 4-B aligned
+    assert L.sff_sift_sqrt(f, f, (1 << 31) + 1, None) == 1
+    assert L.sff_sift_sqrt(f, f, 0, None) == 0                                    # nothing to do
     # overlapping hand-off buffers
     p3 = _good()
     p3.levels = 2

@@ -248,6 +248,28 @@ def _cost_at(phi, hyp, y, x):
     return s
 
 
+def test_sift_sqrt_correctly_rounded(sff):
+    """The cost's square root (sqrtf, on which the bit-exact SIFT-PCA cost and
+    matching rely) against the host's IEEE float32 root, bit for bit: a stride
+    through every non-negative finite float32 pattern (subnormals included),
+    both sides of 2^-96 (where hipcc's sqrtf rescales its argument), the
+    subnormal/normal edge, every float in [0.5, 0.5625) and the largest finite
+    value."""
+    import torch
+    bits = np.arange(0, 0x7F800000, 997, dtype=np.uint32)
+    edge = np.array([0, 1, 2, 3, 0x007FFFFF, 0x00800000, 0x00800001, 0x0F7FFFFF, 0x0F800000,
+                     0x0F800001, 0x3F7FFFFF, 0x3F800000, 0x3F800001, 0x7F7FFFFF], np.uint32)
+    dense = np.arange(0x3F000000, 0x3F000000 + (1 << 20), dtype=np.uint32)  # every float in [0.5, 0.5 + 2^-4)
+    q = np.concatenate([bits, edge, dense]).view(np.float32)
+    _say("sift sqrt", q.size)
+    out = sff.sff_sift_sqrt(dev(q))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    want = np.sqrt(q).view(np.uint32)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, [(hex(q.view(np.uint32)[i]), hex(got[i]), hex(want[i])) for i in bad[:8]]
+
+
 # --------------------------------------------------------------------------
 # Full-resolution matching with the SIFT-PCA cost: bit-exact against the
 # oracle's FP32 matcher on the same features (the oracle's, rounded to FP32)
