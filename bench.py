@@ -24,6 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, vendor figure
 # Per-launch HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs, calibrated against a copy of known size.  The file records a
 # hash of the kernel sources it was measured with; any later edit of those
@@ -174,6 +175,73 @@ def fill_stage(m, imgs, steps: int) -> dict:
         t_f += marks[0].elapsed_time(marks[1])
     return {"sgm_ms": t_s / steps, "fill_ms": t_f / steps,
             "consistent": int(m.valid.sum().item()), "filled": int(m.fill.sum().item())}
+
+
+def _timed(fn, steps: int) -> float:
+    """Mean ms of fn() over `steps` runs on the current stream (after one untimed run)."""
+    import torch
+    st = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        fn()
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cost_f32_stage(p, m, steps: int, cf: int = 32) -> dict:
+    """The FP32 window form of eq. (1) and its backward pass on four random
+    cf-channel feature maps of the workload's size at the matched level-0
+    forward field (after the headline step, timed separately).  Algorithmic
+    bytes: forward reads the four maps, the field and writes the cost; backward
+    also reads the cost gradient and writes four gradient maps."""
+    import torch
+    import paper_1710_10096_amd as sff
+    hyp = m.hyp[0][0]
+    B, H, W = hyp.shape[0], hyp.shape[1], hyp.shape[2]
+    g = torch.Generator(device=hyp.device).manual_seed(5)
+    feat = torch.randn((B, 4, H, W, cf), generator=g, device=hyp.device, dtype=torch.float32)
+    cost = torch.empty((B, H, W), dtype=torch.float32, device=hyp.device)
+    gcost = torch.ones_like(cost)
+    gfeat = torch.empty_like(feat)
+    ws = torch.empty(sff.sff_cost_f32_bwd_workspace_bytes(B, H, W), dtype=torch.uint8, device=hyp.device)
+    t_f = _timed(lambda: sff.sff_cost_f32_fwd(feat, hyp, sff.DIR_FORWARD, cost=cost), steps)
+    t_b = _timed(lambda: sff.sff_cost_f32_bwd(feat, hyp, sff.DIR_FORWARD, gcost, grad_feat=gfeat, workspace=ws),
+                 steps)
+    maps = 4 * B * H * W * cf * 4
+    b_f = maps + B * H * W * (8 + 4)
+    b_b = 2 * maps + B * H * W * (8 + 4)
+    return {"channels": cf, "fwd_ms": t_f, "bwd_ms": t_b,
+            "fwd_GBps_alg": b_f / (t_f * 1e6), "bwd_GBps_alg": b_b / (t_b * 1e6),
+            "fwd_hbm_frac": b_f / (t_f * 1e6) / HBM_PEAK_GBS, "bwd_hbm_frac": b_b / (t_b * 1e6) / HBM_PEAK_GBS}
+
+
+def featnet_stage(imgs, steps: int) -> dict:
+    """The learned-descriptor network (4 conv3x3 layers, BF16 MFMA, FP32
+    accumulation) on the four images of the first pair at full resolution:
+    forward, and forward plus backward (weight and input gradients) for a
+    training step, random weights; FLOP rate against the dense BF16 peak."""
+    import torch
+    from paper_1710_10096_amd.featnet import LAYERS, FeatNet, images_bf16
+    net = FeatNet(seed=0, device=imgs.device)
+    x = images_bf16(imgs[0])
+    wb = net.weights_bf16()
+    n, H, W = x.shape[0], x.shape[1], x.shape[2]
+    dout = torch.ones((n, H, W, LAYERS[-1][1]), dtype=torch.bfloat16, device=imgs.device)
+
+    def train_step():
+        _, acts = net.forward(x, keep=True, wb=wb)
+        net.backward(acts, dout, wb=wb)
+
+    t_f = _timed(lambda: net.forward(x, wb=wb), steps)
+    t_t = _timed(train_step, steps)
+    flop_px = sum(2 * 9 * cin * cout for cin, cout in LAYERS)
+    flops = flop_px * n * H * W
+    return {"images": n, "fwd_ms": t_f, "train_step_ms": t_t, "fwd_TFLOPs": flops / (t_f * 1e9),
+            "fwd_mfma_frac": flops / (t_f * 1e9) / BF16_PEAK_TFLOPS}
 
 
 def sift_stage(p, m, imgs, steps: int) -> dict:
@@ -380,6 +448,8 @@ def main():
     out["region_sparsify"] = region_stage(p, B, m, args.steps)
     out["disparity_fill"] = fill_stage(m, imgs, args.steps)
     out["sift_pca_cost"] = sift_stage(p, m, imgs, args.steps)
+    out["cost_f32"] = cost_f32_stage(p, m, args.steps)
+    out["featnet"] = featnet_stage(imgs, args.steps)
     if not args.no_probes:
         out["probes"] = probes()
     if not args.no_cpu_baseline:

@@ -48,7 +48,9 @@ def _within_bf16_ulp(got, ref, abs_sum):
 
 
 CASES = [(1, 9, 70, 3, 1), (2, 17, 131, 32, 1), (1, 23, 64, 32, 2), (1, 30, 97, 32, 4),
-         (1, 5, 6, 32, 16), (1, 1, 1, 3, 1)]
+         (1, 5, 6, 32, 16), (1, 1, 1, 3, 1),
+         # several 256-pixel tiles of the 32-channel kernel with ragged tails
+         (1, 7, 300, 32, 1), (2, 6, 530, 32, 3), (1, 40, 270, 32, 16)]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[str(c) for c in CASES])
@@ -84,3 +86,45 @@ def test_conv_forward_and_gradients(sff, case):
         assert np.array_equal(_np(dx2), _np(dx))
     dw2, _ = sff.sff_conv3x3_bf16_wgrad(_bf(x), _bf(dy), dil, _bf(relu_out))
     assert np.array_equal(dw2.cpu().numpy(), dw.cpu().numpy())  # deterministic
+
+
+CASES32 = [(2, 17, 131, 32, 1), (1, 7, 300, 32, 1), (2, 6, 530, 32, 3), (1, 40, 270, 32, 16)]
+
+
+@pytest.mark.parametrize("case", CASES32, ids=[str(c) for c in CASES32])
+def test_conv32_kernel_same_as_im2col(sff, case, monkeypatch):
+    """The 32-channel kernel without an im2col tile (the default for 16-byte
+    aligned tensors) against the im2col kernel (SFF_CONV_IM2COL=1) and against
+    the same tensors at a 2-byte offset (which take the im2col kernel): the
+    same MFMAs on the same values, so forward and input gradient agree bit for
+    bit."""
+    import torch
+    n, H, W, cin, dil = case
+    rng = np.random.default_rng(7 * H + W + dil)
+    x = ofn.bf16_round(rng.standard_normal((n, H, W, 32)))
+    w = ofn.bf16_round(rng.standard_normal((32, 3, 3, 32)) / np.sqrt(288))
+    b = torch.from_numpy(rng.standard_normal(32).astype(np.float32)).cuda()
+    relu_out = ofn.bf16_round(np.maximum(rng.standard_normal((n, H, W, 32)), 0))
+    dy = ofn.bf16_round(rng.standard_normal((n, H, W, 32)))
+
+    def offset(a):  # the same values at a 2-byte offset (contiguous, not 16-byte aligned)
+        t = _bf(a).reshape(-1)
+        buf = torch.empty(t.numel() + 8, dtype=torch.bfloat16, device="cuda")
+        v = buf[1:1 + t.numel()]
+        v.copy_(t)
+        return v.view(a.shape)
+
+    _say("conv32 vs im2col", case)
+    monkeypatch.delenv("SFF_CONV_IM2COL", raising=False)
+    y = sff.sff_conv3x3_bf16_fwd(_bf(x), _bf(w), b, dil, True)
+    dx = sff.sff_conv3x3_bf16_dgrad(_bf(dy), _bf(w), dil, _bf(relu_out))
+    y_off = sff.sff_conv3x3_bf16_fwd(offset(x), _bf(w), b, dil, True)
+    dx_off = sff.sff_conv3x3_bf16_dgrad(offset(dy), _bf(w), dil, offset(relu_out))
+    monkeypatch.setenv("SFF_CONV_IM2COL", "1")
+    y_ref = sff.sff_conv3x3_bf16_fwd(_bf(x), _bf(w), b, dil, True)
+    dx_ref = sff.sff_conv3x3_bf16_dgrad(_bf(dy), _bf(w), dil, _bf(relu_out))
+    torch.cuda.synchronize()
+    for got in (y, y_off):
+        assert torch.equal(got.view(torch.int16), y_ref.view(torch.int16))
+    for got in (dx, dx_off):
+        assert torch.equal(got.view(torch.int16), dx_ref.view(torch.int16))
