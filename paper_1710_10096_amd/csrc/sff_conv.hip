@@ -312,24 +312,52 @@ __global__ void __launch_bounds__(256) conv_wgrad_kernel(const bf16_t* __restric
 }
 
 // Fixed-order sum of the per-block partials: dw [COUT][3][3][CIN], db [COUT].
-__global__ void wgrad_reduce_kernel(const float* __restrict__ part, float* __restrict__ dw,
-                                    float* __restrict__ db, int nblk, int cin, int cout, int cpad) {
-    const int e = blockIdx.x * 256 + threadIdx.x;
+// Sum of the per-block partials, in a fixed order: 16 outputs per block, 16
+// threads per output; thread s sums blocks s, s + 16, s + 32, ... with four
+// independent accumulators (their loads in flight together), and the 16
+// segment sums of an output are added in order through LDS.
+constexpr int kRedOut = 16, kRedSeg = 16;
+
+__global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ part, float* __restrict__ dw,
+                                                           float* __restrict__ db, int nblk, int cin, int cout,
+                                                           int cpad) {
+    __shared__ float seg[kRedSeg][kRedOut];
+    const int lo = threadIdx.x % kRedOut, sg = threadIdx.x / kRedOut;
+    const int e = blockIdx.x * kRedOut + lo;
     const int nw = cout * 9 * cin;
+    const bool valid = e < nw + cout;
+    const float* src = part;
+    size_t stride = 0;
     if (e < nw) {
         const int o = e / (9 * cin), r = e - o * 9 * cin;
         const int tap = r / cin, i = r - tap * cin;
-        const size_t stride = (size_t)cout * 9 * cpad;
-        const size_t off = ((size_t)o * 9 + tap) * cpad + i;
-        float s = 0.f;
-        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * stride + off];
-        dw[e] = s;
-    } else if (e < nw + cout) {
-        const int o = e - nw;
-        const float* pd = part + (size_t)nblk * cout * 9 * cpad;
-        float s = 0.f;
-        for (int b = 0; b < nblk; ++b) s += pd[(size_t)b * cout + o];
-        db[o] = s;
+        stride = (size_t)cout * 9 * cpad;
+        src = part + ((size_t)o * 9 + tap) * cpad + i;
+    } else if (valid) {
+        stride = (size_t)cout;
+        src = part + (size_t)nblk * cout * 9 * cpad + (e - nw);
+    }
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    if (valid) {
+        int b = sg;
+        for (; b + 3 * kRedSeg < nblk; b += 4 * kRedSeg) {
+            a0 += src[(size_t)b * stride];
+            a1 += src[(size_t)(b + kRedSeg) * stride];
+            a2 += src[(size_t)(b + 2 * kRedSeg) * stride];
+            a3 += src[(size_t)(b + 3 * kRedSeg) * stride];
+        }
+        for (; b < nblk; b += kRedSeg) a0 += src[(size_t)b * stride];
+    }
+    seg[sg][lo] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (sg == 0 && valid) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < kRedSeg; ++k) t += seg[k][lo];
+        if (e < nw)
+            dw[e] = t;
+        else
+            db[e - nw] = t;
     }
 }
 
@@ -434,7 +462,7 @@ extern "C" sff_status sff_conv3x3_bf16_wgrad(int32_t n, int32_t H, int32_t W, in
         hipLaunchKernelGGL((conv_wgrad_kernel<32, 32>), grid, dim3(256), 0, st, x, dy, relu_out,
                            part, H, W, dil);
     const int cpad = (cin + 15) / 16 * 16;
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((cout * 9 * cin + cout + 255) / 256), dim3(256), 0,
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((cout * 9 * cin + cout + kRedOut - 1) / kRedOut), dim3(256), 0,
                        st, part, dw, db, nblk, cin, cout, cpad);
     return launch_status();
 }
