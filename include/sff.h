@@ -375,6 +375,9 @@ size_t sff_cost_f32_bwd_workspace_bytes(int32_t batch, int32_t H, int32_t W);
  * +2 g delta to its reference entry and -2 g delta to its target entry).
  * grad_cost: [batch][H][W] float32.  grad_feat: [batch][4][H][W][cf] float32,
  * fully overwritten.  Deterministic: the same inputs give the same bits.
+ * Each gradient entry is gathered by cf / 4 lanes, four channels each;
+ * SFF_COST_F32_EVAL=lane gathers with one lane per entry (same bits; testing
+ * and timing).
  * workspace: device buffer, 256-byte aligned, at least
  *   sff_cost_f32_bwd_workspace_bytes(batch, H, W) bytes.
  * Errors: SFF_ERR_INVALID_ARG, SFF_ERR_WORKSPACE. */

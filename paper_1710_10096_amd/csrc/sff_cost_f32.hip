@@ -17,6 +17,9 @@
 // Both are deterministic (no floating-point atomics).
 #include <rocprim/device/device_radix_sort.hpp>
 
+#include <cstdlib>
+#include <cstring>
+
 #include "sff_internal.hpp"
 
 namespace sff {
@@ -176,6 +179,51 @@ __global__ void __launch_bounds__(256) grad_ref_kernel(CostArgs a) {
     for (int k = 0; k < CF / 4; ++k) o[k] = make_float4(acc[4 * k], acc[4 * k + 1], acc[4 * k + 2], acc[4 * k + 3]);
 }
 
+// The same gradient with CF / 4 lanes per entry, four channels each (see
+// grad_target_coop_kernel); every channel adds the same terms in the same
+// order as grad_ref_kernel, so the results are identical.
+template <int CF>
+__global__ void __launch_bounds__(256) grad_ref_coop_kernel(CostArgs a) {
+    constexpr int L = CF / 4, QPB = 256 / L;
+    const int sub = threadIdx.x % L;
+    const int H = a.H, W = a.W, b = blockIdx.y;
+    const size_t HW = (size_t)H * W;
+    const size_t q = (size_t)blockIdx.x * QPB + threadIdx.x / L;
+    if (q >= HW) return;  // all L lanes of the entry together
+    const int qy = (int)(q / W), qx = (int)(q - (size_t)qy * W);
+    const float* base = a.feat + (size_t)b * 4 * HW * CF;
+    const int mR = view(a.s, 0);
+    const float4* M[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[k] = reinterpret_cast<const float4*>(base + (size_t)view(a.s, k + 1) * HW * CF) + sub;
+    const float4 fq = reinterpret_cast<const float4*>(base + ((size_t)mR * HW + q) * CF)[sub];
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int wy = kWin0; wy <= kWin1; ++wy) {
+        int ylo, yhi;
+        preimage(qy, wy, H, ylo, yhi);
+        for (int py = ylo; py <= yhi; ++py)
+            for (int wx = kWin0; wx <= kWin1; ++wx) {
+                int xlo, xhi;
+                preimage(qx, wx, W, xlo, xhi);
+                for (int px = xlo; px <= xhi; ++px) {
+                    const size_t pix = (size_t)b * HW + (size_t)py * W + px;
+                    const float g2 = 2.f * a.gcost[pix];
+                    const Targets t = targets(a.hyp, pix, py, px, a.s, H, W);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const float4 tg = M[k][((size_t)clampi(t.y[k] + wy, 0, H - 1) * W +
+                                                clampi(t.x[k] + wx, 0, W - 1)) * L];
+                        acc.x = fmaf(g2, fq.x - tg.x, acc.x);
+                        acc.y = fmaf(g2, fq.y - tg.y, acc.y);
+                        acc.z = fmaf(g2, fq.z - tg.z, acc.z);
+                        acc.w = fmaf(g2, fq.w - tg.w, acc.w);
+                    }
+                }
+            }
+    }
+    reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mR * HW + q) * CF)[sub] = acc;
+}
+
 // Keys for grouping pixels by the target centre of correspondence k.
 __global__ void target_keys_kernel(const int16_t* __restrict__ hyp, uint32_t* keys, uint32_t* vals,
                                    int H, int W, int s, int k, int batch) {
@@ -249,6 +297,56 @@ __global__ void __launch_bounds__(256) grad_target_kernel(CostArgs a, int k,
         o[kk] = make_float4(acc[4 * kk], acc[4 * kk + 1], acc[4 * kk + 2], acc[4 * kk + 3]);
 }
 
+// The same gradient with CF / 4 lanes per target entry, each owning four
+// channels: a gathered vector is CF / 4 consecutive 16-byte loads of
+// neighbouring lanes (a few cache lines per load instruction instead of one per
+// lane), a lane holds a float4 accumulator instead of CF, and a wave covers
+// 256 / (CF / 4) / 4 entries, so far fewer lanes wait on the slowest entry of
+// their wave.  Every channel adds the same terms in the same order as
+// grad_target_kernel, so the results are identical.
+template <int CF>
+__global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k,
+                                                               const uint32_t* __restrict__ start,
+                                                               const uint32_t* __restrict__ order) {
+    constexpr int L = CF / 4, QPB = 256 / L;
+    const int sub = threadIdx.x % L;
+    const int H = a.H, W = a.W, b = blockIdx.y;
+    const size_t HW = (size_t)H * W;
+    const size_t q = (size_t)blockIdx.x * QPB + threadIdx.x / L;
+    if (q >= HW) return;  // all L lanes of the entry together
+    const int qy = (int)(q / W), qx = (int)(q - (size_t)qy * W);
+    const float* base = a.feat + (size_t)b * 4 * HW * CF;
+    const float4* R = reinterpret_cast<const float4*>(base + (size_t)view(a.s, 0) * HW * CF) + sub;
+    const int mk = view(a.s, k + 1);
+    const float4 fq = reinterpret_cast<const float4*>(base + ((size_t)mk * HW + q) * CF)[sub];
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int wy = kWin0; wy <= kWin1; ++wy) {
+        int ylo, yhi;
+        preimage(qy, wy, H, ylo, yhi);
+        for (int ty = ylo; ty <= yhi; ++ty)
+            for (int wx = kWin0; wx <= kWin1; ++wx) {
+                int xlo, xhi;
+                preimage(qx, wx, W, xlo, xhi);
+                for (int tx = xlo; tx <= xhi; ++tx) {
+                    const size_t cell = (size_t)b * HW + (size_t)ty * W + tx;
+                    const uint32_t e0 = start[cell], e1 = start[cell + 1];
+                    for (uint32_t e = e0; e < e1; ++e) {
+                        const uint32_t pix = order[e];
+                        const int pl = (int)(pix - (size_t)b * HW);
+                        const int py = pl / W, px = pl - py * W;
+                        const float g2 = 2.f * a.gcost[pix];
+                        const float4 r = R[((size_t)clampi(py + wy, 0, H - 1) * W + clampi(px + wx, 0, W - 1)) * L];
+                        acc.x = fmaf(-g2, r.x - fq.x, acc.x);
+                        acc.y = fmaf(-g2, r.y - fq.y, acc.y);
+                        acc.z = fmaf(-g2, r.z - fq.z, acc.z);
+                        acc.w = fmaf(-g2, r.w - fq.w, acc.w);
+                    }
+                }
+            }
+    }
+    reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mk * HW + q) * CF)[sub] = acc;
+}
+
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct BwdWs {
@@ -302,6 +400,16 @@ struct TgtK {
     static constexpr auto fn = grad_target_kernel<CF>;
 };
 
+template <int CF>
+struct RefCoopK {
+    static constexpr auto fn = grad_ref_coop_kernel<CF>;
+};
+
+template <int CF>
+struct TgtCoopK {
+    static constexpr auto fn = grad_target_coop_kernel<CF>;
+};
+
 }  // namespace
 }  // namespace sff
 
@@ -350,7 +458,14 @@ extern "C" sff_status sff_cost_f32_bwd(int32_t batch, int32_t H, int32_t W, int3
     uint32_t* start = reinterpret_cast<uint32_t*>(ws + L.start);
     CostArgs a{feat, hyp, grad_cost, grad_feat, H, W, dir, batch};
     const dim3 grid((W + 63) / 64, (H + 3) / 4, batch);
-    launch_cf<RefK>(cf, grid, st, a);
+    // SFF_COST_F32_EVAL=lane: one lane per gradient entry (same results; testing and timing)
+    const char* ev = std::getenv("SFF_COST_F32_EVAL");
+    const bool lane_grad = ev && std::strcmp(ev, "lane") == 0;
+    const dim3 cgrid((unsigned)(((size_t)H * W * (cf / 4) + 255) / 256), batch);
+    if (lane_grad)
+        launch_cf<RefK>(cf, grid, st, a);
+    else
+        launch_cf<RefCoopK>(cf, cgrid, st, a);
     unsigned int bits = 1;
     while (bits < 32 && (1ull << bits) < n) ++bits;
     for (int k = 0; k < 3; ++k) {
@@ -362,7 +477,10 @@ extern "C" sff_status sff_cost_f32_bwd(int32_t batch, int32_t H, int32_t W, int3
             return SFF_ERR_HIP;
         hipLaunchKernelGGL(cell_starts_kernel, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0,
                            st, keys_out, start, n);
-        launch_cf<TgtK>(cf, grid, st, a, k, (const uint32_t*)start, (const uint32_t*)order);
+        if (lane_grad)
+            launch_cf<TgtK>(cf, grid, st, a, k, (const uint32_t*)start, (const uint32_t*)order);
+        else
+            launch_cf<TgtCoopK>(cf, cgrid, st, a, k, (const uint32_t*)start, (const uint32_t*)order);
     }
     return launch_status();
 }

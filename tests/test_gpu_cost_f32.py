@@ -70,6 +70,26 @@ def test_small_forward_and_backward_match_fp64(sff, s, C):
     assert np.array_equal(again, grad)  # deterministic
 
 
+@pytest.mark.parametrize("C", [4, 8, 16, 32, 64])
+def test_gradient_kernels_identical(sff, C, monkeypatch):
+    """The gradient kernels with C/4 lanes per entry (the default) against one
+    lane per entry (SFF_COST_F32_EVAL=lane): every channel adds the same terms
+    in the same order, so the gradients agree bit for bit; both against the
+    FP64 oracle as above."""
+    B, H, W = 2, 13, 41
+    F, hyp, g = _random_case(100 + C, B, H, W, C, spread=7)
+    _say("cost_f32 gradient kernels", C)
+    monkeypatch.delenv("SFF_COST_F32_EVAL", raising=False)
+    grad = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), -1, _dev(g)).cpu().numpy()
+    monkeypatch.setenv("SFF_COST_F32_EVAL", "lane")
+    lane = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), -1, _dev(g)).cpu().numpy()
+    assert np.array_equal(grad, lane)
+    Fb = [F[1, m].astype(np.float64) for m in range(4)]
+    G = ocf.window_cost_grad(Fb, hyp[1], -1, g[1])
+    for m in range(4):
+        assert _grad_close(grad[1, m], G[m]).all(), m
+
+
 def test_one_pixel_and_one_row_images(sff):
     for (H, W) in ((1, 1), (1, 9), (7, 1)):
         F, hyp, g = _random_case(H * 31 + W, 1, H, W, 4, spread=3)
