@@ -363,6 +363,10 @@ sff_status sff_sift_sqrt(const float* in, float* out, int64_t n, void* stream);
  *   aligned; cf in {4, 8, 16, 32, 64}.
  * hyp:  [batch][H][W][4] int16 full-resolution vectors (held fixed).
  * dir:  SFF_DIR_FORWARD or SFF_DIR_INVERSE.
+ * Each pixel is summed by cf / 4 lanes (four channels each, lane sums added
+ * by a butterfly): deterministic, FP32 with partial sums (relative error below
+ * ~(3 cf + 16) 2^-24); SFF_COST_F32_EVAL=lane sums each pixel in one lane
+ * (another rounding within the same bound; testing and timing).
  * Errors: SFF_ERR_INVALID_ARG (shapes, alignment, dir, batch*H*W >= 2^31). */
 sff_status sff_cost_f32_fwd(int32_t batch, int32_t H, int32_t W, int32_t cf, int32_t dir,
                             const float* feat, const int16_t* hyp, float* cost_px, void* stream);

@@ -115,6 +115,55 @@ __global__ void __launch_bounds__(256) cost_fwd_kernel(CostArgs a) {
     a.out[(size_t)b * HW + (size_t)y * W + x] = total;
 }
 
+// The same cost with CF / 4 lanes per pixel, four channels each: a gathered
+// vector is CF / 4 neighbouring 16-byte loads.  Each lane sums its channels
+// in the nested order above; the CF / 4 lane sums are combined by an xor
+// butterfly (every lane ends with the same value), so the result is
+// deterministic; it rounds differently from cost_fwd_kernel (within the same
+// error bound).
+template <int CF>
+__global__ void __launch_bounds__(256) cost_fwd_coop_kernel(CostArgs a) {
+    constexpr int L = CF / 4, QPB = 256 / L;
+    const int sub = threadIdx.x % L;
+    const int H = a.H, W = a.W, b = blockIdx.y;
+    const size_t HW = (size_t)H * W;
+    const size_t q = (size_t)blockIdx.x * QPB + threadIdx.x / L;
+    if (q >= HW) return;  // all L lanes of the pixel together
+    const int y = (int)(q / W), x = (int)(q - (size_t)y * W);
+    const float* base = a.feat + (size_t)b * 4 * HW * CF;
+    const float4* R = reinterpret_cast<const float4*>(base + (size_t)view(a.s, 0) * HW * CF) + sub;
+    const float4* M[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[k] = reinterpret_cast<const float4*>(base + (size_t)view(a.s, k + 1) * HW * CF) + sub;
+    const Targets t = targets(a.hyp, (size_t)b * HW + q, y, x, a.s, H, W);
+    float total = 0.f;
+    for (int dy = kWin0; dy <= kWin1; ++dy) {
+        const int ry = clampi(y + dy, 0, H - 1);
+        int ty[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ty[k] = clampi(t.y[k] + dy, 0, H - 1);
+        float rsum = 0.f;
+        for (int dx = kWin0; dx <= kWin1; ++dx) {
+            const float4 r = R[((size_t)ry * W + clampi(x + dx, 0, W - 1)) * L];
+            float psum = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float4 tg = M[k][((size_t)ty[k] * W + clampi(t.x[k] + dx, 0, W - 1)) * L];
+                const float d0 = r.x - tg.x, d1 = r.y - tg.y, d2 = r.z - tg.z, d3 = r.w - tg.w;
+                psum = fmaf(d0, d0, psum);
+                psum = fmaf(d1, d1, psum);
+                psum = fmaf(d2, d2, psum);
+                psum = fmaf(d3, d3, psum);
+            }
+            rsum += psum;
+        }
+        total += rsum;
+    }
+#pragma unroll
+    for (int off = L / 2; off >= 1; off >>= 1) total += __shfl_xor(total, off, L);
+    if (sub == 0) a.out[(size_t)b * HW + q] = total;
+}
+
 // Preimage of the clamped coordinate: {p in [0, n) : clamp(p + w, 0, n - 1) = q}.
 __device__ __forceinline__ void preimage(int q, int w, int n, int& lo, int& hi) {
     if (n == 1) {
@@ -391,6 +440,11 @@ template <int CF>
 struct FwdK {
     static constexpr auto fn = cost_fwd_kernel<CF>;
 };
+
+template <int CF>
+struct FwdCoopK {
+    static constexpr auto fn = cost_fwd_coop_kernel<CF>;
+};
 template <int CF>
 struct RefK {
     static constexpr auto fn = grad_ref_kernel<CF>;
@@ -423,7 +477,13 @@ extern "C" sff_status sff_cost_f32_fwd(int32_t batch, int32_t H, int32_t W, int3
         (reinterpret_cast<uintptr_t>(cost_px) & 3) != 0)
         return SFF_ERR_INVALID_ARG;
     CostArgs a{feat, hyp, nullptr, cost_px, H, W, dir, batch};
-    launch_cf<FwdK>(cf, dim3((W + 63) / 64, (H + 3) / 4, batch), as_stream(stream), a);
+    // SFF_COST_F32_EVAL=lane: one lane per pixel (testing and timing)
+    const char* ev = std::getenv("SFF_COST_F32_EVAL");
+    if (ev && std::strcmp(ev, "lane") == 0)
+        launch_cf<FwdK>(cf, dim3((W + 63) / 64, (H + 3) / 4, batch), as_stream(stream), a);
+    else
+        launch_cf<FwdCoopK>(cf, dim3((unsigned)(((size_t)H * W * (cf / 4) + 255) / 256), batch), as_stream(stream),
+                            a);
     return launch_status();
 }
 

@@ -75,7 +75,7 @@ def test_gradient_kernels_identical(sff, C, monkeypatch):
     """The gradient kernels with C/4 lanes per entry (the default) against one
     lane per entry (SFF_COST_F32_EVAL=lane): every channel adds the same terms
     in the same order, so the gradients agree bit for bit; both against the
-    FP64 oracle as above."""
+    FP64 oracle as above.  The forward in both forms against the oracle."""
     B, H, W = 2, 13, 41
     F, hyp, g = _random_case(100 + C, B, H, W, C, spread=7)
     _say("cost_f32 gradient kernels", C)
@@ -88,6 +88,15 @@ def test_gradient_kernels_identical(sff, C, monkeypatch):
     G = ocf.window_cost_grad(Fb, hyp[1], -1, g[1])
     for m in range(4):
         assert _grad_close(grad[1, m], G[m]).all(), m
+    # forward: C/4 lanes per pixel (default; rounds differently from one lane
+    # per pixel, same bound) and one lane per pixel, both against the oracle
+    ref = ocf.window_cost(Fb, hyp[1], -1)
+    c_lane = sff.sff_cost_f32_fwd(_dev(F), _dev(hyp), -1).cpu().numpy()
+    monkeypatch.delenv("SFF_COST_F32_EVAL", raising=False)
+    c_coop = sff.sff_cost_f32_fwd(_dev(F), _dev(hyp), -1).cpu().numpy()
+    assert np.array_equal(c_coop, sff.sff_cost_f32_fwd(_dev(F), _dev(hyp), -1).cpu().numpy())
+    for c in (c_coop, c_lane):
+        assert np.allclose(c[1], ref, rtol=2e-5, atol=0)
 
 
 def test_one_pixel_and_one_row_images(sff):
