@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(256) grad_target_kernel(CostArgs a, int k,
         int ylo, yhi;
         preimage(qy, wy, H, ylo, yhi);
         for (int ty = ylo; ty <= yhi; ++ty)
-            for (int wx = kWin0; wx <= kWin1; ++wx) {
+            for (int wx = kWin1; wx >= kWin0; --wx) {  // target cells in ascending x
                 int xlo, xhi;
                 preimage(qx, wx, W, xlo, xhi);
                 for (int tx = xlo; tx <= xhi; ++tx) {
@@ -369,29 +369,58 @@ __global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k
     const int mk = view(a.s, k + 1);
     const float4 fq = reinterpret_cast<const float4*>(base + ((size_t)mk * HW + q) * CF)[sub];
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int wy = kWin0; wy <= kWin1; ++wy) {
-        int ylo, yhi;
-        preimage(qy, wy, H, ylo, yhi);
-        for (int ty = ylo; ty <= yhi; ++ty)
-            for (int wx = kWin0; wx <= kWin1; ++wx) {
-                int xlo, xhi;
-                preimage(qx, wx, W, xlo, xhi);
-                for (int tx = xlo; tx <= xhi; ++tx) {
-                    const size_t cell = (size_t)b * HW + (size_t)ty * W + tx;
-                    const uint32_t e0 = start[cell], e1 = start[cell + 1];
-                    for (uint32_t e = e0; e < e1; ++e) {
-                        const uint32_t pix = order[e];
-                        const int pl = (int)(pix - (size_t)b * HW);
-                        const int py = pl / W, px = pl - py * W;
-                        const float g2 = 2.f * a.gcost[pix];
-                        const float4 r = R[((size_t)clampi(py + wy, 0, H - 1) * W + clampi(px + wx, 0, W - 1)) * L];
-                        acc.x = fmaf(-g2, r.x - fq.x, acc.x);
-                        acc.y = fmaf(-g2, r.y - fq.y, acc.y);
-                        acc.z = fmaf(-g2, r.z - fq.z, acc.z);
-                        acc.w = fmaf(-g2, r.w - fq.w, acc.w);
+    auto add = [&](uint32_t pix, int wy, int wx) {
+        const int pl = (int)(pix - (size_t)b * HW);
+        const int py = pl / W, px = pl - py * W;
+        const float g2 = 2.f * a.gcost[pix];
+        const float4 r = R[((size_t)clampi(py + wy, 0, H - 1) * W + clampi(px + wx, 0, W - 1)) * L];
+        acc.x = fmaf(-g2, r.x - fq.x, acc.x);
+        acc.y = fmaf(-g2, r.y - fq.y, acc.y);
+        acc.z = fmaf(-g2, r.z - fq.z, acc.z);
+        acc.w = fmaf(-g2, r.w - fq.w, acc.w);
+    };
+    constexpr int kN = kWin1 - kWin0 + 1;  // 8 window columns
+    if (qy >= kWin1 && qy <= H - 1 + kWin0 && qx >= kWin1 && qx <= W - 1 + kWin0) {
+        // interior: window row wy covers the centre cells (qy - wy, qx - 4 .. qx + 3), consecutive,
+        // so their pixels are one run [st[0], st[8]) of the sorted order; it is walked in that
+        // order (cells by ascending x, the order of the generic loop below) four at a time
+        for (int wy = kWin0; wy <= kWin1; ++wy) {
+            const size_t c0 = (size_t)b * HW + (size_t)(qy - wy) * W + (qx - kWin1);
+            uint32_t st[kN + 1];
+#pragma unroll
+            for (int j = 0; j <= kN; ++j) st[j] = start[c0 + j];
+            for (uint32_t e = st[0]; e < st[kN]; e += 4) {
+                uint32_t pv[4];
+                int wxv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t eu = min(e + u, st[kN] - 1);
+                    pv[u] = order[eu];
+                    int j = 0;
+#pragma unroll
+                    for (int jj = 1; jj < kN; ++jj) j += eu >= st[jj] ? 1 : 0;
+                    wxv[u] = kWin1 - j;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (e + u < st[kN]) add(pv[u], wy, wxv[u]);
+            }
+        }
+    } else {
+        for (int wy = kWin0; wy <= kWin1; ++wy) {
+            int ylo, yhi;
+            preimage(qy, wy, H, ylo, yhi);
+            for (int ty = ylo; ty <= yhi; ++ty)
+                for (int wx = kWin1; wx >= kWin0; --wx) {  // target cells in ascending x
+                    int xlo, xhi;
+                    preimage(qx, wx, W, xlo, xhi);
+                    for (int tx = xlo; tx <= xhi; ++tx) {
+                        const size_t cell = (size_t)b * HW + (size_t)ty * W + tx;
+                        const uint32_t e0 = start[cell], e1 = start[cell + 1];
+                        for (uint32_t e = e0; e < e1; ++e) add(order[e], wy, wx);
                     }
                 }
-            }
+        }
     }
     reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mk * HW + q) * CF)[sub] = acc;
 }
