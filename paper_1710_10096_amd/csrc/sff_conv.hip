@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(256) conv_wgrad_kernel(const bf16_t* __restric
                                                          const bf16_t* __restrict__ dy,
                                                          const bf16_t* __restrict__ mask,
                                                          float* __restrict__ part, int H, int W,
-                                                         int dil) {
+                                                         int dil, int vec) {
     constexpr int IT = (CIN + 15) / 16, OT = COUT / 16, XW = kTilePx + 2 * kMaxDil;
     __shared__ __align__(16) bf16_t dzT[COUT][kTilePx];
     __shared__ __align__(16) bf16_t xT[3][IT * 16][XW];
@@ -243,24 +243,66 @@ __global__ void __launch_bounds__(256) conv_wgrad_kernel(const bf16_t* __restric
         const int row = r0 + rr;
         if (row >= H) break;
         __syncthreads();
-        for (int e = threadIdx.x; e < COUT * kTilePx; e += 256) {
-            const int p = e / COUT, o = e - p * COUT;
-            bf16_t v = 0;
-            if (x0 + p < W) {
-                const size_t off = (img + (size_t)row * W + x0 + p) * COUT + o;
-                v = dy[off];
-                if (mask && !(bf2f(mask[off]) > 0.f)) v = 0;
+        bool staged = false;
+        if constexpr (CIN == 32 && COUT == 32) {
+            if (vec) {
+                // 16-byte loads (8 channels of one pixel), scattered transposed into LDS
+                {
+                    const int p = threadIdx.x >> 2, q = threadIdx.x & 3;  // 64 pixels x 4 pieces
+                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                    if (x0 + p < W) {
+                        const size_t off = (img + (size_t)row * W + x0 + p) * 32 + 8 * q;
+                        v = *reinterpret_cast<const uint4*>(dy + off);
+                        if (mask) {
+                            const uint4 m = *reinterpret_cast<const uint4*>(mask + off);
+                            const uint32_t mw[4] = {m.x, m.y, m.z, m.w};
+                            uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                            for (int h = 0; h < 4; ++h) {
+                                const uint32_t lo = bf2f((bf16_t)(mw[h] & 0xFFFFu)) > 0.f ? 0x0000FFFFu : 0u;
+                                const uint32_t hi = bf2f((bf16_t)(mw[h] >> 16)) > 0.f ? 0xFFFF0000u : 0u;
+                                vw[h] &= lo | hi;
+                            }
+                            v = make_uint4(vw[0], vw[1], vw[2], vw[3]);
+                        }
+                    }
+                    const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) dzT[8 * q + t][p] = (bf16_t)(vw[t >> 1] >> (16 * (t & 1)));
+                }
+                for (int e = threadIdx.x; e < 3 * XW * 4; e += 256) {
+                    const int ky = e / (XW * 4), r = e - ky * XW * 4, j = r >> 2, q = r & 3;
+                    const int yy = row + (ky - 1) * dil, xx = x0 - kMaxDil + j;
+                    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                    if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                        v = *reinterpret_cast<const uint4*>(x + (img + (size_t)yy * W + xx) * 32 + 8 * q);
+                    const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) xT[ky][8 * q + t][j] = (bf16_t)(vw[t >> 1] >> (16 * (t & 1)));
+                }
+                staged = true;
             }
-            dzT[o][p] = v;
         }
-        for (int e = threadIdx.x; e < 3 * IT * 16 * XW; e += 256) {
-            const int ky = e / (IT * 16 * XW), r = e - ky * IT * 16 * XW;
-            const int c = r / XW, j = r - c * XW;
-            const int yy = row + (ky - 1) * dil, xx = x0 - kMaxDil + j;
-            bf16_t v = 0;
-            if (c < CIN && yy >= 0 && yy < H && xx >= 0 && xx < W)
-                v = x[(img + (size_t)yy * W + xx) * CIN + c];
-            xT[ky][c][j] = v;
+        if (!staged) {
+            for (int e = threadIdx.x; e < COUT * kTilePx; e += 256) {
+                const int p = e / COUT, o = e - p * COUT;
+                bf16_t v = 0;
+                if (x0 + p < W) {
+                    const size_t off = (img + (size_t)row * W + x0 + p) * COUT + o;
+                    v = dy[off];
+                    if (mask && !(bf2f(mask[off]) > 0.f)) v = 0;
+                }
+                dzT[o][p] = v;
+            }
+            for (int e = threadIdx.x; e < 3 * IT * 16 * XW; e += 256) {
+                const int ky = e / (IT * 16 * XW), r = e - ky * IT * 16 * XW;
+                const int c = r / XW, j = r - c * XW;
+                const int yy = row + (ky - 1) * dil, xx = x0 - kMaxDil + j;
+                bf16_t v = 0;
+                if (c < CIN && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    v = x[(img + (size_t)yy * W + xx) * CIN + c];
+                xT[ky][c][j] = v;
+            }
         }
         __syncthreads();
         if (lane < COUT) {
@@ -369,9 +411,10 @@ bool conv_shape_ok(int n, int H, int W, int cin, int cout, int dil) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// conv32_fwd_kernel reads x (and mask) in 16-byte pieces; unaligned tensors
-// and SFF_CONV_IM2COL=1 (testing and timing) take the im2col kernel, which
-// gives the same results.
+// conv32_fwd_kernel and the 32-channel weight gradient read x (and mask, dy)
+// in 16-byte pieces; unaligned tensors and SFF_CONV_IM2COL=1 (testing and
+// timing) take the element-wise kernels (the im2col forward, element-wise
+// staging of the gradient tiles), which give the same results.
 bool use_conv32(const void* x, const void* mask) {
     if ((reinterpret_cast<uintptr_t>(x) & 15) != 0 || (reinterpret_cast<uintptr_t>(mask) & 15) != 0) return false;
     const char* e = std::getenv("SFF_CONV_IM2COL");
@@ -457,10 +500,10 @@ extern "C" sff_status sff_conv3x3_bf16_wgrad(int32_t n, int32_t H, int32_t W, in
     const int nblk = grid.x * grid.y * grid.z;
     if (cin == 3)
         hipLaunchKernelGGL((conv_wgrad_kernel<3, 32>), grid, dim3(256), 0, st, x, dy, relu_out, part,
-                           H, W, dil);
+                           H, W, dil, 0);
     else
         hipLaunchKernelGGL((conv_wgrad_kernel<32, 32>), grid, dim3(256), 0, st, x, dy, relu_out,
-                           part, H, W, dil);
+                           part, H, W, dil, use_conv32(x, relu_out) && use_conv32(dy, nullptr) ? 1 : 0);
     const int cpad = (cin + 15) / 16 * 16;
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((cout * 9 * cin + cout + kRedOut - 1) / kRedOut), dim3(256), 0,
                        st, part, dw, db, nblk, cin, cout, cpad);

@@ -93,11 +93,12 @@ CASES32 = [(2, 17, 131, 32, 1), (1, 7, 300, 32, 1), (2, 6, 530, 32, 3), (1, 40, 
 
 @pytest.mark.parametrize("case", CASES32, ids=[str(c) for c in CASES32])
 def test_conv32_kernel_same_as_im2col(sff, case, monkeypatch):
-    """The 32-channel kernel without an im2col tile (the default for 16-byte
-    aligned tensors) against the im2col kernel (SFF_CONV_IM2COL=1) and against
-    the same tensors at a 2-byte offset (which take the im2col kernel): the
-    same MFMAs on the same values, so forward and input gradient agree bit for
-    bit."""
+    """The 32-channel kernels with 16-byte staging (the default for 16-byte
+    aligned tensors: forward and input gradient without an im2col tile, weight
+    gradient with vector-loaded transposed tiles) against the element-wise
+    kernels (SFF_CONV_IM2COL=1) and against the same tensors at a 2-byte offset
+    (which take the element-wise kernels): the same MFMAs on the same values,
+    so forward, input and weight gradients agree bit for bit."""
     import torch
     n, H, W, cin, dil = case
     rng = np.random.default_rng(7 * H + W + dil)
@@ -120,11 +121,16 @@ def test_conv32_kernel_same_as_im2col(sff, case, monkeypatch):
     dx = sff.sff_conv3x3_bf16_dgrad(_bf(dy), _bf(w), dil, _bf(relu_out))
     y_off = sff.sff_conv3x3_bf16_fwd(offset(x), _bf(w), b, dil, True)
     dx_off = sff.sff_conv3x3_bf16_dgrad(offset(dy), _bf(w), dil, offset(relu_out))
+    dw, db = sff.sff_conv3x3_bf16_wgrad(_bf(x), _bf(dy), dil, _bf(relu_out))
+    dw_off, db_off = sff.sff_conv3x3_bf16_wgrad(offset(x), offset(dy), dil, offset(relu_out))
     monkeypatch.setenv("SFF_CONV_IM2COL", "1")
     y_ref = sff.sff_conv3x3_bf16_fwd(_bf(x), _bf(w), b, dil, True)
     dx_ref = sff.sff_conv3x3_bf16_dgrad(_bf(dy), _bf(w), dil, _bf(relu_out))
+    dw_ref, db_ref = sff.sff_conv3x3_bf16_wgrad(_bf(x), _bf(dy), dil, _bf(relu_out))
     torch.cuda.synchronize()
     for got in (y, y_off):
         assert torch.equal(got.view(torch.int16), y_ref.view(torch.int16))
     for got in (dx, dx_off):
         assert torch.equal(got.view(torch.int16), dx_ref.view(torch.int16))
+    for got, ref in ((dw, dw_ref), (dw_off, dw_ref), (db, db_ref), (db_off, db_ref)):
+        assert torch.equal(got, ref)
