@@ -398,9 +398,10 @@ sff_status sff_cost_f32_bwd(int32_t batch, int32_t H, int32_t W, int32_t cf, int
  * ((ky - 1) dil, (kx - 1) dil); bias [cout] FP32.  Supported: cin in {3, 32},
  * cout = 32.  Results are rounded to BF16 (nearest even) on store.
  *   y = act(bias + sum_tap W_tap x_shifted), act = ReLU if relu != 0.
- * For cin = 32 and a 16-byte aligned x the kernel reads x in 16-byte pieces
- * without an im2col tile (SFF_CONV_IM2COL=1 forces the im2col kernel; same
- * results).
+ * For cin = 32 and 16-byte aligned tensors the forward, input-gradient and
+ * weight-gradient kernels read their inputs in 16-byte pieces (the forward
+ * without an im2col tile); SFF_CONV_IM2COL=1 forces the element-wise kernels
+ * (same results).
  * Errors: SFF_ERR_INVALID_ARG (shapes, NULL pointers, y not 8-byte aligned). */
 sff_status sff_conv3x3_bf16_fwd(int32_t n, int32_t H, int32_t W, int32_t cin, int32_t cout,
                                 int32_t dil, int32_t relu, const uint16_t* x, const uint16_t* w,
