@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(const bf16_t* __restrict_
 constexpr int kTile32 = 256;
 constexpr int kPxStride = 40;  // bf16 per staged pixel (32 used)
 constexpr int kStageW = kTile32 + 2 * kMaxDil;
+constexpr int kRows32 = 4;  // output rows per block (the weight fragments are loaded once)
 
 __global__ void __launch_bounds__(256) conv32_fwd_kernel(const bf16_t* __restrict__ x,
                                                          const bf16_t* __restrict__ mask,
@@ -130,70 +131,75 @@ __global__ void __launch_bounds__(256) conv32_fwd_kernel(const bf16_t* __restric
                                                          bf16_t* __restrict__ y, int H, int W, int dil,
                                                          int relu) {
     __shared__ __align__(16) bf16_t rows[3][kStageW * kPxStride];
-    const int x0 = blockIdx.x * kTile32, row = blockIdx.y, n = blockIdx.z;
+    const int x0 = blockIdx.x * kTile32, n = blockIdx.z;
     const size_t img = (size_t)n * H * W;
     const int nx = kTile32 + 2 * dil;  // staged pixels per row
-    // stage: 4 x 16 bytes per pixel, zero outside the image
-    for (int e = threadIdx.x; e < 3 * nx * 4; e += 256) {
-        const int ky = e / (nx * 4), r = e - ky * nx * 4, px = r >> 2, q = r & 3;
-        const int yy = row + (ky - 1) * dil, xx = x0 - dil + px;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-            const size_t o = (img + (size_t)yy * W + xx) * 32 + 8 * q;
-            v = *reinterpret_cast<const uint4*>(x + o);
-            if (mask) {
-                const uint4 m = *reinterpret_cast<const uint4*>(mask + o);
-                const uint32_t mw[4] = {m.x, m.y, m.z, m.w};
-                uint32_t vw[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    const uint32_t lo = bf2f((bf16_t)(mw[h] & 0xFFFFu)) > 0.f ? 0x0000FFFFu : 0u;
-                    const uint32_t hi = bf2f((bf16_t)(mw[h] >> 16)) > 0.f ? 0xFFFF0000u : 0u;
-                    vw[h] &= lo | hi;
-                }
-                v = make_uint4(vw[0], vw[1], vw[2], vw[3]);
-            }
-        }
-        *reinterpret_cast<uint4*>(&rows[ky][px * kPxStride + 8 * q]) = v;
-    }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ln = lane & 15, g = lane >> 4;
-    // weight fragments: output 16 t + ln, tap, channels 8 g .. 8 g + 7
+    // weight fragments: output 16 t + ln, tap, channels 8 g .. 8 g + 7 (kept for all rows)
     v8bf a[2][9];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap)
             a[t][tap] = *reinterpret_cast<const v8bf*>(w + ((size_t)(t * 16 + ln) * 9 + tap) * 32 + 8 * g);
-    __syncthreads();
-#pragma unroll 1
-    for (int grp = 0; grp < 4; ++grp) {
-        const int p = wv * 64 + grp * 16 + ln;  // pixel of this lane's B column within the tile
-        v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+    for (int rr = 0; rr < kRows32; ++rr) {
+        const int row = blockIdx.y * kRows32 + rr;
+        if (row >= H) break;  // block-uniform
+        __syncthreads();      // the previous row's reads of the staged rows are done
+        // stage: 4 x 16 bytes per pixel, zero outside the image
+        for (int e = threadIdx.x; e < 3 * nx * 4; e += 256) {
+            const int ky = e / (nx * 4), r = e - ky * nx * 4, px = r >> 2, q = r & 3;
+            const int yy = row + (ky - 1) * dil, xx = x0 - dil + px;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+                const size_t o = (img + (size_t)yy * W + xx) * 32 + 8 * q;
+                v = *reinterpret_cast<const uint4*>(x + o);
+                if (mask) {
+                    const uint4 m = *reinterpret_cast<const uint4*>(mask + o);
+                    const uint32_t mw[4] = {m.x, m.y, m.z, m.w};
+                    uint32_t vw[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int ky = tap / 3, kx = tap - 3 * ky;
-            const v8bf bv = *reinterpret_cast<const v8bf*>(&rows[ky][(p + kx * dil) * kPxStride + 8 * g]);
-            acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][tap], bv, acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][tap], bv, acc[1], 0, 0, 0);
-        }
-        const int px = x0 + p;
-        if (px < W) {
-            bf16_t* out = y + (img + (size_t)row * W + px) * 32;
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                uint32_t packed[2];
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    float v0 = acc[t][2 * h] + (bias ? bias[t * 16 + 4 * g + 2 * h] : 0.f);
-                    float v1 = acc[t][2 * h + 1] + (bias ? bias[t * 16 + 4 * g + 2 * h + 1] : 0.f);
-                    if (relu) {
-                        v0 = fmaxf(v0, 0.f);
-                        v1 = fmaxf(v1, 0.f);
+                    for (int h = 0; h < 4; ++h) {
+                        const uint32_t lo = bf2f((bf16_t)(mw[h] & 0xFFFFu)) > 0.f ? 0x0000FFFFu : 0u;
+                        const uint32_t hi = bf2f((bf16_t)(mw[h] >> 16)) > 0.f ? 0xFFFF0000u : 0u;
+                        vw[h] &= lo | hi;
                     }
-                    packed[h] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+                    v = make_uint4(vw[0], vw[1], vw[2], vw[3]);
                 }
-                *reinterpret_cast<uint2*>(out + t * 16 + 4 * g) = make_uint2(packed[0], packed[1]);
+            }
+            *reinterpret_cast<uint4*>(&rows[ky][px * kPxStride + 8 * q]) = v;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int grp = 0; grp < 4; ++grp) {
+            const int p = wv * 64 + grp * 16 + ln;  // pixel of this lane's B column within the tile
+            v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int ky = tap / 3, kx = tap - 3 * ky;
+                const v8bf bv = *reinterpret_cast<const v8bf*>(&rows[ky][(p + kx * dil) * kPxStride + 8 * g]);
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][tap], bv, acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][tap], bv, acc[1], 0, 0, 0);
+            }
+            const int px = x0 + p;
+            if (px < W) {
+                bf16_t* out = y + (img + (size_t)row * W + px) * 32;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    uint32_t packed[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        float v0 = acc[t][2 * h] + (bias ? bias[t * 16 + 4 * g + 2 * h] : 0.f);
+                        float v1 = acc[t][2 * h + 1] + (bias ? bias[t * 16 + 4 * g + 2 * h + 1] : 0.f);
+                        if (relu) {
+                            v0 = fmaxf(v0, 0.f);
+                            v1 = fmaxf(v1, 0.f);
+                        }
+                        packed[h] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+                    }
+                    *reinterpret_cast<uint2*>(out + t * 16 + 4 * g) = make_uint2(packed[0], packed[1]);
+                }
             }
         }
     }
@@ -444,7 +450,7 @@ extern "C" sff_status sff_conv3x3_bf16_fwd(int32_t n, int32_t H, int32_t W, int3
         hipLaunchKernelGGL((conv_fwd_kernel<3, 32>), grid, dim3(256), 0, st, x, nullptr, w, bias, y,
                            H, W, dil, relu);
     else if (use_conv32(x, nullptr))
-        hipLaunchKernelGGL(conv32_fwd_kernel, dim3((W + kTile32 - 1) / kTile32, H, n), dim3(256), 0, st, x,
+        hipLaunchKernelGGL(conv32_fwd_kernel, dim3((W + kTile32 - 1) / kTile32, (H + kRows32 - 1) / kRows32, n), dim3(256), 0, st, x,
                            nullptr, w, bias, y, H, W, dil, relu);
     else
         hipLaunchKernelGGL((conv_fwd_kernel<32, 32>), grid, dim3(256), 0, st, x, nullptr, w, bias,
@@ -475,7 +481,7 @@ extern "C" sff_status sff_conv3x3_bf16_dgrad(int32_t n, int32_t H, int32_t W, in
     hipLaunchKernelGGL(flip_weights_kernel, dim3((cin * 9 * cout + 255) / 256), dim3(256), 0, st, w,
                        wt, cin, cout);
     if (use_conv32(dy, relu_out))
-        hipLaunchKernelGGL(conv32_fwd_kernel, dim3((W + kTile32 - 1) / kTile32, H, n), dim3(256), 0, st, dy,
+        hipLaunchKernelGGL(conv32_fwd_kernel, dim3((W + kTile32 - 1) / kTile32, (H + kRows32 - 1) / kRows32, n), dim3(256), 0, st, dy,
                            relu_out, wt, nullptr, dx, H, W, dil, 0);
     else
         hipLaunchKernelGGL((conv_fwd_kernel<32, 32>), dim3((W + kTilePx - 1) / kTilePx, H, n), dim3(256),
