@@ -205,6 +205,79 @@ __global__ void __launch_bounds__(256) conv32_fwd_kernel(const bf16_t* __restric
     }
 }
 
+// The first layer (Cin = 3: K = 27, one MFMA step) without an im2col tile:
+// the three input rows of a 256-pixel tile are staged in LDS and each lane
+// reads its 8 (tap, channel) K values straight from them; the two weight
+// fragments stay in registers for the block's rows.  Same operands as
+// conv_fwd_kernel<3, 32>, so the same results.
+__global__ void __launch_bounds__(256) conv3_fwd_kernel(const bf16_t* __restrict__ x,
+                                                        const bf16_t* __restrict__ w,
+                                                        const float* __restrict__ bias,
+                                                        bf16_t* __restrict__ y, int H, int W, int dil,
+                                                        int relu) {
+    __shared__ bf16_t rows[3][kStageW * 3];
+    const int x0 = blockIdx.x * kTile32, n = blockIdx.z;
+    const size_t img = (size_t)n * H * W;
+    const int nx = kTile32 + 2 * dil;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ln = lane & 15, g = lane >> 4;
+    v8bf a[2];
+    int koff[8];  // LDS offset of K value 8 g + e relative to the lane's pixel (-1: zero padding)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int k = 8 * g + e;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            a[t][e] = __builtin_bit_cast(__bf16, k < 27 ? w[(size_t)(t * 16 + ln) * 27 + k] : (bf16_t)0);
+        const int tap = k / 3, ci = k - 3 * tap, ky = tap / 3, kx = tap - 3 * ky;
+        koff[e] = k < 27 ? ky * kStageW * 3 + kx * dil * 3 + ci : -1;
+    }
+    for (int rr = 0; rr < kRows32; ++rr) {
+        const int row = blockIdx.y * kRows32 + rr;
+        if (row >= H) break;  // block-uniform
+        __syncthreads();
+        for (int e = threadIdx.x; e < 3 * nx * 3; e += 256) {
+            const int ky = e / (nx * 3), r = e - ky * nx * 3, px = r / 3, ci = r - 3 * px;
+            const int yy = row + (ky - 1) * dil, xx = x0 - dil + px;
+            bf16_t v = 0;
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W) v = x[(img + (size_t)yy * W + xx) * 3 + ci];
+            rows[ky][px * 3 + ci] = v;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int grp = 0; grp < 4; ++grp) {
+            const int p = wv * 64 + grp * 16 + ln;
+            const bf16_t* src = &rows[0][p * 3];
+            v8bf bv;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bv[e] = __builtin_bit_cast(__bf16, koff[e] >= 0 ? src[koff[e]] : (bf16_t)0);
+            v4f acc[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bv, v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            const int px = x0 + p;
+            if (px < W) {
+                bf16_t* out = y + (img + (size_t)row * W + px) * 32;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    uint32_t packed[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        float v0 = acc[t][2 * h] + (bias ? bias[t * 16 + 4 * g + 2 * h] : 0.f);
+                        float v1 = acc[t][2 * h + 1] + (bias ? bias[t * 16 + 4 * g + 2 * h + 1] : 0.f);
+                        if (relu) {
+                            v0 = fmaxf(v0, 0.f);
+                            v1 = fmaxf(v1, 0.f);
+                        }
+                        packed[h] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+                    }
+                    *reinterpret_cast<uint2*>(out + t * 16 + 4 * g) = make_uint2(packed[0], packed[1]);
+                }
+            }
+        }
+    }
+}
+
 // W'[i][ky][kx][o] = W[o][2 - ky][2 - kx][i]
 __global__ void flip_weights_kernel(const bf16_t* __restrict__ w, bf16_t* __restrict__ wt, int cin,
                                     int cout) {
@@ -446,7 +519,10 @@ extern "C" sff_status sff_conv3x3_bf16_fwd(int32_t n, int32_t H, int32_t W, int3
     if ((reinterpret_cast<uintptr_t>(y) & 7) != 0) return SFF_ERR_INVALID_ARG;
     const dim3 grid((W + kTilePx - 1) / kTilePx, H, n);
     hipStream_t st = as_stream(stream);
-    if (cin == 3)
+    if (cin == 3 && use_conv32(nullptr, nullptr))
+        hipLaunchKernelGGL(conv3_fwd_kernel, dim3((W + kTile32 - 1) / kTile32, (H + kRows32 - 1) / kRows32, n),
+                           dim3(256), 0, st, x, w, bias, y, H, W, dil, relu);
+    else if (cin == 3)
         hipLaunchKernelGGL((conv_fwd_kernel<3, 32>), grid, dim3(256), 0, st, x, nullptr, w, bias, y,
                            H, W, dil, relu);
     else if (use_conv32(x, nullptr))

@@ -134,3 +134,28 @@ def test_conv32_kernel_same_as_im2col(sff, case, monkeypatch):
         assert torch.equal(got.view(torch.int16), dx_ref.view(torch.int16))
     for got, ref in ((dw, dw_ref), (dw_off, dw_ref), (db, db_ref), (db_off, db_ref)):
         assert torch.equal(got, ref)
+
+
+@pytest.mark.parametrize("case", [(2, 9, 70, 1), (1, 7, 300, 1), (1, 12, 530, 4), (1, 40, 270, 16), (1, 1, 1, 1)],
+                         ids=str)
+def test_first_layer_kernel_same_as_im2col(sff, case, monkeypatch):
+    """The 3-channel first layer read from staged input rows (the default)
+    against the im2col kernel (SFF_CONV_IM2COL=1): the same MFMA operands, so
+    the same bits; and against the FP64 oracle."""
+    import torch
+    n, H, W, dil = case
+    rng = np.random.default_rng(H + 3 * W + dil)
+    x = ofn.bf16_round(rng.standard_normal((n, H, W, 3)))
+    w = ofn.bf16_round(rng.standard_normal((32, 3, 3, 3)) / np.sqrt(27))
+    b = rng.standard_normal(32).astype(np.float32)
+    bt = torch.from_numpy(b).cuda()
+    _say("first layer vs im2col", case)
+    monkeypatch.delenv("SFF_CONV_IM2COL", raising=False)
+    y = sff.sff_conv3x3_bf16_fwd(_bf(x), _bf(w), bt, dil, True)
+    monkeypatch.setenv("SFF_CONV_IM2COL", "1")
+    y_ref = sff.sff_conv3x3_bf16_fwd(_bf(x), _bf(w), bt, dil, True)
+    torch.cuda.synchronize()
+    assert torch.equal(y.view(torch.int16), y_ref.view(torch.int16))
+    ref = ofn.bf16_round(ofn.conv3x3(x, w, b.astype(np.float64), dil, True))
+    S = ofn.conv3x3(np.abs(x), np.abs(w), np.abs(b.astype(np.float64)), dil)
+    assert _within_bf16_ulp(_np(y), ref, S).all()
