@@ -494,10 +494,14 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // in 16-byte pieces; unaligned tensors and SFF_CONV_IM2COL=1 (testing and
 // timing) take the element-wise kernels (the im2col forward, element-wise
 // staging of the gradient tiles), which give the same results.
-bool use_conv32(const void* x, const void* mask) {
-    if ((reinterpret_cast<uintptr_t>(x) & 15) != 0 || (reinterpret_cast<uintptr_t>(mask) & 15) != 0) return false;
+bool staged_conv_enabled() {
     const char* e = std::getenv("SFF_CONV_IM2COL");
     return !(e && std::strcmp(e, "1") == 0);
+}
+
+bool use_conv32(const void* x, const void* mask) {
+    if ((reinterpret_cast<uintptr_t>(x) & 15) != 0 || (reinterpret_cast<uintptr_t>(mask) & 15) != 0) return false;
+    return staged_conv_enabled();
 }
 
 size_t wgrad_part_bytes(int n, int H, int W, int cin, int cout) {
@@ -519,7 +523,7 @@ extern "C" sff_status sff_conv3x3_bf16_fwd(int32_t n, int32_t H, int32_t W, int3
     if ((reinterpret_cast<uintptr_t>(y) & 7) != 0) return SFF_ERR_INVALID_ARG;
     const dim3 grid((W + kTilePx - 1) / kTilePx, H, n);
     hipStream_t st = as_stream(stream);
-    if (cin == 3 && use_conv32(nullptr, nullptr))
+    if (cin == 3 && staged_conv_enabled())
         hipLaunchKernelGGL(conv3_fwd_kernel, dim3((W + kTile32 - 1) / kTile32, (H + kRows32 - 1) / kRows32, n),
                            dim3(256), 0, st, x, w, bias, y, H, W, dil, relu);
     else if (cin == 3)
