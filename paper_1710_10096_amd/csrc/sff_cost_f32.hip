@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(256) cost_fwd_coop_kernel(CostArgs a) {
     const int sub = threadIdx.x % L;
     const int H = a.H, W = a.W, b = blockIdx.y;
     const size_t HW = (size_t)H * W;
-    const size_t q = (size_t)blockIdx.x * QPB + threadIdx.x / L;
+    const size_t q = (size_t)xcd_tile(blockIdx.x, gridDim.x) * QPB + threadIdx.x / L;  // a band of rows per XCD
     if (q >= HW) return;  // all L lanes of the pixel together
     const int y = (int)(q / W), x = (int)(q - (size_t)y * W);
     const float* base = a.feat + (size_t)b * 4 * HW * CF;
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(256) grad_ref_coop_kernel(CostArgs a) {
     const int sub = threadIdx.x % L;
     const int H = a.H, W = a.W, b = blockIdx.y;
     const size_t HW = (size_t)H * W;
-    const size_t q = (size_t)blockIdx.x * QPB + threadIdx.x / L;
+    const size_t q = (size_t)xcd_tile(blockIdx.x, gridDim.x) * QPB + threadIdx.x / L;  // a band of rows per XCD
     if (q >= HW) return;  // all L lanes of the entry together
     const int qy = (int)(q / W), qx = (int)(q - (size_t)qy * W);
     const float* base = a.feat + (size_t)b * 4 * HW * CF;
@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k
     const int sub = threadIdx.x % L;
     const int H = a.H, W = a.W, b = blockIdx.y;
     const size_t HW = (size_t)H * W;
-    const size_t q = (size_t)blockIdx.x * QPB + threadIdx.x / L;
+    const size_t q = (size_t)xcd_tile(blockIdx.x, gridDim.x) * QPB + threadIdx.x / L;  // a band of rows per XCD
     if (q >= HW) return;  // all L lanes of the entry together
     const int qy = (int)(q / W), qx = (int)(q - (size_t)qy * W);
     const float* base = a.feat + (size_t)b * 4 * HW * CF;
