@@ -296,6 +296,12 @@ __global__ void cell_starts_kernel(const uint32_t* __restrict__ keys, uint32_t* 
     for (int64_t c = kp + 1; c <= k; ++c) start[c] = (uint32_t)i;
 }
 
+// The target gradients gather the window rows in kRowSplit parts of kPartRows
+// consecutive rows each, summed in part order.
+constexpr int kRowSplit = 4;
+constexpr int kPartRows = (kWin1 - kWin0 + 1) / kRowSplit;
+static_assert(kPartRows * kRowSplit == kWin1 - kWin0 + 1, "rows split evenly");
+
 // Gradient of target map k: one thread per entry q of that map; gathers over
 // the centres t with clamp(t + w) = q and the pixels grouped at each centre.
 template <int CF>
@@ -313,37 +319,47 @@ __global__ void __launch_bounds__(256) grad_target_kernel(CostArgs a, int k,
     const int mk = view(a.s, k + 1);
     float fq[CF], acc[CF];
     load_vec<CF>(base + ((size_t)mk * HW + (size_t)qy * W + qx) * CF, fq);
-#pragma unroll
-    for (int c = 0; c < CF; ++c) acc[c] = 0.f;
-    for (int wy = kWin0; wy <= kWin1; ++wy) {
-        int ylo, yhi;
-        preimage(qy, wy, H, ylo, yhi);
-        for (int ty = ylo; ty <= yhi; ++ty)
-            for (int wx = kWin1; wx >= kWin0; --wx) {  // target cells in ascending x
-                int xlo, xhi;
-                preimage(qx, wx, W, xlo, xhi);
-                for (int tx = xlo; tx <= xhi; ++tx) {
-                    const size_t cell = (size_t)b * HW + (size_t)ty * W + tx;
-                    const uint32_t e0 = start[cell], e1 = start[cell + 1];
-                    for (uint32_t e = e0; e < e1; ++e) {
-                        const uint32_t pix = order[e];
-                        const int pl = (int)(pix - (size_t)b * HW);
-                        const int py = pl / W, px = pl - py * W;
-                        const float g2 = 2.f * a.gcost[pix];
-                        float r[CF];
-                        load_vec<CF>(R + ((size_t)clampi(py + wy, 0, H - 1) * W +
-                                          clampi(px + wx, 0, W - 1)) * CF, r);
-#pragma unroll
-                        for (int c = 0; c < CF; ++c) acc[c] = fmaf(-g2, r[c] - fq[c], acc[c]);
-                    }
-                }
-            }
-    }
     float4* o = reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mk * HW +
                                                    (size_t)qy * W + qx) * CF);
+    // the window rows in kRowSplit parts of consecutive rows; the gradient is
+    // ((part 0 + part 1) + part 2) + ...
+    for (int part = 0; part < kRowSplit; ++part) {
 #pragma unroll
-    for (int kk = 0; kk < CF / 4; ++kk)
-        o[kk] = make_float4(acc[4 * kk], acc[4 * kk + 1], acc[4 * kk + 2], acc[4 * kk + 3]);
+        for (int c = 0; c < CF; ++c) acc[c] = 0.f;
+        for (int wy = kWin0 + part * kPartRows; wy < kWin0 + (part + 1) * kPartRows; ++wy) {
+            int ylo, yhi;
+            preimage(qy, wy, H, ylo, yhi);
+            for (int ty = ylo; ty <= yhi; ++ty)
+                for (int wx = kWin1; wx >= kWin0; --wx) {  // target cells in ascending x
+                    int xlo, xhi;
+                    preimage(qx, wx, W, xlo, xhi);
+                    for (int tx = xlo; tx <= xhi; ++tx) {
+                        const size_t cell = (size_t)b * HW + (size_t)ty * W + tx;
+                        const uint32_t e0 = start[cell], e1 = start[cell + 1];
+                        for (uint32_t e = e0; e < e1; ++e) {
+                            const uint32_t pix = order[e];
+                            const int pl = (int)(pix - (size_t)b * HW);
+                            const int py = pl / W, px = pl - py * W;
+                            const float g2 = 2.f * a.gcost[pix];
+                            float r[CF];
+                            load_vec<CF>(R + ((size_t)clampi(py + wy, 0, H - 1) * W +
+                                              clampi(px + wx, 0, W - 1)) * CF, r);
+#pragma unroll
+                            for (int c = 0; c < CF; ++c) acc[c] = fmaf(-g2, r[c] - fq[c], acc[c]);
+                        }
+                    }
+                }
+        }
+#pragma unroll
+        for (int kk = 0; kk < CF / 4; ++kk) {
+            float4 v = make_float4(acc[4 * kk], acc[4 * kk + 1], acc[4 * kk + 2], acc[4 * kk + 3]);
+            if (part) {
+                const float4 lo = o[kk];
+                v = make_float4(lo.x + v.x, lo.y + v.y, lo.z + v.z, lo.w + v.w);
+            }
+            o[kk] = v;
+        }
+    }
 }
 
 // The same gradient with CF / 4 lanes per target entry, each owning four
@@ -351,18 +367,22 @@ __global__ void __launch_bounds__(256) grad_target_kernel(CostArgs a, int k,
 // neighbouring lanes (a few cache lines per load instruction instead of one per
 // lane), a lane holds a float4 accumulator instead of CF, and a wave covers
 // 256 / (CF / 4) / 4 entries, so far fewer lanes wait on the slowest entry of
-// their wave.  Every channel adds the same terms in the same order as
-// grad_target_kernel, so the results are identical.
+// their wave.  kRowSplit groups of CF / 4 lanes share an entry, each taking
+// one part of the window rows, which shortens the serial chain of each; every
+// channel adds the same terms in the same order as grad_target_kernel (each
+// part in turn, then their sum in part order), so the results are identical.
 template <int CF>
 __global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k,
                                                                const uint32_t* __restrict__ start,
                                                                const uint32_t* __restrict__ order) {
-    constexpr int L = CF / 4, QPB = 256 / L;
-    const int sub = threadIdx.x % L;
+    constexpr int L = CF / 4, G = kRowSplit * L, QPB = 256 / G;
+    static_assert(G <= 64, "the parts of an entry share one wave");
+    const int sub = threadIdx.x % L, part = (threadIdx.x / L) % kRowSplit;
+    const int wy0 = kWin0 + part * kPartRows, wy1 = wy0 + kPartRows - 1;  // this part's window rows
     const int H = a.H, W = a.W, b = blockIdx.y;
     const size_t HW = (size_t)H * W;
-    const size_t q = (size_t)xcd_tile(blockIdx.x, gridDim.x) * QPB + threadIdx.x / L;  // a band of rows per XCD
-    if (q >= HW) return;  // all L lanes of the entry together
+    const size_t q = (size_t)xcd_tile(blockIdx.x, gridDim.x) * QPB + threadIdx.x / G;  // a band of rows per XCD
+    if (q >= HW) return;  // all G lanes of the entry together
     const int qy = (int)(q / W), qx = (int)(q - (size_t)qy * W);
     const float* base = a.feat + (size_t)b * 4 * HW * CF;
     const float4* R = reinterpret_cast<const float4*>(base + (size_t)view(a.s, 0) * HW * CF) + sub;
@@ -384,7 +404,7 @@ __global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k
         // interior: window row wy covers the centre cells (qy - wy, qx - 4 .. qx + 3), consecutive,
         // so their pixels are one run [st[0], st[8]) of the sorted order; it is walked in that
         // order (cells by ascending x, the order of the generic loop below) four at a time
-        for (int wy = kWin0; wy <= kWin1; ++wy) {
+        for (int wy = wy0; wy <= wy1; ++wy) {
             const size_t c0 = (size_t)b * HW + (size_t)(qy - wy) * W + (qx - kWin1);
             uint32_t st[kN + 1];
 #pragma unroll
@@ -407,7 +427,7 @@ __global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k
             }
         }
     } else {
-        for (int wy = kWin0; wy <= kWin1; ++wy) {
+        for (int wy = wy0; wy <= wy1; ++wy) {
             int ylo, yhi;
             preimage(qy, wy, H, ylo, yhi);
             for (int ty = ylo; ty <= yhi; ++ty)
@@ -422,7 +442,18 @@ __global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k
                 }
         }
     }
-    reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mk * HW + q) * CF)[sub] = acc;
+    // ((part 0 + part 1) + part 2) + ..., as the one-lane kernel adds them
+    float4 sum = acc;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int g = 1; g < kRowSplit; ++g) {
+        const int src = lane + g * L;  // part g of this entry, for the lanes of part 0
+        sum.x += __shfl(acc.x, src);
+        sum.y += __shfl(acc.y, src);
+        sum.z += __shfl(acc.z, src);
+        sum.w += __shfl(acc.w, src);
+    }
+    if (part == 0) reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mk * HW + q) * CF)[sub] = sum;
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -569,7 +600,8 @@ extern "C" sff_status sff_cost_f32_bwd(int32_t batch, int32_t H, int32_t W, int3
         if (lane_grad)
             launch_cf<TgtK>(cf, grid, st, a, k, (const uint32_t*)start, (const uint32_t*)order);
         else
-            launch_cf<TgtCoopK>(cf, cgrid, st, a, k, (const uint32_t*)start, (const uint32_t*)order);
+            launch_cf<TgtCoopK>(cf, dim3((unsigned)(((size_t)H * W * (cf / 4) * kRowSplit + 255) / 256), batch), st, a, k,
+                                (const uint32_t*)start, (const uint32_t*)order);
     }
     return launch_status();
 }
