@@ -296,11 +296,11 @@ __global__ void cell_starts_kernel(const uint32_t* __restrict__ keys, uint32_t* 
     for (int64_t c = kp + 1; c <= k; ++c) start[c] = (uint32_t)i;
 }
 
-// The target gradients gather the window rows in kRowSplit parts of kPartRows
-// consecutive rows each, summed in part order.
-constexpr int kRowSplit = 4;
-constexpr int kPartRows = (kWin1 - kWin0 + 1) / kRowSplit;
-static_assert(kPartRows * kRowSplit == kWin1 - kWin0 + 1, "rows split evenly");
+// The target gradients gather the window rows in row_split(CF) parts of
+// consecutive rows, summed in part order: eight single rows up to 32 channels,
+// four pairs of rows at 64 (the CF / 4 lanes of every part of an entry share
+// one wave).
+constexpr int row_split(int cf) { return cf <= 32 ? 8 : 4; }
 
 // Gradient of target map k: one thread per entry q of that map; gathers over
 // the centres t with clamp(t + w) = q and the pixels grouped at each centre.
@@ -321,9 +321,11 @@ __global__ void __launch_bounds__(256) grad_target_kernel(CostArgs a, int k,
     load_vec<CF>(base + ((size_t)mk * HW + (size_t)qy * W + qx) * CF, fq);
     float4* o = reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mk * HW +
                                                    (size_t)qy * W + qx) * CF);
-    // the window rows in kRowSplit parts of consecutive rows; the gradient is
+    // the window rows in kSplit parts of consecutive rows; the gradient is
     // ((part 0 + part 1) + part 2) + ...
-    for (int part = 0; part < kRowSplit; ++part) {
+    constexpr int kSplit = row_split(CF), kPartRows = (kWin1 - kWin0 + 1) / kSplit;
+    static_assert(kPartRows * kSplit == kWin1 - kWin0 + 1, "rows split evenly");
+    for (int part = 0; part < kSplit; ++part) {
 #pragma unroll
         for (int c = 0; c < CF; ++c) acc[c] = 0.f;
         for (int wy = kWin0 + part * kPartRows; wy < kWin0 + (part + 1) * kPartRows; ++wy) {
@@ -367,7 +369,7 @@ __global__ void __launch_bounds__(256) grad_target_kernel(CostArgs a, int k,
 // neighbouring lanes (a few cache lines per load instruction instead of one per
 // lane), a lane holds a float4 accumulator instead of CF, and a wave covers
 // 256 / (CF / 4) / 4 entries, so far fewer lanes wait on the slowest entry of
-// their wave.  kRowSplit groups of CF / 4 lanes share an entry, each taking
+// their wave.  row_split(CF) groups of CF / 4 lanes share an entry, each taking
 // one part of the window rows, which shortens the serial chain of each; every
 // channel adds the same terms in the same order as grad_target_kernel (each
 // part in turn, then their sum in part order), so the results are identical.
@@ -375,9 +377,10 @@ template <int CF>
 __global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k,
                                                                const uint32_t* __restrict__ start,
                                                                const uint32_t* __restrict__ order) {
-    constexpr int L = CF / 4, G = kRowSplit * L, QPB = 256 / G;
+    constexpr int kSplit = row_split(CF), kPartRows = (kWin1 - kWin0 + 1) / kSplit;
+    constexpr int L = CF / 4, G = kSplit * L, QPB = 256 / G;
     static_assert(G <= 64, "the parts of an entry share one wave");
-    const int sub = threadIdx.x % L, part = (threadIdx.x / L) % kRowSplit;
+    const int sub = threadIdx.x % L, part = (threadIdx.x / L) % kSplit;
     const int wy0 = kWin0 + part * kPartRows, wy1 = wy0 + kPartRows - 1;  // this part's window rows
     const int H = a.H, W = a.W, b = blockIdx.y;
     const size_t HW = (size_t)H * W;
@@ -446,7 +449,7 @@ __global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k
     float4 sum = acc;
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int g = 1; g < kRowSplit; ++g) {
+    for (int g = 1; g < kSplit; ++g) {
         const int src = lane + g * L;  // part g of this entry, for the lanes of part 0
         sum.x += __shfl(acc.x, src);
         sum.y += __shfl(acc.y, src);
@@ -600,7 +603,7 @@ extern "C" sff_status sff_cost_f32_bwd(int32_t batch, int32_t H, int32_t W, int3
         if (lane_grad)
             launch_cf<TgtK>(cf, grid, st, a, k, (const uint32_t*)start, (const uint32_t*)order);
         else
-            launch_cf<TgtCoopK>(cf, dim3((unsigned)(((size_t)H * W * (cf / 4) * kRowSplit + 255) / 256), batch), st, a, k,
+            launch_cf<TgtCoopK>(cf, dim3((unsigned)(((size_t)H * W * (cf / 4) * row_split(cf) + 255) / 256), batch), st, a, k,
                                 (const uint32_t*)start, (const uint32_t*)order);
     }
     return launch_status();
