@@ -17,6 +17,7 @@
 // Both are deterministic (no floating-point atomics).
 #include <rocprim/device/device_radix_sort.hpp>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 
@@ -364,6 +365,11 @@ __global__ void __launch_bounds__(256) grad_target_kernel(CostArgs a, int k,
     }
 }
 
+// Blocks of the target-gradient launch (a multiple of 8): 32 per compute unit,
+// four times what is resident at once, so that blocks with short tiles are
+// followed by others; 8 per unit measured 7% slower, 16 to 64 the same.
+constexpr size_t kTgtBlocks = 256 * 32;
+
 // The same gradient with CF / 4 lanes per target entry, each owning four
 // channels: a gathered vector is CF / 4 consecutive 16-byte loads of
 // neighbouring lanes (a few cache lines per load instruction instead of one per
@@ -384,79 +390,88 @@ __global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k
     const int wy0 = kWin0 + part * kPartRows, wy1 = wy0 + kPartRows - 1;  // this part's window rows
     const int H = a.H, W = a.W, b = blockIdx.y;
     const size_t HW = (size_t)H * W;
-    const size_t q = (size_t)xcd_tile(blockIdx.x, gridDim.x) * QPB + threadIdx.x / G;  // a band of rows per XCD
-    if (q >= HW) return;  // all G lanes of the entry together
-    const int qy = (int)(q / W), qx = (int)(q - (size_t)qy * W);
     const float* base = a.feat + (size_t)b * 4 * HW * CF;
     const float4* R = reinterpret_cast<const float4*>(base + (size_t)view(a.s, 0) * HW * CF) + sub;
     const int mk = view(a.s, k + 1);
-    const float4 fq = reinterpret_cast<const float4*>(base + ((size_t)mk * HW + q) * CF)[sub];
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    auto add = [&](uint32_t pix, int wy, int wx) {
-        const int pl = (int)(pix - (size_t)b * HW);
-        const int py = pl / W, px = pl - py * W;
-        const float g2 = 2.f * a.gcost[pix];
-        const float4 r = R[((size_t)clampi(py + wy, 0, H - 1) * W + clampi(px + wx, 0, W - 1)) * L];
-        acc.x = fmaf(-g2, r.x - fq.x, acc.x);
-        acc.y = fmaf(-g2, r.y - fq.y, acc.y);
-        acc.z = fmaf(-g2, r.z - fq.z, acc.z);
-        acc.w = fmaf(-g2, r.w - fq.w, acc.w);
-    };
-    constexpr int kN = kWin1 - kWin0 + 1;  // 8 window columns
-    if (qy >= kWin1 && qy <= H - 1 + kWin0 && qx >= kWin1 && qx <= W - 1 + kWin0) {
-        // interior: window row wy covers the centre cells (qy - wy, qx - 4 .. qx + 3), consecutive,
-        // so their pixels are one run [st[0], st[8]) of the sorted order; it is walked in that
-        // order (cells by ascending x, the order of the generic loop below) four at a time
-        for (int wy = wy0; wy <= wy1; ++wy) {
-            const size_t c0 = (size_t)b * HW + (size_t)(qy - wy) * W + (qx - kWin1);
-            uint32_t st[kN + 1];
+    // A fixed grid (a multiple of 8 blocks) walks the tiles of QPB entries: the
+    // blocks of one XCD take that XCD's band of image rows in turn, so a wave
+    // handles many entries instead of one short entry each.
+    const int ntiles = (int)((HW + QPB - 1) / QPB);
+    const int xcd = blockIdx.x & 7, per = gridDim.x >> 3, nq = ntiles >> 3, rem = ntiles & 7;
+    const int t0 = xcd * nq + min(xcd, rem), t1 = t0 + nq + (xcd < rem ? 1 : 0);
+    for (int tile = t0 + (int)(blockIdx.x >> 3); tile < t1; tile += per) {
+        const size_t q = (size_t)tile * QPB + threadIdx.x / G;
+        if (q >= HW) continue;  // all G lanes of the entry together; only in the last tile
+        const int qy = (int)(q / W), qx = (int)(q - (size_t)qy * W);
+        const float4 fq = reinterpret_cast<const float4*>(base + ((size_t)mk * HW + q) * CF)[sub];
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        auto add = [&](uint32_t pix, int wy, int wx) {
+            const int pl = (int)(pix - (size_t)b * HW);
+            const int py = pl / W, px = pl - py * W;
+            const float g2 = 2.f * a.gcost[pix];
+            const float4 r = R[((size_t)clampi(py + wy, 0, H - 1) * W + clampi(px + wx, 0, W - 1)) * L];
+            acc.x = fmaf(-g2, r.x - fq.x, acc.x);
+            acc.y = fmaf(-g2, r.y - fq.y, acc.y);
+            acc.z = fmaf(-g2, r.z - fq.z, acc.z);
+            acc.w = fmaf(-g2, r.w - fq.w, acc.w);
+        };
+        constexpr int kN = kWin1 - kWin0 + 1;  // 8 window columns
+        if (qy >= kWin1 && qy <= H - 1 + kWin0 && qx >= kWin1 && qx <= W - 1 + kWin0) {
+            // interior: window row wy covers the centre cells (qy - wy, qx - 4 .. qx + 3), consecutive,
+            // so their pixels are one run [st[0], st[8]) of the sorted order; it is walked in that
+            // order (cells by ascending x, the order of the generic loop below) four at a time
+            for (int wy = wy0; wy <= wy1; ++wy) {
+                const size_t c0 = (size_t)b * HW + (size_t)(qy - wy) * W + (qx - kWin1);
+                uint32_t st[kN + 1];
 #pragma unroll
-            for (int j = 0; j <= kN; ++j) st[j] = start[c0 + j];
-            for (uint32_t e = st[0]; e < st[kN]; e += 4) {
-                uint32_t pv[4];
-                int wxv[4];
+                for (int j = 0; j <= kN; ++j) st[j] = start[c0 + j];
+                for (uint32_t e = st[0]; e < st[kN]; e += 4) {
+                    uint32_t pv[4];
+                    int wxv[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t eu = min(e + u, st[kN] - 1);
-                    pv[u] = order[eu];
-                    int j = 0;
+                    for (int u = 0; u < 4; ++u) {
+                        const uint32_t eu = min(e + u, st[kN] - 1);
+                        pv[u] = order[eu];
+                        int j = 0;
 #pragma unroll
-                    for (int jj = 1; jj < kN; ++jj) j += eu >= st[jj] ? 1 : 0;
-                    wxv[u] = kWin1 - j;
+                        for (int jj = 1; jj < kN; ++jj) j += eu >= st[jj] ? 1 : 0;
+                        wxv[u] = kWin1 - j;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (e + u < st[kN]) add(pv[u], wy, wxv[u]);
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (e + u < st[kN]) add(pv[u], wy, wxv[u]);
+            }
+        } else {
+            for (int wy = wy0; wy <= wy1; ++wy) {
+                int ylo, yhi;
+                preimage(qy, wy, H, ylo, yhi);
+                for (int ty = ylo; ty <= yhi; ++ty)
+                    for (int wx = kWin1; wx >= kWin0; --wx) {  // target cells in ascending x
+                        int xlo, xhi;
+                        preimage(qx, wx, W, xlo, xhi);
+                        for (int tx = xlo; tx <= xhi; ++tx) {
+                            const size_t cell = (size_t)b * HW + (size_t)ty * W + tx;
+                            const uint32_t e0 = start[cell], e1 = start[cell + 1];
+                            for (uint32_t e = e0; e < e1; ++e) add(order[e], wy, wx);
+                        }
+                    }
             }
         }
-    } else {
-        for (int wy = wy0; wy <= wy1; ++wy) {
-            int ylo, yhi;
-            preimage(qy, wy, H, ylo, yhi);
-            for (int ty = ylo; ty <= yhi; ++ty)
-                for (int wx = kWin1; wx >= kWin0; --wx) {  // target cells in ascending x
-                    int xlo, xhi;
-                    preimage(qx, wx, W, xlo, xhi);
-                    for (int tx = xlo; tx <= xhi; ++tx) {
-                        const size_t cell = (size_t)b * HW + (size_t)ty * W + tx;
-                        const uint32_t e0 = start[cell], e1 = start[cell + 1];
-                        for (uint32_t e = e0; e < e1; ++e) add(order[e], wy, wx);
-                    }
-                }
-        }
-    }
-    // ((part 0 + part 1) + part 2) + ..., as the one-lane kernel adds them
-    float4 sum = acc;
-    const int lane = threadIdx.x & 63;
+        // ((part 0 + part 1) + part 2) + ..., as the one-lane kernel adds them
+        float4 sum = acc;
+        const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int g = 1; g < kSplit; ++g) {
-        const int src = lane + g * L;  // part g of this entry, for the lanes of part 0
-        sum.x += __shfl(acc.x, src);
-        sum.y += __shfl(acc.y, src);
-        sum.z += __shfl(acc.z, src);
-        sum.w += __shfl(acc.w, src);
+        for (int g = 1; g < kSplit; ++g) {
+            const int src = lane + g * L;  // part g of this entry, for the lanes of part 0
+            sum.x += __shfl(acc.x, src);
+            sum.y += __shfl(acc.y, src);
+            sum.z += __shfl(acc.z, src);
+            sum.w += __shfl(acc.w, src);
+        }
+        if (part == 0)
+            reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mk * HW + q) * CF)[sub] = sum;
     }
-    if (part == 0) reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mk * HW + q) * CF)[sub] = sum;
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -603,8 +618,8 @@ extern "C" sff_status sff_cost_f32_bwd(int32_t batch, int32_t H, int32_t W, int3
         if (lane_grad)
             launch_cf<TgtK>(cf, grid, st, a, k, (const uint32_t*)start, (const uint32_t*)order);
         else
-            launch_cf<TgtCoopK>(cf, dim3((unsigned)(((size_t)H * W * (cf / 4) * row_split(cf) + 255) / 256), batch), st, a, k,
-                                (const uint32_t*)start, (const uint32_t*)order);
+            launch_cf<TgtCoopK>(cf, dim3((unsigned)std::min<size_t>(((((size_t)H * W * (cf / 4) * row_split(cf) + 255) / 256) + 7) & ~(size_t)7, kTgtBlocks), batch),
+                                st, a, k, (const uint32_t*)start, (const uint32_t*)order);
     }
     return launch_status();
 }
