@@ -366,8 +366,8 @@ __global__ void __launch_bounds__(256) grad_target_kernel(CostArgs a, int k,
 }
 
 // Blocks of the target-gradient launch (a multiple of 8): 32 per compute unit,
-// four times what is resident at once, so that blocks with short tiles are
-// followed by others; 8 per unit measured 7% slower, 16 to 64 the same.
+// four times what is resident at once (8 per unit measured 7% slower, 16 to 64
+// the same).
 constexpr size_t kTgtBlocks = 256 * 32;
 
 // The same gradient with CF / 4 lanes per target entry, each owning four
