@@ -294,7 +294,7 @@ __global__ void flip_weights_kernel(const bf16_t* __restrict__ w, bf16_t* __rest
 // transposed [CIN][64 + 2 d] in LDS; wave t accumulates the (o-tile, i-tile)
 // pair t for all 9 taps (K = pixels).  Partial results per block are reduced
 // in a fixed order by a second kernel.
-constexpr int kWgRows = 32;  // 960 blocks on four KITTI-size images: 1.3% faster per training step than 16, 8 slower
+constexpr int kWgRows = 32;  // 960 blocks on four KITTI-size images: 1.3% faster per training step than 16; 8 and 64 slower
 
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) conv_wgrad_kernel(const bf16_t* __restrict__ x,
