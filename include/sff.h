@@ -27,6 +27,20 @@
  *    Cp = sff_desc_channels(C) = 1, 2, 4, 4 for C = 1..4: each pixel's record
  *    is padded to 32, 64 or 128 bytes so that it never straddles a 128-byte
  *    cache line.  Channels C..Cp-1 are never written nor read by the library.
+ *  - bins   uint16 level-k bin-sum planes, sff_bin_bytes(p, k) bytes per image:
+ *    the 2 x 2-bin sums the WHT descriptors are formed from.  The descriptor
+ *    block is the 4-point Hadamard transform (both axes) of a pixel's 4 x 4
+ *    grid of bin sums, so descriptor squared distances are exactly 16 times
+ *    bin-grid squared distances.  Bin (i, j) of pixel (X, Y) sums the level-k
+ *    image at X + n (2j - 3 + b), Y + n (2i - 3 + a), a, b in {0, 1}
+ *    (replicated border).  With P = 2n, Hq = (H - 1) / P + 1 and Wq =
+ *    ((W - 1) / P + 4) rounded up to a multiple of 16, an image is P * P
+ *    planes (py * P + px) of Hq x Wq entries; entry (r, q) of plane (py, px)
+ *    holds the bins at extended column q P + px and extended rows (r + m) P +
+ *    py, m = 0..3 (extended coordinate = coordinate + 3n), C uint16 each, in
+ *    the order m, channel: 8 C bytes.  The 4 x 4 grid of pixel (X, Y) is then
+ *    the 4 consecutive entries q = X / P .. + 3 of row Y / P of plane
+ *    (Y mod P, X mod P): 32 C contiguous bytes.
  *  - the four views of a pair are stored consecutively in the canonical order
  *    (I_l^0, I_l^1, I_r^0, I_r^1); `batch` pairs make n = 4 * batch images.
  *  - hyp    int16  [ndir][batch][Hk][Wk][4]     (u, v, d0, d1), full-res px
@@ -92,6 +106,10 @@ sff_status sff_lanczos_q14(int32_t n, int32_t* table);
  * `level`; 0 for level 0. */
 size_t sff_wht_workspace_bytes(const sff_params* p, int32_t nimg, int32_t level);
 
+/* Bytes of one image's bin-sum planes at `level` (layout above); 0 for bad
+ * arguments. */
+size_t sff_bin_bytes(const sff_params* p, int32_t level);
+
 /* WHT feature vectors at one pyramid level (Section 3.1, "Initialization" --
  * WHT features; "Multi-Scale Propagation" -- scale simulation).
  *   For level k >= 1 each image is first smoothed: area-based downsampling by
@@ -101,15 +119,23 @@ size_t sff_wht_workspace_bytes(const sff_params* p, int32_t nimg, int32_t level)
  *   Then, at EVERY full-resolution pixel q and channel c, the 8x8 patch sampled
  *   every n-th pixel at offsets -3..+4 (replicated border) is transformed by
  *   the unnormalised 2-D Walsh-Hadamard transform and the 16 coefficients of
- *   vertical/horizontal sequency < 4 are stored (exact in int16).
+ *   vertical/horizontal sequency < 4 are stored (exact in int16).  The
+ *   transform is taken in two stages, 2 x 2-bin sums then a 4-point Hadamard
+ *   transform per axis; the first stage's sums can be written as bin-sum
+ *   planes (layout above), from which sff_match_level_bins evaluates the
+ *   descriptor distances.
  * img:  [nimg][H][W][C] uint8, read only.
- * desc: [nimg][H][W][Cp][16] int16, channels 0..C-1 written.
+ * desc: [nimg][H][W][Cp][16] int16, channels 0..C-1 written; or NULL.
+ * bins: nimg images of sff_bin_bytes(p, level) bytes, written; or NULL.
+ *   At least one of desc and bins; both 16-byte aligned.
  * workspace: device buffer of at least sff_wht_workspace_bytes(p, nimg, level)
  *   bytes (may be NULL at level 0); contents on entry are ignored.
  * Errors: SFF_ERR_INVALID_ARG (NULL pointers, nimg < 1, level outside
- *   0..levels-1, bad params), SFF_ERR_WORKSPACE (workspace too small). */
+ *   0..levels-1, bad params), SFF_ERR_WORKSPACE (workspace too small),
+ *   SFF_ERR_UNSUPPORTED (descriptors at level 4 with C >= 3). */
 sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_t level, const uint8_t* img,
-                            int16_t* desc, void* workspace, size_t workspace_bytes, void* stream);
+                            int16_t* desc, uint16_t* bins, void* workspace, size_t workspace_bytes,
+                            void* stream);
 
 /* Device workspace (bytes) that sff_init_nn needs for `batch` pairs. */
 size_t sff_init_workspace_bytes(const sff_params* p, int32_t batch);
@@ -181,6 +207,22 @@ sff_status sff_init_nn_leaves(const sff_params* p, int32_t batch, int32_t dir, i
 sff_status sff_match_level(const sff_params* p, int32_t batch, int32_t dir, int32_t level,
                            const int16_t* desc, const uint64_t* seeds, const int16_t* hyp_coarse,
                            int16_t* hyp, uint32_t* cost, void* stream);
+
+/* The same level with the descriptor distances taken from the WHT bin-sum
+ * planes (16 x the bin-grid squared distance, exactly the descriptor squared
+ * distance, so hyp and cost equal those of sff_match_level on the level's WHT
+ * descriptors).  bins: level-k planes of the 4 views of each pair,
+ * [batch][4] images of sff_bin_bytes(p, level) bytes (sff_wht_features),
+ * 16-byte aligned.  Other arguments as for sff_match_level.  Wave-cooperative
+ * gathers from 20000 pixel updates per launch (32 pixels per wave below
+ * 50000, 64 above), one lane per pixel below; SFF_MATCH_EVAL=lane|coop|coop-32
+ * forces one (identical results).
+ * Errors: as sff_match_level; SFF_ERR_UNSUPPORTED when an image's planes
+ *   reach 2 GiB (32-bit gather offsets). */
+sff_status sff_match_level_bins(const sff_params* p, int32_t batch, int32_t dir, int32_t level,
+                                const uint16_t* bins, const uint64_t* seeds,
+                                const int16_t* hyp_coarse, int16_t* hyp, uint32_t* cost,
+                                void* stream);
 
 /* Consistency check (Section 3.1, "Consistency Check"; tau_c, Section 5).
  * For every pixel p with forward vector (u, v, d0, d1): if a forward target

@@ -85,27 +85,44 @@ def sff_wht_workspace_bytes(p, nimg: int, level: int) -> int:
     return int(lib().sff_wht_workspace_bytes(ctypes.byref(pp), nimg, level))
 
 
+def sff_bin_bytes(p, level: int) -> int:
+    """Bytes of one image's WHT bin-sum planes at ``level``."""
+    return int(lib().sff_bin_bytes(ctypes.byref(_params(p)), level))
+
+
 def sff_wht_features(p, img: torch.Tensor, level: int, desc: torch.Tensor | None = None,
-                     workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+                     workspace: torch.Tensor | None = None, stream=None, *, bins=None,
+                     want_desc: bool = True) -> torch.Tensor:
     """img uint8 [n][H][W][C] -> desc int16 [n][H][W][Cp][16] at ``level``
     (Cp = desc_channels(C); channels C..Cp-1 are left as they are, zero for a
-    descriptor tensor allocated here)."""
+    descriptor tensor allocated here).  ``bins``, if given (uint8 or int16
+    tensor of n * sff_bin_bytes bytes), also receives the bin-sum planes; with
+    want_desc=False only the planes are computed and they are returned."""
     pp = _params(p)
     nimg = img.shape[0]
     if tuple(img.shape[1:]) != (pp.H, pp.W, pp.C):
         raise ValueError("img shape does not match params")
     shape = (nimg, pp.H, pp.W, desc_channels(pp.C), 16)
-    if desc is None:
-        desc = torch.zeros(shape, dtype=torch.int16, device=img.device)
-    _check_shape(desc, shape, "desc")
+    if want_desc:
+        if desc is None:
+            desc = torch.zeros(shape, dtype=torch.int16, device=img.device)
+        _check_shape(desc, shape, "desc")
+    else:
+        desc = None
+        if bins is None:
+            bins = torch.empty(nimg * sff_bin_bytes(pp, level), dtype=torch.uint8, device=img.device)
+    if bins is not None:
+        if not bins.is_contiguous() or bins.numel() * bins.element_size() < nimg * sff_bin_bytes(pp, level):
+            raise ValueError("bins too small or not contiguous")
     need = sff_wht_workspace_bytes(pp, nimg, level)
     if workspace is None and need > 0:
         workspace = torch.empty(need, dtype=torch.uint8, device=img.device)
     ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
     _check(lib().sff_wht_features(ctypes.byref(pp), nimg, level, _ptr(img, torch.uint8, "img"),
-                                  _ptr(desc, torch.int16, "desc"), _ptr(workspace, None, "ws"),
-                                  ws_bytes, _stream(stream)), "sff_wht_features")
-    return desc
+                                  _ptr(desc, torch.int16, "desc"), _ptr(bins, None, "bins"),
+                                  _ptr(workspace, None, "ws"), ws_bytes, _stream(stream)),
+           "sff_wht_features")
+    return desc if want_desc else bins
 
 
 def _field(p, batch, ndir, level, device, hyp=None, cost=None):
@@ -172,6 +189,31 @@ def sff_match_level(p, desc: torch.Tensor, dir: int, level: int, seeds: torch.Te
                                  _ptr(hyp_coarse, torch.int16, "hyp_coarse"),
                                  _ptr(hyp, torch.int16, "hyp"), _ptr(cost, torch.int32, "cost"),
                                  _stream(stream)), "sff_match_level")
+    return hyp, cost
+
+
+def sff_match_level_bins(p, bins: torch.Tensor, dir: int, level: int, seeds: torch.Tensor,
+                         hyp: torch.Tensor | None = None, cost: torch.Tensor | None = None,
+                         hyp_coarse: torch.Tensor | None = None, stream=None):
+    """One level of propagation + random search with the WHT descriptor
+    distances taken from the bin-sum planes, in place on (hyp, cost); bins
+    holds the level's planes of the 4 views of ``seeds.numel()`` pairs."""
+    pp = _params(p)
+    batch = seeds.numel()
+    if not bins.is_contiguous() or bins.numel() * bins.element_size() < 4 * batch * sff_bin_bytes(pp, level):
+        raise ValueError("bins too small or not contiguous")
+    if hyp_coarse is not None:
+        Hc, Wc = grid_shape(pp, level + 1)
+        _check_shape(hyp_coarse, (2 if dir == DIR_BOTH else 1, batch, Hc, Wc, 4), "hyp_coarse")
+    ndir = 2 if dir == DIR_BOTH else 1
+    if hyp_coarse is None and (hyp is None or cost is None):
+        raise ValueError("without hyp_coarse the starting field (hyp, cost) is required")
+    hyp, cost = _field(pp, batch, ndir, level, bins.device, hyp, cost)
+    _check(lib().sff_match_level_bins(ctypes.byref(pp), batch, dir, level, _ptr(bins, None, "bins"),
+                                      _ptr(seeds, torch.int64, "seeds"),
+                                      _ptr(hyp_coarse, torch.int16, "hyp_coarse"),
+                                      _ptr(hyp, torch.int16, "hyp"), _ptr(cost, torch.int32, "cost"),
+                                      _stream(stream)), "sff_match_level_bins")
     return hyp, cost
 
 

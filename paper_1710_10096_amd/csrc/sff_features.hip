@@ -276,10 +276,59 @@ void launch_smooth(const sff_params& p, int nimg, int level, const uint8_t* img,
                        dim3(256), 0, st, A, S, H, W, C, g.n, g.Hk, g.Wk, T);
 }
 
+// Bin-sum planes (layout in BinGeom): one thread per extended position
+// (ex, ey), so a wave reads consecutive source pixels; its bin goes to slot i
+// of entry (ey / P - i, ex / P) of plane (ey mod P, ex mod P), i = 0..3.
+template <int C>
+__global__ void __launch_bounds__(256) bins_kernel(const uint8_t* __restrict__ S,
+                                                   uint16_t* __restrict__ bins, int H, int W, int n,
+                                                   int sh, int Hq, int Wq) {
+    const int P = 1 << sh;
+    const int ex = blockIdx.x * blockDim.x + threadIdx.x, ey = blockIdx.y, m = blockIdx.z;
+    if (ex >= P * Wq) return;
+    const int X0 = ex - 3 * n, Y0 = ey - 3 * n;
+    const int x0 = clampi(X0, 0, W - 1), x1 = clampi(X0 + n, 0, W - 1);
+    const int y0 = clampi(Y0, 0, H - 1), y1 = clampi(Y0 + n, 0, H - 1);
+    const uint8_t* src = S + (size_t)m * H * W * C;
+    const uint8_t* r0 = src + (size_t)y0 * W * C;
+    const uint8_t* r1 = src + (size_t)y1 * W * C;
+    uint16_t v[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        v[c] = (uint16_t)((int)r0[x0 * C + c] + (int)r0[x1 * C + c] + (int)r1[x0 * C + c] +
+                          (int)r1[x1 * C + c]);
+    const int plane = ((ey & (P - 1)) << sh) + (ex & (P - 1));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = (ey >> sh) - i;
+        if (r < 0 || r >= Hq) continue;
+        uint16_t* o = bins + (((((size_t)m * P * P + plane) * Hq + r) * Wq + (ex >> sh)) * 4 + i) * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) o[c] = v[c];
+    }
+}
+
+void launch_bins(const sff_params& p, int nimg, int level, const uint8_t* S, uint16_t* bins,
+                 hipStream_t st) {
+    const BinGeom g = bin_geom(p, level);
+    const dim3 grid((g.P * g.Wq + 255) / 256, g.P * (g.Hq + 3), nimg);
+    switch (p.C) {
+        case 1: hipLaunchKernelGGL(bins_kernel<1>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
+        case 2: hipLaunchKernelGGL(bins_kernel<2>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
+        case 3: hipLaunchKernelGGL(bins_kernel<3>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
+        default: hipLaunchKernelGGL(bins_kernel<4>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
+    }
+}
+
 }  // namespace
 }  // namespace sff
 
 using namespace sff;
+
+extern "C" size_t sff_bin_bytes(const sff_params* p, int32_t level) {
+    if (!params_ok(p) || level < 0 || level >= p->levels) return 0;
+    return bin_image_bytes(*p, level);
+}
 
 extern "C" sff_status sff_lanczos_q14(int32_t n, int32_t* table) {
     if (!table || n < 2 || n > kMaxN) return SFF_ERR_INVALID_ARG;
@@ -296,33 +345,36 @@ extern "C" size_t sff_wht_workspace_bytes(const sff_params* p, int32_t nimg, int
 }
 
 extern "C" sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_t level,
-                                       const uint8_t* img, int16_t* desc, void* workspace,
-                                       size_t workspace_bytes, void* stream) {
+                                       const uint8_t* img, int16_t* desc, uint16_t* bins,
+                                       void* workspace, size_t workspace_bytes, void* stream) {
     if (!params_ok(p) || nimg < 1 || nimg > 65535 || level < 0 || level >= p->levels || !img ||
-        !desc)
+        (!desc && !bins))
         return SFF_ERR_INVALID_ARG;
-    if ((reinterpret_cast<uintptr_t>(desc) & 15) != 0) return SFF_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(desc) & 15) != 0 || (reinterpret_cast<uintptr_t>(bins) & 15) != 0)
+        return SFF_ERR_INVALID_ARG;
     const WsLayout L = ws_layout(*p, nimg, level);
     if (level > 0 && (!workspace || workspace_bytes < L.total)) return SFF_ERR_WORKSPACE;
     hipStream_t st = as_stream(stream);
     const int H = p->H, W = p->W, C = p->C;
     const LevelGeom g = level_geom(*p, level);
     const size_t smem = wht_smem(g.n, C);
-    if (smem > 65536) return SFF_ERR_UNSUPPORTED;  // levels = 5 with C >= 3
+    if (desc && smem > 65536) return SFF_ERR_UNSUPPORTED;  // levels = 5 with C >= 3
     const uint8_t* src = img;
     if (level > 0) {
         uint8_t* ws = static_cast<uint8_t*>(workspace);
-        launch_smooth(*p, nimg, level, img, ws + L.a_off,
-                      ws + L.s_off, st);
+        launch_smooth(*p, nimg, level, img, ws + L.a_off, ws + L.s_off, st);
         src = ws + L.s_off;
     }
-    const dim3 grid((W + kTW - 1) / kTW, (H + wht_rows_rt(g.n) - 1) / wht_rows_rt(g.n), nimg);
-    switch (C) {
-        case 1: launch_wht<1>(g.n, grid, smem, st, src, desc, H, W); break;
-        case 2: launch_wht<2>(g.n, grid, smem, st, src, desc, H, W); break;
-        case 3: launch_wht<3>(g.n, grid, smem, st, src, desc, H, W); break;
-        default: launch_wht<4>(g.n, grid, smem, st, src, desc, H, W); break;
+    if (desc) {
+        const dim3 grid((W + kTW - 1) / kTW, (H + wht_rows_rt(g.n) - 1) / wht_rows_rt(g.n), nimg);
+        switch (C) {
+            case 1: launch_wht<1>(g.n, grid, smem, st, src, desc, H, W); break;
+            case 2: launch_wht<2>(g.n, grid, smem, st, src, desc, H, W); break;
+            case 3: launch_wht<3>(g.n, grid, smem, st, src, desc, H, W); break;
+            default: launch_wht<4>(g.n, grid, smem, st, src, desc, H, W); break;
+        }
     }
+    if (bins) launch_bins(*p, nimg, level, src, bins, st);
     return launch_status();
 }
 

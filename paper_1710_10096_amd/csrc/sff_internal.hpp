@@ -28,6 +28,39 @@ inline LevelGeom level_geom(const sff_params& p, int level) {
     return g;
 }
 
+// Bin-sum planes of level k.  The 4x4 lowest-sequency block of a WHT patch is
+// the 4-point Hadamard transform (both axes) of the patch's 4 x 4 grid of
+// 2 x 2-bin sums, so the squared distance of two descriptors is exactly 16
+// times that of their bin grids.  Bin (i, j) of the patch at (X, Y) sums the
+// four pixels at X + n (2j - 3 + b), Y + n (2i - 3 + a), a, b in {0, 1}
+// (replicated border); the bin at extended column ex = X + n (2j - 3) + 3n
+// lives in phase plane ex mod 2n at index ex / 2n, so a patch is 4 x 4
+// consecutive positions of one plane: columns X / 2n .. + 3 of plane X mod 2n,
+// rows Y / 2n .. + 3 of plane Y mod 2n.  Plane (py, px) = py * 2n + px holds
+// Hq x Wq entries; entry (r, q) holds the bins of plane rows r .. r + 3 at
+// column q (each bin stored in four entries), C uint16 channels per bin, so a
+// patch is one contiguous run of 4 entries = 32 C bytes (16-byte pieces: 2 C).
+struct BinGeom {
+    int n, sh, P, Hq, Wq;  // n = 2^k, P = 2n = 1 << sh
+};
+
+inline BinGeom bin_geom(const sff_params& p, int level) {
+    BinGeom g;
+    g.n = 1 << level;
+    g.sh = level + 1;
+    g.P = 2 * g.n;
+    g.Hq = (p.H - 1) / g.P + 1;
+    g.Wq = (((p.W - 1) / g.P + 4) + 15) & ~15;
+    return g;
+}
+
+// Bytes of one entry (4 plane rows of C channels) and of one image's planes.
+__host__ __device__ constexpr int bin_entry_bytes(int C) { return 8 * C; }
+inline size_t bin_image_bytes(const sff_params& p, int level) {
+    const BinGeom g = bin_geom(p, level);
+    return (size_t)g.P * g.P * g.Hq * g.Wq * bin_entry_bytes(p.C);
+}
+
 // Host-side parameter validation shared by every entry point.
 inline bool params_ok(const sff_params* p) {
     if (!p) return false;
@@ -73,18 +106,18 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
+// Each round's two 32 x 32 -> 64-bit products are formed as 64-bit multiplies
+// (one v_mad_u64_u32 each instead of a low and a high multiply).
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
         U4 o;
-        o.x = hi1 ^ c.y ^ k0;
-        o.y = lo1;
-        o.z = hi0 ^ c.w ^ k1;
-        o.w = lo0;
+        o.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        o.y = (uint32_t)p1;
+        o.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        o.w = (uint32_t)p0;
         c = o;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;

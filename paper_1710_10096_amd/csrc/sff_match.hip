@@ -1,6 +1,5 @@
 // Multi-scale propagation and random search at one level (SceneFlowFields,
-// Section 3.1, "Multi-Scale Propagation"), with the eq. (1) matching cost on
-// WHT descriptors.
+// Section 3.1, "Multi-Scale Propagation"), with the eq. (1) matching cost.
 //
 // Schedule: per iteration a red half-step (pixels with (i + j) even) then a
 // black one.  Pixels of one colour only read the other colour's vectors, so a
@@ -12,6 +11,19 @@
 // The hand-off from the coarser level is fused into iteration 0: a pixel whose
 // level-k vector has not been written yet reads its parent's vector from the
 // coarse field and computes its cost at this level.
+//
+// Two kinds of feature maps feed the same kernel: descriptor records (one
+// record of C x 16 int16 per pixel: the WHT descriptors, or any descriptors
+// such as learned ones; sff_match_level), and the WHT descriptors' bin-sum
+// planes (sff_match_level_bins).  The descriptor of a pixel is the 4x4
+// lowest-sequency block of the WHT of its 8x8 patch, i.e. the 4-point Hadamard
+// transform along both axes of the patch's 4 x 4 grid of 2 x 2-bin sums; that
+// transform is orthogonal up to a factor of 4 per axis, so the squared
+// distance of two descriptors is exactly 16 times the squared distance of
+// their bin grids (all integers).  The bin grids of neighbouring pixels
+// overlap, so one level's planes (BinGeom: 24 bytes per position at C = 3,
+// each bin stored for four rows) are a fifth of the descriptor records' size
+// and the gathers mostly hit the L2 instead of streaming records.
 #include <cstdlib>
 #include <cstring>
 
@@ -21,12 +33,14 @@ namespace sff {
 namespace {
 
 struct MatchArgs {
-    const int16_t* desc;        // [batch][4][H][W][Cp][16], Cp = kRecC<C>
+    const uint8_t* maps;        // [batch][4] images of descriptor records or bin planes
+    size_t img_bytes;           // bytes of one image's map
     const uint64_t* seeds;      // [batch]
     const int16_t* hyp_coarse;  // [ndir][batch][Hc][Wc][4] or null
     int16_t* hyp;               // [ndir][batch][Hk][Wk][4]
     uint32_t* cost;             // [ndir][batch][Hk][Wk]
     int H, W, n, level, Hk, Wk, Hc, Wc;
+    int sh, Hq, Wq;             // bin planes (BinGeom)
     int rs_r0, rs_samples, fmax, dmax;
     int batch, dir0, ndir;
 };
@@ -62,6 +76,39 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Raw buffer descriptor of one image's map (wave-uniform base), with the
+// image's size as its range: a load at an offset at or past `bytes` returns
+// zeros without a memory access.  Offsets are 32-bit, so a map is smaller than
+// 2 GiB.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t map_rsrc(const void* M, uint32_t bytes) {
+    const uint64_t p = reinterpret_cast<uint64_t>(M);
+    const uint64_t u = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)p) |
+                       ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(p >> 32)) << 32);
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(u), (short)0,
+                                             (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+
+// Offset of no patch: past the range of every image (images are smaller).
+constexpr int kNoTarget = 0x7FFFFFF0;
+
+// Map of view v (0..3 in the canonical order) for direction s: the forward
+// field has reference I_l^0 and targets I_l^1 (temporal), I_r^0 (stereo),
+// I_r^1 (cross); the inverse field has reference I_r^1 and targets I_r^0,
+// I_l^1, I_l^0.
+struct Views {
+    const uint8_t *R, *T, *S, *X;
+    __device__ __forceinline__ Views(const MatchArgs& a, int b, int s) {
+        const uint8_t* base = a.maps + (size_t)b * 4 * a.img_bytes;
+        R = base + (size_t)(s > 0 ? 0 : 3) * a.img_bytes;
+        T = base + (size_t)(s > 0 ? 1 : 2) * a.img_bytes;
+        S = base + (size_t)(s > 0 ? 2 : 1) * a.img_bytes;
+        X = base + (size_t)(s > 0 ? 3 : 0) * a.img_bytes;
+    }
+};
+
+// s * v for a direction s = +1 or -1.
+__device__ __forceinline__ int dirmul(int s, int v) { return s > 0 ? v : -v; }
+
 // Descriptor gathers of one wave, done cooperatively.  Lane l of the wave owns
 // one pixel (its reference descriptor and hypothesis); a descriptor is P = 2C
 // pieces of 16 bytes.  Gathering one descriptor per owner takes P wave-wide
@@ -87,18 +134,10 @@ struct Coop {
     uint4 refp[K];                          // reference piece of slot k
     uint32_t* part;                         // this wave's LDS slice [64 P]
     int lane;
+    uint32_t bytes;                         // bytes of one map
 
     __device__ __forceinline__ static int owner(int k, int lane) { return (64 * k + lane) / P; }
     __device__ __forceinline__ static int piece(int k, int lane) { return (64 * k + lane) % P; }
-
-    // Raw buffer descriptor of a map (wave-uniform base; offsets below 2^31).
-    // The base words are zero-extended: readfirstlane returns int.
-    __device__ __forceinline__ static __amdgpu_buffer_rsrc_t map_rsrc(const uint4* M) {
-        const uint64_t p = reinterpret_cast<uint64_t>(M);
-        const uint64_t u = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)p) |
-                           ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(p >> 32)) << 32);
-        return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(u), (short)0, 0x7FFFFFFF, 0x00020000);
-    }
 
     // Piece (k, lane) of the record at byte offset ob of the slot's owner.
     __device__ __forceinline__ uint4 gather(__amdgpu_buffer_rsrc_t rs, int ob, int k) const {
@@ -118,7 +157,7 @@ struct Coop {
     // descriptor of pixel tp in map M (0 for owners passing tp < 0).  Must be
     // called by all lanes of the wave.
     __device__ __forceinline__ uint32_t ssd(const uint4* M, int tp) {
-        const __amdgpu_buffer_rsrc_t rs = map_rsrc(M);
+        const __amdgpu_buffer_rsrc_t rs = map_rsrc(M, bytes);
         const int ob = max(tp, 0) * (RS * 16);
         uint4 v[K];
 #pragma unroll
@@ -138,7 +177,7 @@ struct Coop {
     // needs a slice of N * 64 K words.
     template <int N>
     __device__ __forceinline__ void ssdN(const uint4* M, const int (&tp)[N], uint32_t (&c)[N]) {
-        const __amdgpu_buffer_rsrc_t rs = map_rsrc(M);
+        const __amdgpu_buffer_rsrc_t rs = map_rsrc(M, bytes);
         int ob[N];
 #pragma unroll
         for (int m = 0; m < N; ++m) ob[m] = max(tp[m], 0) * (RS * 16);
@@ -185,13 +224,24 @@ struct LaneEval {
     static constexpr int kOwners = 64;
     static constexpr int kLdsWords = 1;
     static constexpr int kPG = 1, kRG = 1;
-    static constexpr bool kCoop = false;
-    const uint4 *T, *S, *X;
+    static constexpr bool kGroups = false;
+    const uint4 *T, *S, *X, *R;
     int H, W, s;
     Desc<C> ref;
 
+    __device__ __forceinline__ void setup(const MatchArgs& a, int b, int sd) {
+        const Views v(a, b, sd);
+        R = reinterpret_cast<const uint4*>(v.R);
+        T = reinterpret_cast<const uint4*>(v.T);
+        S = reinterpret_cast<const uint4*>(v.S);
+        X = reinterpret_cast<const uint4*>(v.X);
+        H = a.H;
+        W = a.W;
+        s = sd;
+    }
+
     template <class F>
-    __device__ __forceinline__ void init(const uint4* R, int x, int y, int, uint32_t*, F) {
+    __device__ __forceinline__ void init(int x, int y, int, uint32_t*, F) {
         ref = load_desc<C>(reinterpret_cast<const int16_t*>(R), (size_t)y * W + x);
     }
 
@@ -203,12 +253,16 @@ struct LaneEval {
                                                    uint32_t bound) {
         if (!want) return 0xFFFFFFFFu;
         const int ty = clampi(y + h.v, 0, H - 1);
-        uint32_t c = map_ssd(X, ty * W + clampi(x + h.u - s * h.d1, 0, W - 1));
+        uint32_t c = map_ssd(X, ty * W + clampi(x + h.u - dirmul(s, h.d1), 0, W - 1));
         if (c >= bound) return c;
         c += map_ssd(T, ty * W + clampi(x + h.u, 0, W - 1));
         if (c >= bound) return c;
-        return c + map_ssd(S, y * W + clampi(x - s * h.d0, 0, W - 1));
+        return c + map_ssd(S, y * W + clampi(x - dirmul(s, h.d0), 0, W - 1));
     }
+
+    template <int N>
+    __device__ __forceinline__ void cost_belowN(const bool (&)[N], const Hyp (&)[N], int, int,
+                                                uint32_t, uint32_t (&)[N]) {}
 };
 
 // PG neighbour candidates and RG random-search samples are scored together
@@ -220,13 +274,25 @@ struct CoopEval {
     static constexpr int kPG = PG, kRG = RG;
     static constexpr int kGroup = PG > RG ? PG : RG;
     static constexpr int kLdsWords = kGroup * 64 * Coop<C, O>::K;
-    static constexpr bool kCoop = true;
-    const uint4 *T, *S, *X;
+    static constexpr bool kGroups = true;
+    const uint4 *T, *S, *X, *R;
     int H, W, s;
     Coop<C, O> cp;
 
+    __device__ __forceinline__ void setup(const MatchArgs& a, int b, int sd) {
+        const Views v(a, b, sd);
+        R = reinterpret_cast<const uint4*>(v.R);
+        T = reinterpret_cast<const uint4*>(v.T);
+        S = reinterpret_cast<const uint4*>(v.S);
+        X = reinterpret_cast<const uint4*>(v.X);
+        H = a.H;
+        W = a.W;
+        s = sd;
+        cp.bytes = (uint32_t)a.img_bytes;
+    }
+
     template <class F>
-    __device__ __forceinline__ void init(const uint4* R, int, int, int lane, uint32_t* part, F pix_of) {
+    __device__ __forceinline__ void init(int, int, int lane, uint32_t* part, F pix_of) {
         cp.lane = lane;
         cp.part = part;
         cp.load_ref(R, pix_of);
@@ -235,7 +301,7 @@ struct CoopEval {
     __device__ __forceinline__ uint32_t cost_below(bool want, int x, int y, const Hyp& h,
                                                    uint32_t bound) {
         const int ty = clampi(y + h.v, 0, H - 1);
-        const int txX = clampi(x + h.u - s * h.d1, 0, W - 1);
+        const int txX = clampi(x + h.u - dirmul(s, h.d1), 0, W - 1);
         uint32_t c = cp.ssd(X, want ? ty * W + txX : -1);
         bool alive = want && c < bound;
         if (__any(alive)) {
@@ -243,7 +309,7 @@ struct CoopEval {
             c += cp.ssd(T, alive ? ty * W + txT : -1);
             alive = alive && c < bound;
             if (__any(alive)) {
-                const int txS = clampi(x - s * h.d0, 0, W - 1);
+                const int txS = clampi(x - dirmul(s, h.d0), 0, W - 1);
                 c += cp.ssd(S, alive ? y * W + txS : -1);
             }
         }
@@ -262,7 +328,7 @@ struct CoopEval {
 #pragma unroll
         for (int m = 0; m < N; ++m) {
             ty[m] = clampi(y + h[m].v, 0, H - 1);
-            tp[m] = w[m] ? ty[m] * W + clampi(x + h[m].u - s * h[m].d1, 0, W - 1) : -1;
+            tp[m] = w[m] ? ty[m] * W + clampi(x + h[m].u - dirmul(s, h[m].d1), 0, W - 1) : -1;
         }
         cp.template ssdN<N>(X, tp, c);
 #pragma unroll
@@ -280,10 +346,240 @@ struct CoopEval {
             c[m] += d[m];
             al[m] = al[m] && c[m] < bound;
             any = any || al[m];
-            tp[m] = al[m] ? y * W + clampi(x - s * h[m].d0, 0, W - 1) : -1;
+            tp[m] = al[m] ? y * W + clampi(x - dirmul(s, h[m].d0), 0, W - 1) : -1;
         }
         if (!__any(any)) return;
         cp.template ssdN<N>(S, tp, d);
+#pragma unroll
+        for (int m = 0; m < N; ++m) c[m] += d[m];
+    }
+};
+
+// a * b + c on the 24-bit multiplier (full rate; the operands are below 2^24).
+// Written out because the compiler otherwise forms a quarter-rate 64-bit
+// multiply-add for it.
+__device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t d;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
+// Byte offset of the patch of target (X, Y) (inside the image) in an image's
+// bin planes.  An image is below 2^31 bytes and a plane row at least 128, so
+// plane * Hq + row < 2^24, and so is the row stride Wq * entry bytes.
+template <int C>
+struct BinAddr {
+    int sh, Hq, RS;  // RS = Wq * entry bytes
+    __device__ __forceinline__ int operator()(int X, int Y) const {
+        const uint32_t m = (1u << sh) - 1u, x = (uint32_t)X, y = (uint32_t)Y;
+        const uint32_t plane = ((y & m) << sh) + (x & m);
+        const uint32_t row = mad24(plane, (uint32_t)Hq, y >> sh);
+        return (int)mad24(row, (uint32_t)RS, __umul24(x >> sh, (uint32_t)bin_entry_bytes(C)));
+    }
+};
+
+// Bin-plane evaluators: eq. (1) as 16 x the bin-grid squared distance of the
+// reference patch and the three target patches, with the same early-out and
+// view order as the descriptor evaluators.  A patch is P = 2C pieces of 16
+// bytes, contiguous (4 entries of 4 plane rows).
+//
+// BinLane: each lane gathers its own patches (fewest instructions and the
+// shortest chain of round trips; for launches too small to fill the chip).
+// BinCoop: the patches of a wave's owners are gathered cooperatively, as in
+// Coop, so one wave-wide load reads the whole patches of a few owners instead
+// of one piece each of 64 unrelated patches: the texture path handles about
+// one 64-byte sector per clock per CU, and with the planes resident in the L2
+// that, not the L2, bounds a full chip.  Owners without a target get an offset
+// past the map's range (the load returns zeros without a memory access).
+template <int C>
+struct BinLane {
+    static constexpr int P = 2 * C;
+    static constexpr int kOwners = 64;
+    static constexpr int kLdsWords = 1;
+    static constexpr int kPG = 1, kRG = 1;
+    static constexpr bool kGroups = false;
+    __amdgpu_buffer_rsrc_t rR, rT, rS, rX;
+    BinAddr<C> addr;
+    int H, W, s;
+    uint4 ref[P];
+
+    __device__ __forceinline__ void setup(const MatchArgs& a, int b, int sd) {
+        const Views v(a, b, sd);
+        const uint32_t bytes = (uint32_t)a.img_bytes;
+        rR = map_rsrc(v.R, bytes);
+        rT = map_rsrc(v.T, bytes);
+        rS = map_rsrc(v.S, bytes);
+        rX = map_rsrc(v.X, bytes);
+        H = a.H;
+        W = a.W;
+        s = sd;
+        addr.sh = a.sh;
+        addr.Hq = a.Hq;
+        addr.RS = a.Wq * bin_entry_bytes(C);
+    }
+
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, int off, uint4* v) const {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+            v[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16 * k, 0, 0));
+    }
+
+    template <class F>
+    __device__ __forceinline__ void init(int x, int y, int, uint32_t*, F) {
+        load(rR, addr(x, y), ref);
+    }
+
+    __device__ __forceinline__ uint32_t view_cost(__amdgpu_buffer_rsrc_t rs, int X, int Y) const {
+        uint4 v[P];
+        load(rs, addr(X, Y), v);
+        int acc = 0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) acc = piece_ssd(ref[k], v[k], acc);
+        return 16u * (uint32_t)acc;
+    }
+
+    __device__ __forceinline__ uint32_t cost_below(bool want, int x, int y, const Hyp& h,
+                                                   uint32_t bound) {
+        if (!want) return 0xFFFFFFFFu;
+        const int ty = clampi(y + h.v, 0, H - 1);
+        uint32_t c = view_cost(rX, clampi(x + h.u - dirmul(s, h.d1), 0, W - 1), ty);
+        if (c >= bound) return c;
+        c += view_cost(rT, clampi(x + h.u, 0, W - 1), ty);
+        if (c >= bound) return c;
+        return c + view_cost(rS, clampi(x - dirmul(s, h.d0), 0, W - 1), y);
+    }
+
+    template <int N>
+    __device__ __forceinline__ void cost_belowN(const bool (&)[N], const Hyp (&)[N], int, int,
+                                                uint32_t, uint32_t (&)[N]) {}
+};
+
+template <int C, int PG, int RG, int O = 64>
+struct BinCoop {
+    static_assert(O == 64 || O == 32, "owners per wave");
+    static constexpr int P = 2 * C;
+    static constexpr int K = O * P / 64;  // wave-wide loads per patch gather
+    static constexpr int kOwners = O;
+    static constexpr int kPG = PG, kRG = RG;
+    static constexpr int kGroup = PG > RG ? PG : RG;
+    static constexpr int kLdsWords = kGroup * 64 * K;
+    static constexpr bool kGroups = true;
+    __amdgpu_buffer_rsrc_t rR, rT, rS, rX;
+    BinAddr<C> addr;
+    int H, W, s;
+    uint4 refp[K];   // reference piece of slot k
+    uint32_t* part;  // this wave's LDS slice
+    int lane;
+
+    __device__ __forceinline__ void setup(const MatchArgs& a, int b, int sd) {
+        const Views v(a, b, sd);
+        const uint32_t bytes = (uint32_t)a.img_bytes;
+        rR = map_rsrc(v.R, bytes);
+        rT = map_rsrc(v.T, bytes);
+        rS = map_rsrc(v.S, bytes);
+        rX = map_rsrc(v.X, bytes);
+        H = a.H;
+        W = a.W;
+        s = sd;
+        addr.sh = a.sh;
+        addr.Hq = a.Hq;
+        addr.RS = a.Wq * bin_entry_bytes(C);
+    }
+
+    __device__ __forceinline__ static int owner(int k, int l) { return (64 * k + l) / P; }
+    __device__ __forceinline__ static int piece(int k, int l) { return (64 * k + l) % P; }
+
+    // Offset of slot (k, lane): piece of its owner's patch at ob, or past the
+    // map's range when the owner has no target (ob < 0).
+    __device__ __forceinline__ int slot_off(int ob, int k) const {
+        const int oo = __shfl(ob, owner(k, lane));
+        return oo >= 0 ? oo + piece(k, lane) * 16 : kNoTarget;
+    }
+
+    template <class F>
+    __device__ __forceinline__ void init(int x, int y, int l, uint32_t* lds, F) {
+        lane = l;
+        part = lds;
+        const int ob = addr(x, y);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            refp[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rR, slot_off(ob, k), 0, 0));
+    }
+
+    // Squared distances (x 16) of N patches per owner, all gathers in flight
+    // together; ob[m] < 0 marks no target (result 0).  Must be called by all
+    // lanes of the wave.
+    template <int N>
+    __device__ __forceinline__ void ssdN(__amdgpu_buffer_rsrc_t rs, const int (&ob)[N], uint32_t (&c)[N]) {
+        uint4 v[N][K];
+        int so[N][K];
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k) so[m][k] = slot_off(ob[m], k);
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                v[m][k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, so[m][k], 0, 0));
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k) part[64 * (m * K + k) + lane] = (uint32_t)piece_ssd(refp[k], v[m][k], 0);
+        wave_sync();
+        const int ol = lane & (O - 1);  // lanes past the owners read a valid slot
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int w = 0; w < P; ++w) t += part[64 * K * m + ol * P + w];
+            c[m] = ob[m] >= 0 ? 16u * t : 0u;
+        }
+        wave_sync();
+    }
+
+    __device__ __forceinline__ uint32_t cost_below(bool want, int x, int y, const Hyp& h,
+                                                   uint32_t bound) {
+        bool w[1] = {want};
+        Hyp hh[1] = {h};
+        uint32_t c[1];
+        cost_belowN<1>(w, hh, x, y, bound, c);
+        return c[0];
+    }
+
+    // cost_below for N candidates of each lane, their gathers issued together
+    // view by view; same results as N calls with the same bound.
+    template <int N>
+    __device__ __forceinline__ void cost_belowN(const bool (&w)[N], const Hyp (&h)[N], int x, int y,
+                                                uint32_t bound, uint32_t (&c)[N]) {
+        int ty[N], ob[N];
+        bool al[N];
+        bool any = false;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            ty[m] = clampi(y + h[m].v, 0, H - 1);
+            ob[m] = w[m] ? addr(clampi(x + h[m].u - dirmul(s, h[m].d1), 0, W - 1), ty[m]) : -1;
+        }
+        ssdN<N>(rX, ob, c);
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            al[m] = w[m] && c[m] < bound;
+            any = any || al[m];
+            ob[m] = al[m] ? addr(clampi(x + h[m].u, 0, W - 1), ty[m]) : -1;
+        }
+        if (!__any(any)) return;
+        uint32_t d[N];
+        ssdN<N>(rT, ob, d);
+        any = false;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            c[m] += d[m];
+            al[m] = al[m] && c[m] < bound;
+            any = any || al[m];
+            ob[m] = al[m] ? addr(clampi(x - dirmul(s, h[m].d0), 0, W - 1), y) : -1;
+        }
+        if (!__any(any)) return;
+        ssdN<N>(rS, ob, d);
 #pragma unroll
         for (int m = 0; m < N; ++m) c[m] += d[m];
     }
@@ -319,21 +615,13 @@ __global__ void __launch_bounds__(64) half_step_kernel(MatchArgs a, int it, int 
     const bool act = lane < O && j < a.Wk;
     const int di = z / a.batch, b = z - di * a.batch;
     const int s = (a.ndir == 2) ? (di == 0 ? 1 : -1) : a.dir0;
-    const size_t mapsz = (size_t)a.H * a.W * Coop<C, 64>::RS;  // in 16-byte pieces
-    const uint4* base = reinterpret_cast<const uint4*>(a.desc) + (size_t)b * 4 * mapsz;
     E V;
-    V.T = base + (size_t)(s > 0 ? 1 : 2) * mapsz;
-    V.S = base + (size_t)(s > 0 ? 2 : 1) * mapsz;
-    V.X = base + (size_t)(s > 0 ? 3 : 0) * mapsz;
-    V.H = a.H;
-    V.W = a.W;
-    V.s = s;
-    const uint4* R = base + (size_t)(s > 0 ? 0 : 3) * mapsz;
+    V.setup(a, b, s);
     const int n = a.n;
     const int x = n * min(j, a.Wk - 1), y = n * i;
     {
         const int j0 = step * tx * O + par, W = a.W, Wk1 = a.Wk - 1;
-        V.init(R, x, y, lane, part_lds, [=](int o) { return y * W + n * min(j0 + step * o, Wk1); });
+        V.init(x, y, lane, part_lds, [=](int o) { return y * W + n * min(j0 + step * o, Wk1); });
     }
 
     const size_t field_off = (size_t)z * a.Hk * a.Wk;
@@ -392,7 +680,7 @@ __global__ void __launch_bounds__(64) half_step_kernel(MatchArgs a, int it, int 
             }
         };
         constexpr int kPropGroup = E::kPG;
-        if constexpr (E::kCoop) {
+        if constexpr (E::kGroups) {
 #pragma unroll
             for (int q0 = 0; q0 < 4; q0 += kPropGroup) {
                 bool wg[kPropGroup];
@@ -450,7 +738,7 @@ __global__ void __launch_bounds__(64) half_step_kernel(MatchArgs a, int it, int 
                 }
                 if (!__any(any)) continue;
                 uint32_t cc[kRS];
-                if constexpr (E::kCoop) V.template cost_belowN<kRS>(wg, cg, x, y, bestc, cc);
+                if constexpr (E::kGroups) V.template cost_belowN<kRS>(wg, cg, x, y, bestc, cc);
 #pragma unroll
                 for (int m = 0; m < kRS; ++m) take(wg[m], cg[m], cc[m]);
             } else {
@@ -532,7 +820,7 @@ sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
         if (std::strcmp(e, "coop-wide-32") == 0) coop = true, wide = true, half = true;
     }
     // The cooperative gathers address a map with 32-bit offsets.
-    if ((size_t)a.H * a.W * Coop<C, 64>::RS * 16 > kMaxCoopMapBytes) coop = false;
+    if (a.img_bytes > kMaxCoopMapBytes) coop = false;
     if (!coop) return launch_level<C, LaneEval<C>>(a, iters, st);
     if (half) {
         if (wide) return launch_level<C, CoopEval<C, 4, 3, 32>>(a, iters, st);
@@ -540,6 +828,27 @@ sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
     }
     if (wide) return launch_level<C, CoopEval<C, 4, 3>>(a, iters, st);
     return launch_level<C, CoopEval<C, 2, 3>>(a, iters, st);
+}
+
+// Bin-plane evaluators by launch size, as for the descriptor evaluators
+// (measured on the KITTI-size pair: level 0, 465,750 updates per launch,
+// BinCoop<3, 2, 3> 82 us per launch against 108 us per lane; level 1 30 us
+// with 64 owners; level 2, 29,328 updates, 16.6 us with 32 owners against
+// 18.7 us with 64 and 20 us per lane).  SFF_MATCH_EVAL = "lane", "coop"
+// (64 owners) or "coop-32" forces one (all give identical results); anything
+// else: auto.
+template <int C>
+sff_status run_bin_level(const MatchArgs& a, int iters, hipStream_t st) {
+    const long updates = (long)a.ndir * a.batch * a.Hk * ((a.Wk + 1) / 2);
+    bool coop = updates >= kCoopMinUpdates, half = updates < kHalfOwnersMaxUpdates;
+    if (const char* e = std::getenv("SFF_MATCH_EVAL")) {
+        if (std::strcmp(e, "lane") == 0) coop = false;
+        if (std::strcmp(e, "coop") == 0) coop = true, half = false;
+        if (std::strcmp(e, "coop-32") == 0) coop = true, half = true;
+    }
+    if (!coop) return launch_level<C, BinLane<C>>(a, iters, st);
+    if (half) return launch_level<C, BinCoop<C, 2, 3, 32>>(a, iters, st);
+    return launch_level<C, BinCoop<C, 2, 3>>(a, iters, st);
 }
 
 }  // namespace
@@ -570,7 +879,9 @@ extern "C" sff_status sff_match_level(const sff_params* p, int32_t batch, int32_
         if (f0 < c1 && c0 < f1) return SFF_ERR_INVALID_ARG;
     }
     MatchArgs a;
-    a.desc = desc;
+    a.maps = reinterpret_cast<const uint8_t*>(desc);
+    a.img_bytes = (size_t)p->H * p->W * rec_channels(p->C) * 32;
+    a.sh = a.Hq = a.Wq = 0;
     a.seeds = seeds;
     a.hyp_coarse = hyp_coarse;
     a.hyp = hyp;
@@ -601,5 +912,66 @@ extern "C" sff_status sff_match_level(const sff_params* p, int32_t batch, int32_
         case 2: return run_level<2>(a, p->iters, st);
         case 3: return run_level<3>(a, p->iters, st);
         default: return run_level<4>(a, p->iters, st);
+    }
+}
+
+extern "C" sff_status sff_match_level_bins(const sff_params* p, int32_t batch, int32_t dir,
+                                           int32_t level, const uint16_t* bins, const uint64_t* seeds,
+                                           const int16_t* hyp_coarse, int16_t* hyp, uint32_t* cost,
+                                           void* stream) {
+    if (!params_ok(p) || batch < 1 || batch > 32767 || (dir != 1 && dir != -1 && dir != 0) ||
+        level < 0 || level >= p->levels || !bins || !seeds || !hyp || !cost)
+        return SFF_ERR_INVALID_ARG;
+    if (hyp_coarse && level >= p->levels - 1) return SFF_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(bins) & 15) != 0 || (reinterpret_cast<uintptr_t>(hyp) & 7) != 0 ||
+        (reinterpret_cast<uintptr_t>(cost) & 3) != 0 ||
+        (reinterpret_cast<uintptr_t>(hyp_coarse) & 7) != 0)
+        return SFF_ERR_INVALID_ARG;
+    const size_t img_bytes = bin_image_bytes(*p, level);
+    if (img_bytes > (size_t)kNoTarget) return SFF_ERR_UNSUPPORTED;  // 32-bit gather offsets
+    const LevelGeom g = level_geom(*p, level);
+    const BinGeom bg = bin_geom(*p, level);
+    const int ndir = dir == 0 ? 2 : 1;
+    const size_t fine_bytes = (size_t)ndir * batch * g.Hk * g.Wk * 8;
+    MatchArgs a;
+    if (hyp_coarse) {
+        const LevelGeom gc = level_geom(*p, level + 1);
+        const size_t coarse_bytes = (size_t)ndir * batch * gc.Hk * gc.Wk * 8;
+        const uintptr_t f0 = reinterpret_cast<uintptr_t>(hyp), f1 = f0 + fine_bytes;
+        const uintptr_t c0 = reinterpret_cast<uintptr_t>(hyp_coarse), c1 = c0 + coarse_bytes;
+        if (f0 < c1 && c0 < f1) return SFF_ERR_INVALID_ARG;
+        a.Hc = gc.Hk;
+        a.Wc = gc.Wk;
+    } else {
+        a.Hc = a.Wc = 0;
+    }
+    a.maps = reinterpret_cast<const uint8_t*>(bins);
+    a.img_bytes = img_bytes;
+    a.seeds = seeds;
+    a.hyp_coarse = hyp_coarse;
+    a.hyp = hyp;
+    a.cost = cost;
+    a.H = p->H;
+    a.W = p->W;
+    a.n = g.n;
+    a.level = level;
+    a.Hk = g.Hk;
+    a.Wk = g.Wk;
+    a.sh = bg.sh;
+    a.Hq = bg.Hq;
+    a.Wq = bg.Wq;
+    a.rs_r0 = p->rs_r0;
+    a.rs_samples = p->rs_samples;
+    a.fmax = p->fmax;
+    a.dmax = p->dmax;
+    a.batch = batch;
+    a.ndir = ndir;
+    a.dir0 = dir == 0 ? 1 : dir;
+    hipStream_t st = as_stream(stream);
+    switch (p->C) {
+        case 1: return run_bin_level<1>(a, p->iters, st);
+        case 2: return run_bin_level<2>(a, p->iters, st);
+        case 3: return run_bin_level<3>(a, p->iters, st);
+        default: return run_bin_level<4>(a, p->iters, st);
     }
 }

@@ -3,6 +3,10 @@ overview, up to the consistency check), as a sequence of libsff calls on one
 stream: for levels K-1 .. 0, WHT features of the four views, exact-NN
 initialisation at the coarsest level, propagation + random search with the
 hand-off from the coarser level; then the consistency check at level 0.
+The matcher takes the descriptor distances from the WHT bin-sum planes
+(``maps="bins"``, the default; descriptors are formed only at the coarsest
+level, for the initialisation) or from the descriptor records of every level
+(``maps="desc"``); both give the same fields.
 Forward and inverse fields run together (SFF_DIR_BOTH).  With ``s_c`` set,
 the region filter (Section 3.1, second consistency step) and the 3x3
 sparsification (Section 3.2) follow, giving the seeds of the interpolation.
@@ -19,13 +23,19 @@ from ._native import SffParams
 
 class PairMatcher:
     def __init__(self, params, batch: int = 1, device: str | torch.device = "cuda",
-                 s_c: int | None = None, leaves: int = 1):
+                 s_c: int | None = None, leaves: int = 1, maps: str = "bins"):
         self.p = params if isinstance(params, SffParams) else SffParams.from_dict(params)
         self.batch = int(batch)
+        if maps not in ("bins", "desc"):
+            raise ValueError("maps must be 'bins' or 'desc'")
+        self.maps = maps
         p, B = self.p, self.batch
         dev = torch.device(device)
         self.desc = torch.zeros((B, 4, p.H, p.W, api.desc_channels(p.C), 16), dtype=torch.int16,
                                 device=dev)
+        # bin-sum planes of one level at a time (the largest level's size)
+        nb = max(api.sff_bin_bytes(p, k) for k in range(p.levels))
+        self.bins = torch.empty(4 * B * nb, dtype=torch.uint8, device=dev)
         ws = max(api.sff_wht_workspace_bytes(p, 4 * B, k) for k in range(p.levels))
         ws = max(ws, api.sff_init_workspace_bytes(p, B))
         self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
@@ -57,18 +67,25 @@ class PairMatcher:
         flat_desc = self.desc.view(4 * B, p.H, p.W, self.desc.shape[4], 16)
         top = p.levels - 1
         mk("start")
+        bins = self.maps == "bins"
         for k in range(top, -1, -1):
-            api.sff_wht_features(p, flat_img, k, flat_desc, self.ws, stream)
+            if bins:
+                api.sff_wht_features(p, flat_img, k, flat_desc, self.ws, stream, bins=self.bins,
+                                     want_desc=k == top)
+            else:
+                api.sff_wht_features(p, flat_img, k, flat_desc, self.ws, stream)
             mk(f"features:L{k}")
+            coarse = None if k == top else self.hyp[k + 1]
             if k == top:
                 api.sff_init_nn(p, self.desc, api.DIR_BOTH, self.hyp[k], self.cost[k], self.ws,
                                 stream, leaves=self.leaves)
                 mk(f"init:L{k}")
-                api.sff_match_level(p, self.desc, api.DIR_BOTH, k, seeds, self.hyp[k],
-                                    self.cost[k], None, stream)
+            if bins:
+                api.sff_match_level_bins(p, self.bins, api.DIR_BOTH, k, seeds, self.hyp[k],
+                                         self.cost[k], coarse, stream)
             else:
                 api.sff_match_level(p, self.desc, api.DIR_BOTH, k, seeds, self.hyp[k],
-                                    self.cost[k], self.hyp[k + 1], stream)
+                                    self.cost[k], coarse, stream)
             mk(f"match:L{k}")
         api.sff_consistency(p, self.hyp[0][0], self.hyp[0][1], self.valid, self.err, stream)
         mk("consistency:L0")

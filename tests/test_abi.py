@@ -69,6 +69,20 @@ def test_descriptor_record_channels():
     assert [L.sff_desc_channels(c) for c in range(6)] == [0, 1, 2, 4, 4, 0]
 
 
+def test_bin_plane_sizes():
+    """Bytes of one image's bin-sum planes: P^2 planes of Hq x Wq entries of
+    8 C bytes, P = 2^(level+1), Hq = (H-1)/P + 1, Wq = (W-1)/P + 4 rounded up
+    to 16 (the layout include/sff.h documents)."""
+    L = _native.lib()
+    for H, W, C, lv in ((375, 1242, 3, 0), (375, 1242, 3, 2), (1, 1, 1, 0), (29, 71, 2, 3)):
+        p = SffParams(H=H, W=W, C=C, levels=lv + 1, iters=1, rs_r0=32, rs_samples=6, fmax=8,
+                      dmax=8, tau=1)
+        P = 2 << lv
+        Hq, Wq = (H - 1) // P + 1, -(-((W - 1) // P + 4) // 16) * 16
+        assert L.sff_bin_bytes(ctypes.byref(p), lv) == P * P * Hq * Wq * 8 * C
+        assert L.sff_bin_bytes(ctypes.byref(p), lv + 1) == 0
+
+
 def _good():
     return SffParams(H=96, W=160, C=1, levels=1, iters=4, rs_r0=32, rs_samples=6, fmax=32, dmax=32,
                      tau=1)
@@ -87,10 +101,12 @@ def test_invalid_params_rejected_without_launch(bad):
     for k, v in bad.items():
         setattr(p, k, v)
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
-    assert L.sff_wht_features(ctypes.byref(p), 1, 0, fake, fake, None, 0, None) == 1
+    assert L.sff_wht_features(ctypes.byref(p), 1, 0, fake, fake, fake, None, 0, None) == 1
     assert L.sff_init_nn(ctypes.byref(p), 1, 0, fake, fake, fake, fake, 1 << 30, None) == 1
     assert L.sff_init_workspace_bytes(ctypes.byref(p), 1) == 0
     assert L.sff_match_level(ctypes.byref(p), 1, 0, 0, fake, fake, None, fake, fake, None) == 1
+    assert L.sff_match_level_bins(ctypes.byref(p), 1, 0, 0, fake, fake, None, fake, fake, None) == 1
+    assert L.sff_bin_bytes(ctypes.byref(p), 0) == 0
     assert L.sff_consistency(ctypes.byref(p), 1, fake, fake, fake, fake, None) == 1
     assert L.sff_wht_workspace_bytes(ctypes.byref(p), 4, 0) == 0
 
@@ -102,7 +118,13 @@ def test_invalid_arguments_rejected():
     P = ctypes.byref(p)
     f = ctypes.c_void_p(0x1000)
     # null pointers
-    assert L.sff_wht_features(P, 1, 0, None, f, None, 0, None) == 1
+    assert L.sff_wht_features(P, 1, 0, None, f, None, None, 0, None) == 1
+    assert L.sff_wht_features(P, 1, 0, f, None, None, None, 0, None) == 1      # neither output
+    assert L.sff_wht_features(P, 1, 0, f, None, ctypes.c_void_p(0x1008), None, 0, None) == 1  # bins misaligned
+    assert L.sff_match_level_bins(P, 1, 0, 0, None, f, None, f, f, None) == 1
+    assert L.sff_match_level_bins(P, 1, 0, 0, ctypes.c_void_p(0x1008), f, None, f, f, None) == 1
+    assert L.sff_match_level_bins(P, 1, 0, 1, f, f, None, f, f, None) == 1  # level >= levels
+    assert L.sff_match_level_bins(P, 1, 0, 0, f, f, f, f, f, None) == 1     # hand-off at top
     assert L.sff_init_nn(P, 1, 0, f, None, f, f, 1 << 30, None) == 1
     assert L.sff_match_level(P, 1, 0, 0, f, None, None, f, f, None) == 1
     assert L.sff_consistency(P, 1, f, f, None, f, None) == 1
@@ -111,7 +133,7 @@ def test_invalid_arguments_rejected():
     assert L.sff_init_nn(P, 1, 2, f, f, f, f, 1 << 30, None) == 1
     assert L.sff_match_level(P, 1, 0, 1, f, f, None, f, f, None) == 1      # level >= levels
     assert L.sff_match_level(P, 1, 0, 0, f, f, f, f, f, None) == 1         # hand-off at top
-    assert L.sff_wht_features(P, 1, 1, f, f, None, 0, None) == 1          # level >= levels
+    assert L.sff_wht_features(P, 1, 1, f, f, None, None, 0, None) == 1    # level >= levels
     # temporal leaves: 1, 2 or 4
     need_i = L.sff_init_workspace_bytes(P, 1)
     assert L.sff_init_nn_leaves(P, 1, 0, 0, f, f, f, f, need_i, None) == 1
@@ -131,8 +153,9 @@ def test_invalid_arguments_rejected():
     need = L.sff_wht_workspace_bytes(ctypes.byref(p2), 4, 1)
     assert need > 0
     assert L.sff_wht_workspace_bytes(ctypes.byref(p2), 4, 0) == 0
-    assert L.sff_wht_features(ctypes.byref(p2), 4, 1, f, f, None, 0, None) == 4
-    assert L.sff_wht_features(ctypes.byref(p2), 4, 1, f, f, f, need - 1, None) == 4
+    assert L.sff_wht_features(ctypes.byref(p2), 4, 1, f, f, None, None, 0, None) == 4
+    assert L.sff_wht_features(ctypes.byref(p2), 4, 1, f, f, None, f, need - 1, None) == 4
+    assert L.sff_wht_features(ctypes.byref(p2), 4, 1, f, None, f, f, need - 1, None) == 4
     # region filter and sparsification
     need = L.sff_region_workspace_bytes(P, 1)
     assert need == 3 * ((96 * 160 * 4 + 255) // 256 * 256)
@@ -187,6 +210,8 @@ def test_invalid_arguments_rejected():
     base = 0x100000
     assert L.sff_match_level(ctypes.byref(p3), 1, 0, 0, f, f, ctypes.c_void_p(base + 64),
                              ctypes.c_void_p(base), f, None) == 1
+    assert L.sff_match_level_bins(ctypes.byref(p3), 1, 0, 0, f, f, ctypes.c_void_p(base + 64),
+                                  ctypes.c_void_p(base), f, None) == 1
 
 
 def test_lanczos_table_identical_to_oracle():

@@ -4,6 +4,7 @@
 Inputs are seeded synthetic scenes; expected values come only from ``oracle``.
 """
 import sys
+import zlib
 
 import numpy as np
 import pytest
@@ -60,7 +61,7 @@ FEATURE_CASES = [
 @pytest.mark.parametrize("case", FEATURE_CASES, ids=[c[0] for c in FEATURE_CASES])
 def test_wht_features_parity(sff, case):
     name, H, W, C, levels, lvls = case
-    rng = np.random.default_rng(abs(hash(name)) % 2 ** 32)
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
     imgs = rng.integers(0, 256, (4, H, W, C), dtype=np.uint8)
     p = params_dict(H, W, C, levels=levels, iters=1)
     Cp = sff.desc_channels(C)
@@ -84,6 +85,59 @@ def test_wht_features_kitti_full(sff):
         d = host(sff.sff_wht_features(p, g, lv))
         for m in range(4):
             assert np.array_equal(d[m][:, :, :p["C"]], oracle.features(imgs[m], lv)), (lv, m)
+
+
+def _bins_expected(S, level):
+    """Bin-sum planes of one smoothed image S [H][W][C] in the layout of
+    include/sff.h, from the plain definition: bin at extended position
+    (ex, ey) = (X + 3n, Y + 3n) sums S at X + {0, n}, Y + {0, n} (clamped);
+    entry (r, q) of plane (py, px) holds extended rows (r + m) P + py, m = 0..3,
+    at extended column q P + px."""
+    H, W, C = S.shape
+    n, P = 1 << level, 2 << level
+    Hq, Wq = (H - 1) // P + 1, -(-((W - 1) // P + 4) // 16) * 16
+    ey = np.arange(P * (Hq + 3)) - 3 * n
+    ex = np.arange(P * Wq) - 3 * n
+    Si = S.astype(np.int64)
+    b = np.zeros((ey.size, ex.size, C), np.int64)
+    for a in (0, n):
+        for c in (0, n):
+            b += Si[np.clip(ey + a, 0, H - 1)][:, np.clip(ex + c, 0, W - 1)]
+    out = np.zeros((P, P, Hq, Wq, 4, C), np.uint16)
+    for py in range(P):
+        for px in range(P):
+            for m in range(4):
+                out[py, px, :, :, m] = b[(np.arange(Hq) + m) * P + py][:, np.arange(Wq) * P + px]
+    return out
+
+
+BIN_CASES = [("ragged_c3", 37, 53, 3, 3), ("c1_l2", 29, 71, 1, 3), ("c2", 20, 24, 2, 2),
+             ("c4", 13, 40, 4, 2), ("one_pixel", 1, 1, 3, 2)]
+
+
+@pytest.mark.parametrize("case", BIN_CASES, ids=[c[0] for c in BIN_CASES])
+def test_wht_bins_layout(sff, case):
+    """The bin-sum planes against the layout written out from the oracle's
+    smoothed image; descriptors and planes from one call agree with the
+    descriptors alone."""
+    import torch
+    name, H, W, C, levels = case
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    imgs = rng.integers(0, 256, (4, H, W, C), dtype=np.uint8)
+    p = params_dict(H, W, C, levels=levels, iters=1)
+    for lv in range(levels):
+        _say("bins", name, "level", lv)
+        nb = sff.sff_bin_bytes(p, lv)
+        bins = torch.zeros(4 * nb, dtype=torch.uint8, device="cuda")
+        d = host(sff.sff_wht_features(p, dev(imgs), lv, bins=bins))
+        for m in range(4):
+            S = imgs[m] if lv == 0 else oracle.smooth(imgs[m], 1 << lv)
+            exp = _bins_expected(S, lv)
+            g = host(bins)[m * nb:(m + 1) * nb].view(np.uint16).reshape(exp.shape)
+            assert np.array_equal(g, exp), (name, lv, m)
+            assert np.array_equal(d[m][:, :, :C], oracle.features(imgs[m], lv)), (name, lv, m)
+        only = host(sff.sff_wht_features(p, dev(imgs), lv, want_desc=False))
+        assert np.array_equal(only, host(bins))
 
 
 # ----------------------------------------------------------------- init ----
@@ -155,14 +209,20 @@ LEVEL_CASES = [
 ]
 
 
-@pytest.mark.parametrize("evaluator", ["lane", "coop-narrow", "coop-wide", "coop-narrow-32",
-                                       "coop-wide-32"])
+MATCH_KERNELS = [("desc", "lane"), ("desc", "coop-narrow"), ("desc", "coop-wide"),
+                 ("desc", "coop-narrow-32"), ("desc", "coop-wide-32"),
+                 ("bins", "lane"), ("bins", "coop"), ("bins", "coop-32")]
+
+
+@pytest.mark.parametrize("kernel", MATCH_KERNELS, ids=[f"{a}-{b}" for a, b in MATCH_KERNELS])
 @pytest.mark.parametrize("case", LEVEL_CASES, ids=[c[0] for c in LEVEL_CASES])
-def test_match_level_parity(sff, case, evaluator, monkeypatch):
-    """Every descriptor-gather kernel (per-lane; wave-cooperative scoring 2
-    neighbours and 3 samples, or 4 and 3, at a time, with 64 or 32 pixels per
-    wave) against the oracle; SFF_MATCH_EVAL forces one of them."""
+def test_match_level_parity(sff, case, kernel, monkeypatch):
+    """Every gather kernel against the oracle: descriptor records (per-lane;
+    wave-cooperative scoring 2 neighbours and 3 samples, or 4 and 3, at a
+    time, with 64 or 32 pixels per wave) and bin-sum planes (per-lane;
+    cooperative with 64 or 32 pixels per wave); SFF_MATCH_EVAL forces one."""
     import torch
+    maps, evaluator = kernel
     monkeypatch.setenv("SFF_MATCH_EVAL", evaluator)
     name, H, W, C, levels, level, iters, rs, B = case
     fmax, dmax = 16, 12
@@ -172,16 +232,20 @@ def test_match_level_parity(sff, case, evaluator, monkeypatch):
     imgs = _imgs_stack(scenes)
     seeds = np.array([11 + 1000003 * b for b in range(B)], np.int64)
     flat = dev(imgs.reshape(4 * B, H, W, C))
-    desc_l = sff.sff_wht_features(p, flat, level).view(B, 4, H, W, sff.desc_channels(C), 16)
+    if maps == "desc":
+        desc_l = sff.sff_wht_features(p, flat, level).view(B, 4, H, W, sff.desc_channels(C), 16)
+        match = sff.sff_match_level
+    else:
+        desc_l = sff.sff_wht_features(p, flat, level, want_desc=False)
+        match = sff.sff_match_level_bins
     Dl = [_oracle_descs(imgs[b], level) for b in range(B)]
     if level < levels - 1:
         # a coarse field: oracle init at the next level (both sides get the same input)
         Dc = [_oracle_descs(imgs[b], level + 1) for b in range(B)]
         coarse = np.stack([np.stack([oracle.init_nn(Dc[b], level + 1, s, fmax, dmax)[0]
                                      for b in range(B)]) for s in (1, -1)])
-        _say("match_level", name, evaluator, "hand-off")
-        hyp, cost = sff.sff_match_level(p, desc_l, sff.DIR_BOTH, level, dev(seeds),
-                                        hyp_coarse=dev(coarse))
+        _say("match_level", name, maps, evaluator, "hand-off")
+        hyp, cost = match(p, desc_l, sff.DIR_BOTH, level, dev(seeds), hyp_coarse=dev(coarse))
         for di, s in enumerate((1, -1)):
             for b in range(B):
                 oh, oc = oracle.match_level(Dl[b], level, s, int(seeds[b]), iters, 32, rs, fmax,
@@ -193,10 +257,10 @@ def test_match_level_parity(sff, case, evaluator, monkeypatch):
                                     for b in range(B)]) for s in (1, -1)])
         startc = np.stack([np.stack([oracle.init_nn(Dl[b], level, s, fmax, dmax)[1]
                                      for b in range(B)]) for s in (1, -1)])
-        _say("match_level", name, evaluator, "from init")
+        _say("match_level", name, maps, evaluator, "from init")
         hyp = dev(start)
         cost = dev(startc.view(np.int32))
-        sff.sff_match_level(p, desc_l, sff.DIR_BOTH, level, dev(seeds), hyp, cost)
+        match(p, desc_l, sff.DIR_BOTH, level, dev(seeds), hyp, cost)
         for di, s in enumerate((1, -1)):
             for b in range(B):
                 oh, oc = oracle.match_level(Dl[b], level, s, int(seeds[b]), iters, 32, rs, fmax,
@@ -207,7 +271,7 @@ def test_match_level_parity(sff, case, evaluator, monkeypatch):
         for di, s in enumerate((1, -1)):
             h1 = dev(start[di:di + 1])
             c1 = dev(startc[di:di + 1].view(np.int32))
-            sff.sff_match_level(p, desc_l, s, level, dev(seeds), h1, c1)
+            match(p, desc_l, s, level, dev(seeds), h1, c1)
             assert np.array_equal(host(h1)[0], host(hyp)[di])
     torch.cuda.synchronize()
 
@@ -238,11 +302,11 @@ def test_consistency_parity(sff):
 
 
 # ---------------------------------------------------------- whole stage ----
-def _check_pipeline(sff, scenes, p, seeds, stream=None):
+def _check_pipeline(sff, scenes, p, seeds, stream=None, maps="bins"):
     import torch
     B = len(scenes)
     imgs = _imgs_stack(scenes)
-    m = sff.PairMatcher(p, B)
+    m = sff.PairMatcher(p, B, maps=maps)
     out = m.run(dev(imgs), dev(np.array(seeds, np.int64)), stream)
     if stream is not None:
         stream.synchronize()
@@ -274,12 +338,17 @@ def test_pipeline_ragged_batch_on_side_stream(sff):
         _check_pipeline(sff, scenes, p, [5, 6, 7], stream=st)
 
 
-@pytest.mark.parametrize("evaluator", ["auto", "lane", "coop-narrow", "coop-wide", "coop-narrow-32",
-                                       "coop-wide-32"])
-def test_pipeline_kitti_full(sff, evaluator, monkeypatch):
+PIPE_KERNELS = [("bins", "auto"), ("bins", "lane"), ("bins", "coop"), ("bins", "coop-32"),
+                ("desc", "auto"), ("desc", "lane"), ("desc", "coop-narrow"), ("desc", "coop-wide"),
+                ("desc", "coop-narrow-32"), ("desc", "coop-wide-32")]
+
+
+@pytest.mark.parametrize("kernel", PIPE_KERNELS, ids=[f"{a}-{b}" for a, b in PIPE_KERNELS])
+def test_pipeline_kitti_full(sff, kernel, monkeypatch):
+    maps, evaluator = kernel
     monkeypatch.setenv("SFF_MATCH_EVAL", evaluator)
-    _say("pipeline kitti 1242x375", evaluator)
-    _check_pipeline(sff, [make_scene(kitti_spec())], kitti_params(), [2])
+    _say("pipeline kitti 1242x375", maps, evaluator)
+    _check_pipeline(sff, [make_scene(kitti_spec())], kitti_params(), [2], maps=maps)
 
 
 def test_invalid_batch_raises(sff):
@@ -298,12 +367,16 @@ def test_pipeline_batch16_small(sff):
     scenes = [make_scene(small_spec(H, W, C, 500 + b, flow_max=8, d_range=(0, 10))) for b in range(B)]
     imgs = _imgs_stack(scenes)
     seeds = np.arange(B, dtype=np.int64) * 7919 + 3
-    _say("match_level batch 16, one thread per pixel")
+    _say("pipeline batch 16, 96x160")
     out = sff.PairMatcher(p, B).run(dev(imgs), dev(seeds))
-    hyp = host(out["hyp"])
-    for b in range(0, B, 3):
+    hyp, cost = host(out["hyp"]), host(out["cost"], u32=True)
+    valid, err = host(out["valid"]), host(out["err"], u32=True)
+    for b in range(B):
         ref = oracle.match_pair(imgs[b], p, int(seeds[b]))
         assert np.array_equal(hyp[:, b], ref["hyp"]), b
+        assert np.array_equal(cost[:, b], ref["cost"]), b
+        assert np.array_equal(valid[b], ref["valid"]), b
+        assert np.array_equal(err[b], ref["err"]), b
 
 
 def test_pipeline_kitti_batch16(sff):
