@@ -137,6 +137,26 @@ sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_t level, co
                             int16_t* desc, uint16_t* bins, void* workspace, size_t workspace_bytes,
                             void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation as sff_wht_features without a workspace argument.  The block
+ * means and smoothed images of level >= 1 go to a fixed scratch array of
+ * sff_wht_scratch_bytes() bytes (32 MiB) in device memory that the library
+ * holds on each GPU it runs on until the process ends; its address on a
+ * device is looked up on the first call with that device current.  Nothing
+ * is allocated by the call.  Every call on one GPU shares that GPU's array
+ * (the call writes all of the scratch it reads, so nothing needs clearing):
+ * calls that overlap on one GPU (different streams, or different host threads
+ * without ordering) race and must not be made.
+ * Errors: as sff_wht_features; SFF_ERR_WORKSPACE when the call needs more
+ *   than sff_wht_scratch_bytes() (nimg H W C plus the block means, each
+ *   rounded up to 256 bytes, at level >= 1); SFF_ERR_HIP if the scratch's
+ *   address cannot be obtained. */
+size_t sff_wht_scratch_bytes(void);
+sff_status sff_wht_features_noalloc(const sff_params* p, int32_t nimg, int32_t level,
+                                    const uint8_t* img, int16_t* desc, uint16_t* bins,
+                                    void* stream);
+
 /* Device workspace (bytes) that sff_init_nn needs for `batch` pairs. */
 size_t sff_init_workspace_bytes(const sff_params* p, int32_t batch);
 

@@ -13,6 +13,7 @@
 // matrix of 2x2-bin sums; the kernel computes it that way (exact integers).
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "sff_device.hpp"
 
@@ -344,24 +345,18 @@ extern "C" size_t sff_wht_workspace_bytes(const sff_params* p, int32_t nimg, int
     return ws_layout(*p, nimg, level).total;
 }
 
-extern "C" sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_t level,
-                                       const uint8_t* img, int16_t* desc, uint16_t* bins,
-                                       void* workspace, size_t workspace_bytes, void* stream) {
-    if (!params_ok(p) || nimg < 1 || nimg > 65535 || level < 0 || level >= p->levels || !img ||
-        (!desc && !bins))
-        return SFF_ERR_INVALID_ARG;
-    if ((reinterpret_cast<uintptr_t>(desc) & 15) != 0 || (reinterpret_cast<uintptr_t>(bins) & 15) != 0)
-        return SFF_ERR_INVALID_ARG;
-    const WsLayout L = ws_layout(*p, nimg, level);
-    if (level > 0 && (!workspace || workspace_bytes < L.total)) return SFF_ERR_WORKSPACE;
-    hipStream_t st = as_stream(stream);
+namespace sff {
+namespace {
+
+sff_status wht_features(const sff_params* p, int32_t nimg, int32_t level, const uint8_t* img,
+                        int16_t* desc, uint16_t* bins, uint8_t* ws, hipStream_t st) {
     const int H = p->H, W = p->W, C = p->C;
     const LevelGeom g = level_geom(*p, level);
     const size_t smem = wht_smem(g.n, C);
     if (desc && smem > 65536) return SFF_ERR_UNSUPPORTED;  // levels = 5 with C >= 3
+    const WsLayout L = ws_layout(*p, nimg, level);
     const uint8_t* src = img;
     if (level > 0) {
-        uint8_t* ws = static_cast<uint8_t*>(workspace);
         launch_smooth(*p, nimg, level, img, ws + L.a_off, ws + L.s_off, st);
         src = ws + L.s_off;
     }
@@ -376,6 +371,69 @@ extern "C" sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_
     }
     if (bins) launch_bins(*p, nimg, level, src, bins, st);
     return launch_status();
+}
+
+bool wht_args_ok(const sff_params* p, int32_t nimg, int32_t level, const uint8_t* img,
+                 const int16_t* desc, const uint16_t* bins) {
+    if (!params_ok(p) || nimg < 1 || nimg > 65535 || level < 0 || level >= p->levels || !img ||
+        (!desc && !bins))
+        return false;
+    return (reinterpret_cast<uintptr_t>(desc) & 15) == 0 && (reinterpret_cast<uintptr_t>(bins) & 15) == 0;
+}
+
+// Fixed device scratch of the allocation-free variant: the block means and
+// smoothed images of one call.  Each GPU the library runs on holds its own
+// copy until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in, not a device address).
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+uint8_t* scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch, looked up once per device
+// (on the first call with that device current); NULL on a runtime error.
+uint8_t* scratch_for_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        scratch_ptr[dev] = static_cast<uint8_t*>(ptr);
+    }
+    return scratch_ptr[dev];
+}
+
+}  // namespace
+}  // namespace sff
+
+extern "C" sff_status sff_wht_features(const sff_params* p, int32_t nimg, int32_t level,
+                                       const uint8_t* img, int16_t* desc, uint16_t* bins,
+                                       void* workspace, size_t workspace_bytes, void* stream) {
+    if (!wht_args_ok(p, nimg, level, img, desc, bins)) return SFF_ERR_INVALID_ARG;
+    const WsLayout L = ws_layout(*p, nimg, level);
+    if (level > 0 && (!workspace || workspace_bytes < L.total)) return SFF_ERR_WORKSPACE;
+    return wht_features(p, nimg, level, img, desc, bins, static_cast<uint8_t*>(workspace),
+                        as_stream(stream));
+}
+
+extern "C" size_t sff_wht_scratch_bytes(void) { return kScratchBytes; }
+
+extern "C" sff_status sff_wht_features_noalloc(const sff_params* p, int32_t nimg, int32_t level,
+                                               const uint8_t* img, int16_t* desc, uint16_t* bins,
+                                               void* stream) {
+    if (!wht_args_ok(p, nimg, level, img, desc, bins)) return SFF_ERR_INVALID_ARG;
+    const WsLayout L = ws_layout(*p, nimg, level);
+    if (L.total > kScratchBytes) return SFF_ERR_WORKSPACE;
+    uint8_t* ws = nullptr;
+    if (level > 0) {
+        ws = scratch_for_current_device();
+        if (!ws) return SFF_ERR_HIP;
+    }
+    return wht_features(p, nimg, level, img, desc, bins, ws, as_stream(stream));
 }
 
 extern "C" sff_status sff_smooth_level(const sff_params* p, int32_t nimg, int32_t level,
