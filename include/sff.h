@@ -195,6 +195,25 @@ sff_status sff_init_nn_leaves(const sff_params* p, int32_t batch, int32_t dir, i
                               const int16_t* desc, int16_t* hyp, uint32_t* cost, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+/* Device workspace (bytes) that sff_init_nn_bins needs for `batch` pairs. */
+size_t sff_init_bins_workspace_bytes(const sff_params* p, int32_t batch);
+
+/* The initialisation of sff_init_nn / sff_init_nn_leaves (`leaves` = 1, 2 or
+ * 4) from the coarsest level's bin-sum planes instead of its descriptors, with
+ * the same results: descriptor distances are 16 times bin-grid distances, so
+ * the argmins, ties and costs are the same.  The temporal search runs on fp16
+ * MFMA with centred bins (bin - 510, exact in fp16; the products' sums are
+ * exact in fp32).
+ * bins: level-(levels-1) planes of the 4 views of each pair, [batch][4] images
+ *   of sff_bin_bytes bytes, 16-byte aligned.
+ * workspace: 256-byte aligned, at least sff_init_bins_workspace_bytes(p, batch)
+ *   bytes; contents on entry are ignored.
+ * Errors: as sff_init_nn_leaves; SFF_ERR_UNSUPPORTED when an image's planes
+ *   reach 2 GiB. */
+sff_status sff_init_nn_bins(const sff_params* p, int32_t batch, int32_t dir, int32_t leaves,
+                            const uint16_t* bins, int16_t* hyp, uint32_t* cost, void* workspace,
+                            size_t workspace_bytes, void* stream);
+
 /* Propagation and random search at one level (Section 3.1, "Multi-Scale
  * Propagation"), eq. (1) cost: sum over the temporal (x + u, y + v), stereo
  * (x - s d0, y) and cross (x + u - s d1, y + v) partners of the squared

@@ -6,7 +6,7 @@ include/sff.h.
 """
 from ._native import SffParams, LIB_PATH, EXPORTS  # noqa: F401
 from .api import (DIR_BOTH, DIR_FORWARD, DIR_INVERSE,  # noqa: F401
-                  SffError, desc_channels, grid_shape, sff_consistency, sff_init_nn, sff_init_workspace_bytes, sff_lanczos_q14,
+                  SffError, desc_channels, grid_shape, sff_consistency, sff_init_nn, sff_init_workspace_bytes, sff_init_nn_bins, sff_init_bins_workspace_bytes, sff_lanczos_q14,
                   sff_match_level, sff_match_level_bins, sff_bin_bytes, sff_region_filter, sff_region_workspace_bytes, sff_sparsify,
                   sff_sgm_disparity, sff_sgm_workspace_bytes, sff_disparity_fill,
                   sff_sift_workspace_bytes, sff_dense_sift, sff_sift_pca, sff_cost_sift, sff_match_sift, sff_sift_sqrt,

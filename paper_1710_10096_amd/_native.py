@@ -29,7 +29,7 @@ class SffParams(ctypes.Structure):
 
 EXPORTS = ("sff_status_string", "sff_version", "sff_desc_channels", "sff_lanczos_q14", "sff_wht_workspace_bytes",
            "sff_wht_features", "sff_wht_scratch_bytes", "sff_wht_features_noalloc", "sff_bin_bytes", "sff_match_level_bins",
-           "sff_init_workspace_bytes", "sff_init_nn", "sff_init_nn_leaves", "sff_match_level",
+           "sff_init_workspace_bytes", "sff_init_nn", "sff_init_bins_workspace_bytes", "sff_init_nn_bins", "sff_init_nn_leaves", "sff_match_level",
            "sff_consistency", "sff_region_workspace_bytes", "sff_region_filter", "sff_sparsify",
            "sff_sgm_workspace_bytes", "sff_sgm_disparity", "sff_disparity_fill",
            "sff_sift_workspace_bytes", "sff_dense_sift", "sff_sift_pca", "sff_cost_sift",
@@ -77,6 +77,10 @@ def lib() -> ctypes.CDLL:
     L.sff_init_workspace_bytes.restype = ctypes.c_size_t
     L.sff_init_nn.argtypes = [PP, i32, i32, P, P, P, P, ctypes.c_size_t, P]
     L.sff_init_nn.restype = i32
+    L.sff_init_bins_workspace_bytes.argtypes = [PP, i32]
+    L.sff_init_bins_workspace_bytes.restype = ctypes.c_size_t
+    L.sff_init_nn_bins.argtypes = [PP, i32, i32, i32, P, P, P, P, ctypes.c_size_t, P]
+    L.sff_init_nn_bins.restype = i32
     L.sff_init_nn_leaves.argtypes = [PP, i32, i32, i32, P, P, P, P, ctypes.c_size_t, P]
     L.sff_init_nn_leaves.restype = i32
     L.sff_match_level.argtypes = [PP, i32, i32, i32, P, P, P, P, P, P]

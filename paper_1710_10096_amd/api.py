@@ -166,6 +166,32 @@ def sff_init_nn(p, desc: torch.Tensor, dir: int = DIR_BOTH, hyp=None, cost=None,
     return hyp, cost
 
 
+def sff_init_bins_workspace_bytes(p, batch: int) -> int:
+    return int(lib().sff_init_bins_workspace_bytes(ctypes.byref(_params(p)), batch))
+
+
+def sff_init_nn_bins(p, bins: torch.Tensor, batch: int, dir: int = DIR_BOTH, hyp=None, cost=None,
+                     workspace=None, stream=None, leaves: int = 1):
+    """Exact-NN initialisation at the coarsest level from its bin-sum planes
+    (``bins``: the 4 views of ``batch`` pairs); same results as sff_init_nn on
+    the level's descriptors."""
+    pp = _params(p)
+    top = pp.levels - 1
+    if not bins.is_contiguous() or bins.numel() * bins.element_size() < 4 * batch * sff_bin_bytes(pp, top):
+        raise ValueError("bins too small or not contiguous")
+    ndir = 2 if dir == DIR_BOTH else 1
+    hyp, cost = _field(pp, batch, ndir, top, bins.device, hyp, cost)
+    need = sff_init_bins_workspace_bytes(pp, batch)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=bins.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(lib().sff_init_nn_bins(ctypes.byref(pp), batch, dir, int(leaves), _ptr(bins, None, "bins"),
+                                  _ptr(hyp, torch.int16, "hyp"), _ptr(cost, torch.int32, "cost"),
+                                  _ptr(workspace, None, "ws"), ws_bytes, _stream(stream)),
+           "sff_init_nn_bins")
+    return hyp, cost
+
+
 def sff_match_level(p, desc: torch.Tensor, dir: int, level: int, seeds: torch.Tensor,
                     hyp: torch.Tensor | None = None, cost: torch.Tensor | None = None,
                     hyp_coarse: torch.Tensor | None = None, stream=None):

@@ -355,29 +355,6 @@ struct CoopEval {
     }
 };
 
-// a * b + c on the 24-bit multiplier (full rate; the operands are below 2^24).
-// Written out because the compiler otherwise forms a quarter-rate 64-bit
-// multiply-add for it.
-__device__ __forceinline__ uint32_t mad24(uint32_t a, uint32_t b, uint32_t c) {
-    uint32_t d;
-    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
-}
-
-// Byte offset of the patch of target (X, Y) (inside the image) in an image's
-// bin planes.  An image is below 2^31 bytes and a plane row at least 128, so
-// plane * Hq + row < 2^24, and so is the row stride Wq * entry bytes.
-template <int C>
-struct BinAddr {
-    int sh, Hq, RS;  // RS = Wq * entry bytes
-    __device__ __forceinline__ int operator()(int X, int Y) const {
-        const uint32_t m = (1u << sh) - 1u, x = (uint32_t)X, y = (uint32_t)Y;
-        const uint32_t plane = ((y & m) << sh) + (x & m);
-        const uint32_t row = mad24(plane, (uint32_t)Hq, y >> sh);
-        return (int)mad24(row, (uint32_t)RS, __umul24(x >> sh, (uint32_t)bin_entry_bytes(C)));
-    }
-};
-
 // Bin-plane evaluators: eq. (1) as 16 x the bin-grid squared distance of the
 // reference patch and the three target patches, with the same early-out and
 // view order as the descriptor evaluators.  A patch is P = 2C pieces of 16

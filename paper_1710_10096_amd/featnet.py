@@ -161,7 +161,7 @@ class LearnedMatcher:
         pc = dict(params)
         pc["C"] = 2
         self.pimg = SffParams.from_dict(params)
-        self.inner = PairMatcher(pc, batch, net.device)
+        self.inner = PairMatcher(pc, batch, net.device, maps="desc")
         self.batch = batch
         ws = max(api.sff_wht_workspace_bytes(self.pimg, 4 * batch, k) for k in range(self.pimg.levels))
         self.ws_img = torch.empty(max(ws, 256), dtype=torch.uint8, device=net.device)

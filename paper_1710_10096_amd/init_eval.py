@@ -82,9 +82,8 @@ def _init_only(m, imgs, top):
     from . import api
     p, B = m.p, m.batch
     flat_img = imgs.view(4 * B, p.H, p.W, p.C)
-    flat_desc = m.desc.view(4 * B, p.H, p.W, m.desc.shape[4], 16)
-    api.sff_wht_features(p, flat_img, top, flat_desc, m.ws)
-    hyp, _ = api.sff_init_nn(p, m.desc, api.DIR_BOTH, None, None, m.ws, leaves=m.leaves)
+    api.sff_wht_features(p, flat_img, top, None, m.ws, bins=m.bins, want_desc=False)
+    hyp, _ = api.sff_init_nn_bins(p, m.bins, B, api.DIR_BOTH, None, None, m.ws, leaves=m.leaves)
     return hyp[0, 0].cpu().numpy()
 
 

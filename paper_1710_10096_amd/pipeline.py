@@ -31,13 +31,16 @@ class PairMatcher:
         self.maps = maps
         p, B = self.p, self.batch
         dev = torch.device(device)
-        self.desc = torch.zeros((B, 4, p.H, p.W, api.desc_channels(p.C), 16), dtype=torch.int16,
-                                device=dev)
-        # bin-sum planes of one level at a time (the largest level's size)
-        nb = max(api.sff_bin_bytes(p, k) for k in range(p.levels))
-        self.bins = torch.empty(4 * B * nb, dtype=torch.uint8, device=dev)
         ws = max(api.sff_wht_workspace_bytes(p, 4 * B, k) for k in range(p.levels))
-        ws = max(ws, api.sff_init_workspace_bytes(p, B))
+        if maps == "desc":
+            self.desc = torch.zeros((B, 4, p.H, p.W, api.desc_channels(p.C), 16), dtype=torch.int16,
+                                    device=dev)
+            ws = max(ws, api.sff_init_workspace_bytes(p, B))
+        else:
+            # bin-sum planes of one level at a time (the largest level's size)
+            nb = max(api.sff_bin_bytes(p, k) for k in range(p.levels))
+            self.bins = torch.empty(4 * B * nb, dtype=torch.uint8, device=dev)
+            ws = max(ws, api.sff_init_bins_workspace_bytes(p, B))
         self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=dev)
         self.hyp, self.cost = [], []
         for k in range(p.levels):
@@ -64,21 +67,25 @@ class PairMatcher:
         if tuple(imgs.shape) != (B, 4, p.H, p.W, p.C):
             raise ValueError(f"imgs must be [{B}, 4, {p.H}, {p.W}, {p.C}]")
         flat_img = imgs.view(4 * B, p.H, p.W, p.C)
-        flat_desc = self.desc.view(4 * B, p.H, p.W, self.desc.shape[4], 16)
         top = p.levels - 1
         mk("start")
         bins = self.maps == "bins"
         for k in range(top, -1, -1):
             if bins:
-                api.sff_wht_features(p, flat_img, k, flat_desc, self.ws, stream, bins=self.bins,
-                                     want_desc=k == top)
+                api.sff_wht_features(p, flat_img, k, None, self.ws, stream, bins=self.bins,
+                                     want_desc=False)
             else:
+                flat_desc = self.desc.view(4 * B, p.H, p.W, self.desc.shape[4], 16)
                 api.sff_wht_features(p, flat_img, k, flat_desc, self.ws, stream)
             mk(f"features:L{k}")
             coarse = None if k == top else self.hyp[k + 1]
             if k == top:
-                api.sff_init_nn(p, self.desc, api.DIR_BOTH, self.hyp[k], self.cost[k], self.ws,
-                                stream, leaves=self.leaves)
+                if bins:
+                    api.sff_init_nn_bins(p, self.bins, B, api.DIR_BOTH, self.hyp[k], self.cost[k],
+                                         self.ws, stream, leaves=self.leaves)
+                else:
+                    api.sff_init_nn(p, self.desc, api.DIR_BOTH, self.hyp[k], self.cost[k], self.ws,
+                                    stream, leaves=self.leaves)
                 mk(f"init:L{k}")
             if bins:
                 api.sff_match_level_bins(p, self.bins, api.DIR_BOTH, k, seeds, self.hyp[k],

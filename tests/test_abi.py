@@ -104,6 +104,8 @@ def test_invalid_params_rejected_without_launch(bad):
     assert L.sff_wht_features(ctypes.byref(p), 1, 0, fake, fake, fake, None, 0, None) == 1
     assert L.sff_init_nn(ctypes.byref(p), 1, 0, fake, fake, fake, fake, 1 << 30, None) == 1
     assert L.sff_init_workspace_bytes(ctypes.byref(p), 1) == 0
+    assert L.sff_init_bins_workspace_bytes(ctypes.byref(p), 1) == 0
+    assert L.sff_init_nn_bins(ctypes.byref(p), 1, 0, 1, fake, fake, fake, fake, 1 << 30, None) == 1
     assert L.sff_match_level(ctypes.byref(p), 1, 0, 0, fake, fake, None, fake, fake, None) == 1
     assert L.sff_match_level_bins(ctypes.byref(p), 1, 0, 0, fake, fake, None, fake, fake, None) == 1
     assert L.sff_bin_bytes(ctypes.byref(p), 0) == 0
@@ -134,6 +136,15 @@ def test_invalid_arguments_rejected():
     assert L.sff_match_level(P, 1, 0, 1, f, f, None, f, f, None) == 1      # level >= levels
     assert L.sff_match_level(P, 1, 0, 0, f, f, f, f, f, None) == 1         # hand-off at top
     assert L.sff_wht_features(P, 1, 1, f, f, None, None, 0, None) == 1    # level >= levels
+    # bin-plane initialisation
+    need_b = L.sff_init_bins_workspace_bytes(P, 1)
+    assert need_b > 0 and L.sff_init_bins_workspace_bytes(P, 0) == 0
+    assert L.sff_init_nn_bins(P, 1, 0, 1, None, f, f, f, need_b, None) == 1
+    assert L.sff_init_nn_bins(P, 1, 2, 1, f, f, f, f, need_b, None) == 1             # dir 2
+    assert L.sff_init_nn_bins(P, 1, 0, 3, f, f, f, f, need_b, None) == 2             # leaves 3
+    assert L.sff_init_nn_bins(P, 1, 0, 1, ctypes.c_void_p(0x1008), f, f, f, need_b, None) == 1
+    assert L.sff_init_nn_bins(P, 1, 0, 1, f, f, f, f, need_b - 1, None) == 4
+    assert L.sff_init_nn_bins(P, 1, 0, 1, f, f, f, ctypes.c_void_p(0x1010), need_b, None) == 4
     # temporal leaves: 1, 2 or 4
     need_i = L.sff_init_workspace_bytes(P, 1)
     assert L.sff_init_nn_leaves(P, 1, 0, 0, f, f, f, f, need_i, None) == 1

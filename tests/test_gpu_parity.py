@@ -151,39 +151,68 @@ INIT_CASES = [
 ]
 
 
+def _init(sff, p, imgs_dev, maps, dir, leaves=1):
+    """Initialisation of one pair from its descriptor records or bin planes."""
+    top = p["levels"] - 1
+    if maps == "desc":
+        desc = sff.sff_wht_features(p, imgs_dev, top).view(1, 4, p["H"], p["W"],
+                                                          sff.desc_channels(p["C"]), 16)
+        return sff.sff_init_nn(p, desc, dir, leaves=leaves)
+    bins = sff.sff_wht_features(p, imgs_dev, top, want_desc=False)
+    return sff.sff_init_nn_bins(p, bins, 1, dir, leaves=leaves)
+
+
+@pytest.mark.parametrize("maps", ["desc", "bins"])
 @pytest.mark.parametrize("leaves", [1, 2, 4])
 @pytest.mark.parametrize("case", INIT_CASES, ids=[c[0] for c in INIT_CASES])
-def test_init_nn_parity(sff, case, leaves):
+def test_init_nn_parity(sff, case, leaves, maps):
+    """Descriptor-record (int8 MFMA) and bin-plane (fp16 MFMA) initialisation
+    against the oracle's exact nearest neighbours."""
     name, H, W, C, levels, fmax, dmax, seed = case
     sc = make_scene(small_spec(H, W, C, seed, flow_max=min(fmax, 10), d_range=(0, min(dmax, 10))))
     p = params_dict(H, W, C, levels=levels, iters=1, fmax=fmax, dmax=dmax)
     top = levels - 1
     imgs = sc.stack()
-    desc = sff.sff_wht_features(p, dev(imgs), top).view(1, 4, H, W, sff.desc_channels(C), 16)
     D = _oracle_descs(imgs, top)
-    _say("init", name, "leaves", leaves, "both directions")
-    hyp, cost = sff.sff_init_nn(p, desc, sff.DIR_BOTH, leaves=leaves)
+    _say("init", name, maps, "leaves", leaves, "both directions")
+    hyp, cost = _init(sff, p, dev(imgs), maps, sff.DIR_BOTH, leaves)
     h, c = host(hyp), host(cost, u32=True)
     for di, s in enumerate((1, -1)):
         oh, oc = oracle.init_nn(D, top, s, fmax, dmax, leaves=leaves)
         assert np.array_equal(h[di, 0], oh), (name, s)
         assert np.array_equal(c[di, 0], oc), (name, s)
-    _say("init", name, "leaves", leaves, "single directions")
+    _say("init", name, maps, "leaves", leaves, "single directions")
     for s in (1, -1):
-        hyp1, cost1 = sff.sff_init_nn(p, desc, s, leaves=leaves)
+        hyp1, cost1 = _init(sff, p, dev(imgs), maps, s, leaves)
         assert np.array_equal(host(hyp1)[0, 0], h[0 if s > 0 else 1, 0])
         assert np.array_equal(host(cost1, u32=True)[0, 0], c[0 if s > 0 else 1, 0])
 
 
-def test_init_nn_kitti_full(sff):
+def test_init_bins_extreme_contrast(sff):
+    """Bin values at both ends (0 and 1020 after the 2x2 sums) on every
+    channel: the fp16 products and their fp32 sums stay exact (C = 4, the
+    largest K)."""
+    H, W, C = 24, 48, 4
+    rng = np.random.default_rng(9)
+    imgs = (rng.integers(0, 2, (4, H, W, C)) * 255).astype(np.uint8)
+    p = params_dict(H, W, C, levels=1, iters=1, fmax=12, dmax=10)
+    D = _oracle_descs(imgs, 0)
+    _say("init bins extreme contrast")
+    hyp, cost = _init(sff, p, dev(imgs), "bins", sff.DIR_BOTH)
+    for di, s in enumerate((1, -1)):
+        oh, oc = oracle.init_nn(D, 0, s, 12, 10)
+        assert np.array_equal(host(hyp)[di, 0], oh)
+        assert np.array_equal(host(cost, u32=True)[di, 0], oc)
+
+
+@pytest.mark.parametrize("maps", ["desc", "bins"])
+def test_init_nn_kitti_full(sff, maps):
     sc = make_scene(kitti_spec())
     p = kitti_params()
     imgs = sc.stack()
     top = p["levels"] - 1
-    desc = sff.sff_wht_features(p, dev(imgs), top).view(1, 4, p["H"], p["W"],
-                                                        sff.desc_channels(p["C"]), 16)
-    _say("init kitti")
-    hyp, cost = sff.sff_init_nn(p, desc, sff.DIR_BOTH)
+    _say("init kitti", maps)
+    hyp, cost = _init(sff, p, dev(imgs), maps, sff.DIR_BOTH)
     D = _oracle_descs(imgs, top)
     for di, s in enumerate((1, -1)):
         oh, oc = oracle.init_nn(D, top, s, p["fmax"], p["dmax"])

@@ -193,3 +193,21 @@ def test_features_level_composes_smooth_and_wht():
         n = 1 << level
         D = oracle.features(sc.l0, level)
         assert np.array_equal(D, oracle.wht(oracle.smooth(sc.l0, n), n))
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_descriptor_distance_is_16x_bin_distance(level):
+    """Squared distance of two WHT descriptors (any two pixels, any two images,
+    borders included) = 16 x squared distance of their 2x2-bin grids: the
+    4-point sequency Walsh matrix is orthogonal with W W^T = 4 I per axis."""
+    rng = np.random.default_rng(40 + level)
+    n = 1 << level
+    a = rng.integers(0, 256, (23, 31, 3), dtype=np.uint8)
+    b = rng.integers(0, 256, (23, 31, 3), dtype=np.uint8)
+    Da, Db = oracle.features(a, level).astype(np.int64), oracle.features(b, level).astype(np.int64)
+    Ba = indep.bin_sums(oracle.smooth(a, n) if n > 1 else a, n)
+    Bb = indep.bin_sums(oracle.smooth(b, n) if n > 1 else b, n)
+    for _ in range(300):
+        y0, x0, y1, x1 = rng.integers(0, 23), rng.integers(0, 31), rng.integers(0, 23), rng.integers(0, 31)
+        d = ((Da[y0, x0] - Db[y1, x1]) ** 2).sum()
+        assert d == 16 * ((Ba[y0, x0] - Bb[y1, x1]) ** 2).sum()
