@@ -6,7 +6,7 @@ propagation + random search on every level for the forward and inverse
 fields, and the consistency check.  Prints one JSON line.
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload kitti|kitti_batch16|tiny]
-                       [--no-cpu-baseline] [--no-probes]
+                       [--no-cpu-baseline] [--no-probes] [--no-batch16]
 """
 from __future__ import annotations
 
@@ -111,15 +111,58 @@ def algorithmic_bytes(p) -> dict:
                 consistency=cons, total=feat + 2 * (it + hand + init) + cons)
 
 
+def host_cpu() -> dict:
+    """CPU model (from /proc/cpuinfo) and logical CPU counts of the host."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def _median_runs(fn, runs: int = 3):
+    t = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        fn()
+        t.append(time.perf_counter() - t0)
+    return float(np.median(t)), [round(x, 4) for x in t]
+
+
 def cpu_baseline(scenes, p, seeds) -> dict:
+    """The CPU oracle timed on the host: the whole stage on the first pair of
+    the workload with every usable core (OpenMP inside each half-step; the
+    threads honour OMP_NUM_THREADS when it is set), median of 3; and a
+    single-thread leg on the 160x96 grey pair (the full-size pair takes tens
+    of seconds on one thread), median of 3.  Both legs give identical fields
+    whatever the thread count (the red-black half-steps are race-free)."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(os.cpu_count() or 1, 16)
-    t0 = time.perf_counter()
-    oracle.match_pair(scenes[0].stack(), p, int(seeds[0]), nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": p["H"] * p["W"] / dt, "unit": "px/s", "cores": threads, "kind": "oracle",
-            "sample": f"whole stage on 1 pair of the workload ({dt:.2f} s)",
-            "cpu": platform.processor() or platform.machine()}
+    from sff_inputs import make_scene, tiny_params, tiny_spec
+    host = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or host["usable_cpus"]
+    imgs = scenes[0].stack()
+    med, runs = _median_runs(lambda: oracle.match_pair(imgs, p, int(seeds[0]), nthreads=threads))
+    tiny = make_scene(tiny_spec())
+    tp = tiny_params()
+    med1, runs1 = _median_runs(lambda: oracle.match_pair(tiny.stack(), tp, 1, nthreads=1))
+    return {"value": p["H"] * p["W"] / med, "unit": "px/s", "cores": threads, "kind": "oracle",
+            "sample": f"whole stage on pair 0 of the workload ({p['W']}x{p['H']}x{p['C']}), "
+                      f"median of 3 runs {runs} s",
+            "cpu": host["model"], "host_logical_cpus": host["logical_cpus"],
+            "host_usable_cpus": host["usable_cpus"],
+            "single_thread": {"value": tp["H"] * tp["W"] / med1, "unit": "px/s", "cores": 1,
+                              "workload": "tiny_160x96x1_K1_it4 (the 1242x375 pair is too long "
+                                          "on one thread for the bench)",
+                              "median_s": med1, "runs_s": runs1}}
 
 
 def region_stage(p, B, m, steps: int) -> dict:
@@ -350,6 +393,76 @@ def probes(reps: int = 5) -> dict:
     return res
 
 
+def half_step_bytes(p, B: int) -> list:
+    """Algorithmic bytes of the propagation / random-search launches per level
+    (both fields, B pairs): per level-iteration and grid pixel 128 C + 32, plus
+    the hand-off (20 + 128 C per grid pixel) fused into the first launch below
+    the top level."""
+    out = []
+    for k in range(p["levels"]):
+        Hk, Wk = grid(p, k)
+        n_k = 2 * B * Hk * Wk
+        b_k = p["iters"] * n_k * (128 * p["C"] + 32)
+        if k < p["levels"] - 1:
+            b_k += n_k * (20 + 128 * p["C"])
+        out.append(b_k)
+    return out
+
+
+def batch16_stage(steps: int = 5) -> dict:
+    """The 16-pair batch of KITTI-size pairs (seeds 100..115, flow <= 64 for
+    pairs 0-7 and <= 256 for 8-15) through the whole stage, features to
+    consistency, in one PairMatcher run per batch; timed with events on the
+    launching stream, mean of `steps` runs after two untimed ones."""
+    import torch
+    import paper_1710_10096_amd as sff
+    scenes, p, seeds = workload("kitti_batch16")
+    B = len(scenes)
+    imgs = torch.from_numpy(np.stack([s.stack() for s in scenes])).cuda()
+    seeds_t = torch.tensor(seeds, dtype=torch.int64, device="cuda")
+    m = sff.PairMatcher(p, B)
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        m.run(imgs, seeds_t)
+    torch.cuda.synchronize()
+    match_ms = [0.0] * p["levels"]
+    total = 0.0
+    for _ in range(steps):
+        marks = []
+
+        def mark(name):
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(st)
+            marks.append((name, e))
+
+        m.run(imgs, seeds_t, mark=mark)
+        marks[-1][1].synchronize()
+        total += marks[0][1].elapsed_time(marks[-1][1])
+        for (n0, e0), (n1, e1) in zip(marks[:-1], marks[1:]):
+            if n1.startswith("match:L"):
+                match_ms[int(n1[7:])] += e0.elapsed_time(e1)
+    ms = total / steps
+    hs = half_step_bytes(p, B)
+    hs_ms = sum(match_ms) / steps
+    del m, imgs
+    torch.cuda.empty_cache()
+    return {"pairs": B, "seeds": f"{seeds[0]}..{seeds[-1]}", "ms_per_batch": ms,
+            "px_per_s": B * p["H"] * p["W"] / (ms * 1e-3),
+            "half_step_frac": sum(hs) / (hs_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+            "hbm_frac_whole_batch": algorithmic_bytes(p)["total"] * B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)}
+
+
+# The paper's only runtime (Table 1): the whole SceneFlowFields method on a
+# KITTI scene-flow test pair, CPU (the caption marks GPU times in parentheses;
+# this one is not), model and core count unstated.  Context, not this stage's
+# target: it includes filtering, interpolation and variational refinement.
+PAPER_FIGURE = {"value": 65.0, "unit": "s per frame pair", "source": "Table 1",
+                "covers": "whole method: matching, consistency and region filtering, "
+                          "edge-aware interpolation, variational refinement",
+                "hardware": "CPU, model and core count unstated",
+                "workload": "KITTI 2015 scene flow test pairs (about 1242x375)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -359,6 +472,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true",
                     help="skip the copy / gather bandwidth probes")
+    ap.add_argument("--no-batch16", action="store_true",
+                    help="skip the 16-pair batch record")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -410,12 +525,7 @@ def main():
     hs_bytes = 0.0
     hs_ms = 0.0
     levels = {}
-    for k in range(K):
-        Hk, Wk = grid(p, k)
-        n_k = 2 * B * Hk * Wk  # grid pixels of both fields
-        b_k = p["iters"] * n_k * (128 * p["C"] + 32)
-        if k < K - 1:
-            b_k += n_k * (20 + 128 * p["C"])
+    for k, b_k in enumerate(half_step_bytes(p, B)):
         t_k = stage_ms[f"match:L{k}"]
         levels[f"L{k}"] = {"avg_launch_us": t_k * 1e3 / (2 * p["iters"]),
                            "GBps": b_k / (t_k * 1e-3) / 1e9}
@@ -427,7 +537,12 @@ def main():
     traffic = measured_traffic(KERNEL_COUNTERS, "half_step_kernel", args.workload)
     roof = {"kernel": "half_step_kernel", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": traffic, "algorithmic_bytes_per_launch": hs_bytes / launches,
+            "traffic": traffic,
+            "traffic_counts": "FETCH_SIZE + WRITE_SIZE per launch (rocprofv3, calibrated on a "
+                              "device copy): bytes crossing the L2-fabric boundary, Infinity "
+                              "Cache hits included; TCC_EA0_RDREQ_DRAM reads the same as "
+                              "TCC_EA0_RDREQ here, so the HBM share is not separable",
+            "algorithmic_bytes_per_launch": hs_bytes / launches,
             "launches_per_step": launches, "avg_launch_us": avg_us, "levels": levels}
 
     out = {
@@ -443,8 +558,11 @@ def main():
         "hbm_frac_whole_step": ab["total"] * B / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "roofline": roof,
+        "paper": PAPER_FIGURE,
     }
     out["with_upload"] = with_upload(m, imgs, seeds_t, args.steps)
+    if args.workload == "kitti" and not args.no_batch16:
+        out["batch16"] = batch16_stage()
     out["region_sparsify"] = region_stage(p, B, m, args.steps)
     out["disparity_fill"] = fill_stage(m, imgs, args.steps)
     out["sift_pca_cost"] = sift_stage(p, m, imgs, args.steps)

@@ -58,3 +58,24 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_half_step_bytes_kitti():
+    """Per-level algorithmic bytes of the propagation / random-search launches
+    (both fields): 416 B per grid pixel and iteration at C = 3, plus the
+    404-B hand-off below the top level; 3.52 GB per KITTI-size pair, 16 times
+    that for the 16-pair batch."""
+    p = kitti_params()
+    N = [465750, 621 * 188, 311 * 94]
+    b = bench.half_step_bytes(p, 1)
+    assert b[0] == 2 * N[0] * (6 * 416 + 404)
+    assert b[1] == 2 * N[1] * (6 * 416 + 404)
+    assert b[2] == 2 * N[2] * 6 * 416
+    assert abs(sum(b) / 3.524e9 - 1) < 0.001
+    assert bench.half_step_bytes(p, 16) == [16 * x for x in b]
+
+
+def test_host_cpu_record():
+    h = bench.host_cpu()
+    assert isinstance(h["model"], str) and h["model"]
+    assert h["logical_cpus"] >= h["usable_cpus"] >= 1
