@@ -18,10 +18,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-# Per-file code generation options.  The exact-NN kernel consumes every MFMA
+# Per-file code generation options.  The exact-NN kernels consume every MFMA
 # result in VALU code at once; keeping the results in VGPRs (instead of
 # accumulation registers that need a copy-out each) removes 3 moves per element.
-EXTRA = {"sff_init.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+EXTRA = {"sff_init.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         "sff_init_bins.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def sources():

@@ -807,25 +807,44 @@ sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
     return launch_level<C, CoopEval<C, 2, 3>>(a, iters, st);
 }
 
-// Bin-plane evaluators by launch size, as for the descriptor evaluators
-// (measured on the KITTI-size pair: level 0, 465,750 updates per launch,
-// BinCoop<3, 2, 3> 82 us per launch against 108 us per lane; level 1 30 us
-// with 64 owners; level 2, 29,328 updates, 16.6 us with 32 owners against
-// 18.7 us with 64 and 20 us per lane).  SFF_MATCH_EVAL = "lane", "coop"
-// (64 owners) or "coop-32" forces one (all give identical results); anything
-// else: auto.
+// Bin-plane evaluators by launch size (updates per launch), measured on the
+// KITTI-size pair with every shape giving identical fields:
+//  - level 2 (29,328 updates, under one wave per SIMD): all 4 neighbours and
+//    all 6 samples in one group each, 32 owners per wave: 0.190 ms per level
+//    against 0.221 with groups of 2 and 3 (the chain of dependent round trips
+//    and instructions of a lone wave is what these launches wait on);
+//  - level 1 (116,936 updates): 4 neighbours, 3 samples, 32 owners: 0.364 vs
+//    0.379 ms;
+//  - level 0 (465,750 updates): 2 neighbours, 3 samples, 64 owners, 82-85 us
+//    per launch, bound by the texture path (TA 68 %, TD 79 % busy; about
+//    2.5 clocks per distinct 128-byte line a wave-wide load touches); wider
+//    groups cost occupancy (1.04-1.22 ms).
+// Issuing the temporal and stereo gathers with the cross one (no early-out
+// between views) was slower at every level (level 0: 1.10-2.11 ms), and so
+// were other tile orders (row-major 1.10 ms, no XCD grouping 1.37 ms).
+// Below 20,000 updates each lane gathers its own patches.  SFF_MATCH_EVAL =
+// "lane", "coop" (2/3, 64 owners), "coop-32" (2/3, 32 owners), "coop-43-32"
+// or "coop-46-32" forces one (all give identical results); anything else:
+// auto.
+constexpr long kBinWideMaxUpdates = 262144;
 template <int C>
 sff_status run_bin_level(const MatchArgs& a, int iters, hipStream_t st) {
     const long updates = (long)a.ndir * a.batch * a.Hk * ((a.Wk + 1) / 2);
-    bool coop = updates >= kCoopMinUpdates, half = updates < kHalfOwnersMaxUpdates;
+    int pick = updates < kCoopMinUpdates ? 0 : updates < kHalfOwnersMaxUpdates ? 4 : updates < kBinWideMaxUpdates ? 3 : 1;
     if (const char* e = std::getenv("SFF_MATCH_EVAL")) {
-        if (std::strcmp(e, "lane") == 0) coop = false;
-        if (std::strcmp(e, "coop") == 0) coop = true, half = false;
-        if (std::strcmp(e, "coop-32") == 0) coop = true, half = true;
+        if (std::strcmp(e, "lane") == 0) pick = 0;
+        if (std::strcmp(e, "coop") == 0) pick = 1;
+        if (std::strcmp(e, "coop-32") == 0) pick = 2;
+        if (std::strcmp(e, "coop-43-32") == 0) pick = 3;
+        if (std::strcmp(e, "coop-46-32") == 0) pick = 4;
     }
-    if (!coop) return launch_level<C, BinLane<C>>(a, iters, st);
-    if (half) return launch_level<C, BinCoop<C, 2, 3, 32>>(a, iters, st);
-    return launch_level<C, BinCoop<C, 2, 3>>(a, iters, st);
+    switch (pick) {
+        case 0: return launch_level<C, BinLane<C>>(a, iters, st);
+        case 1: return launch_level<C, BinCoop<C, 2, 3>>(a, iters, st);
+        case 2: return launch_level<C, BinCoop<C, 2, 3, 32>>(a, iters, st);
+        case 3: return launch_level<C, BinCoop<C, 4, 3, 32>>(a, iters, st);
+        default: return launch_level<C, BinCoop<C, 4, 6, 32>>(a, iters, st);
+    }
 }
 
 }  // namespace

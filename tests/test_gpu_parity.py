@@ -240,7 +240,8 @@ LEVEL_CASES = [
 
 MATCH_KERNELS = [("desc", "lane"), ("desc", "coop-narrow"), ("desc", "coop-wide"),
                  ("desc", "coop-narrow-32"), ("desc", "coop-wide-32"),
-                 ("bins", "lane"), ("bins", "coop"), ("bins", "coop-32")]
+                 ("bins", "lane"), ("bins", "coop"), ("bins", "coop-32"), ("bins", "coop-43-32"),
+                 ("bins", "coop-46-32")]
 
 
 @pytest.mark.parametrize("kernel", MATCH_KERNELS, ids=[f"{a}-{b}" for a, b in MATCH_KERNELS])
@@ -368,6 +369,7 @@ def test_pipeline_ragged_batch_on_side_stream(sff):
 
 
 PIPE_KERNELS = [("bins", "auto"), ("bins", "lane"), ("bins", "coop"), ("bins", "coop-32"),
+                ("bins", "coop-43-32"), ("bins", "coop-46-32"),
                 ("desc", "auto"), ("desc", "lane"), ("desc", "coop-narrow"), ("desc", "coop-wide"),
                 ("desc", "coop-narrow-32"), ("desc", "coop-wide-32")]
 
