@@ -12,11 +12,9 @@
 // 2 g_p delta to the reference entry and subtracts it from the target entry.
 //   * reference map: a gather over the preimage {(p, w) : clamp(p + w) = q};
 //   * target maps: pixels are grouped by their (clamped) target centre with a
-//     stable radix sort, then every target entry gathers over the centres
-//     whose window covers it.
+//     stable radix sort (hand-written, 8-bit digits), then every target entry
+//     gathers over the centres whose window covers it.
 // Both are deterministic (no floating-point atomics).
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -183,7 +181,17 @@ __device__ __forceinline__ void preimage(int q, int w, int n, int& lo, int& hi) 
     }
 }
 
-// Reference-map gradient: one thread per entry q of R.
+// The gradient entries gather their terms in row_split(CF) parts of
+// consecutive window rows, summed alone and then added in part order: eight
+// single rows up to 32 channels, four pairs of rows at 64 (the CF / 4 lanes of
+// every part of an entry share one wave).
+constexpr int row_split(int cf) { return cf <= 32 ? 8 : 4; }
+constexpr int kWinN = kWin1 - kWin0 + 1;  // 8 window rows and columns
+
+// Reference-map gradient, one thread per entry q of R (testing and timing).
+// The terms of q are the (p, w) with clamp(p + w) = q, taken by window row wy,
+// preimage row py, window column wx, preimage column px and correspondence;
+// each part of the window rows is summed alone, then the parts in order.
 template <int CF>
 __global__ void __launch_bounds__(256) grad_ref_kernel(CostArgs a) {
     const int qx = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -197,116 +205,214 @@ __global__ void __launch_bounds__(256) grad_ref_kernel(CostArgs a) {
     const float* M[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) M[k] = base + (size_t)view(a.s, k + 1) * HW * CF;
-    float fq[CF], acc[CF];
+    float fq[CF], acc[CF], sum[CF];
     load_vec<CF>(base + ((size_t)mR * HW + (size_t)qy * W + qx) * CF, fq);
+    constexpr int kSplit = row_split(CF), kPartRows = kWinN / kSplit;
+    for (int part = 0; part < kSplit; ++part) {
 #pragma unroll
-    for (int c = 0; c < CF; ++c) acc[c] = 0.f;
-    for (int wy = kWin0; wy <= kWin1; ++wy) {
-        int ylo, yhi;
-        preimage(qy, wy, H, ylo, yhi);
-        for (int py = ylo; py <= yhi; ++py)
-            for (int wx = kWin0; wx <= kWin1; ++wx) {
-                int xlo, xhi;
-                preimage(qx, wx, W, xlo, xhi);
-                for (int px = xlo; px <= xhi; ++px) {
-                    const size_t pix = (size_t)b * HW + (size_t)py * W + px;
-                    const float g2 = 2.f * a.gcost[pix];
-                    const Targets t = targets(a.hyp, pix, py, px, a.s, H, W);
+        for (int c = 0; c < CF; ++c) acc[c] = 0.f;
+        for (int wy = kWin0 + part * kPartRows; wy < kWin0 + (part + 1) * kPartRows; ++wy) {
+            int ylo, yhi;
+            preimage(qy, wy, H, ylo, yhi);
+            for (int py = ylo; py <= yhi; ++py)
+                for (int wx = kWin0; wx <= kWin1; ++wx) {
+                    int xlo, xhi;
+                    preimage(qx, wx, W, xlo, xhi);
+                    for (int px = xlo; px <= xhi; ++px) {
+                        const size_t pix = (size_t)b * HW + (size_t)py * W + px;
+                        const float g2 = 2.f * a.gcost[pix];
+                        const Targets t = targets(a.hyp, pix, py, px, a.s, H, W);
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        float tg[CF];
-                        load_vec<CF>(M[k] + ((size_t)clampi(t.y[k] + wy, 0, H - 1) * W +
-                                             clampi(t.x[k] + wx, 0, W - 1)) * CF, tg);
+                        for (int k = 0; k < 3; ++k) {
+                            float tg[CF];
+                            load_vec<CF>(M[k] + ((size_t)clampi(t.y[k] + wy, 0, H - 1) * W +
+                                                 clampi(t.x[k] + wx, 0, W - 1)) * CF, tg);
 #pragma unroll
-                        for (int c = 0; c < CF; ++c) acc[c] = fmaf(g2, fq[c] - tg[c], acc[c]);
+                            for (int c = 0; c < CF; ++c) acc[c] = fmaf(g2, fq[c] - tg[c], acc[c]);
+                        }
                     }
                 }
-            }
+        }
+#pragma unroll
+        for (int c = 0; c < CF; ++c) sum[c] = part ? sum[c] + acc[c] : acc[c];
     }
     float4* o = reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mR * HW +
                                                    (size_t)qy * W + qx) * CF);
 #pragma unroll
-    for (int k = 0; k < CF / 4; ++k) o[k] = make_float4(acc[4 * k], acc[4 * k + 1], acc[4 * k + 2], acc[4 * k + 3]);
+    for (int k = 0; k < CF / 4; ++k) o[k] = make_float4(sum[4 * k], sum[4 * k + 1], sum[4 * k + 2], sum[4 * k + 3]);
 }
 
-// The same gradient with CF / 4 lanes per entry, four channels each (see
-// grad_target_coop_kernel); every channel adds the same terms in the same
-// order as grad_ref_kernel, so the results are identical.
-template <int CF>
-__global__ void __launch_bounds__(256) grad_ref_coop_kernel(CostArgs a) {
-    constexpr int L = CF / 4, QPB = 256 / L;
-    const int sub = threadIdx.x % L;
-    const int H = a.H, W = a.W, b = blockIdx.y;
+// Grouping of the pixels by target centre, all three correspondences in one
+// list: element k * n + i (pixel i of the batch, n pixels) has the key
+// k * n + (centre cell of correspondence k) and the value i.  After a stable
+// sort by key, the pixels of each centre cell are in ascending pixel order.
+__global__ void target_keys_kernel(const int16_t* __restrict__ hyp, uint32_t* __restrict__ keys,
+                                   uint32_t* __restrict__ vals, int H, int W, int s, uint32_t n) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= 3 * (size_t)n) return;
+    const uint32_t k = (uint32_t)(e / n), i = (uint32_t)(e - (size_t)k * n);
     const size_t HW = (size_t)H * W;
-    const size_t q = (size_t)xcd_tile(blockIdx.x, gridDim.x) * QPB + threadIdx.x / L;  // a band of rows per XCD
-    if (q >= HW) return;  // all L lanes of the entry together
-    const int qy = (int)(q / W), qx = (int)(q - (size_t)qy * W);
-    const float* base = a.feat + (size_t)b * 4 * HW * CF;
-    const int mR = view(a.s, 0);
-    const float4* M[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) M[k] = reinterpret_cast<const float4*>(base + (size_t)view(a.s, k + 1) * HW * CF) + sub;
-    const float4 fq = reinterpret_cast<const float4*>(base + ((size_t)mR * HW + q) * CF)[sub];
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int wy = kWin0; wy <= kWin1; ++wy) {
-        int ylo, yhi;
-        preimage(qy, wy, H, ylo, yhi);
-        for (int py = ylo; py <= yhi; ++py)
-            for (int wx = kWin0; wx <= kWin1; ++wx) {
-                int xlo, xhi;
-                preimage(qx, wx, W, xlo, xhi);
-                for (int px = xlo; px <= xhi; ++px) {
-                    const size_t pix = (size_t)b * HW + (size_t)py * W + px;
-                    const float g2 = 2.f * a.gcost[pix];
-                    const Targets t = targets(a.hyp, pix, py, px, a.s, H, W);
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const float4 tg = M[k][((size_t)clampi(t.y[k] + wy, 0, H - 1) * W +
-                                                clampi(t.x[k] + wx, 0, W - 1)) * L];
-                        acc.x = fmaf(g2, fq.x - tg.x, acc.x);
-                        acc.y = fmaf(g2, fq.y - tg.y, acc.y);
-                        acc.z = fmaf(g2, fq.z - tg.z, acc.z);
-                        acc.w = fmaf(g2, fq.w - tg.w, acc.w);
-                    }
-                }
-            }
-    }
-    reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mR * HW + q) * CF)[sub] = acc;
-}
-
-// Keys for grouping pixels by the target centre of correspondence k.
-__global__ void target_keys_kernel(const int16_t* __restrict__ hyp, uint32_t* keys, uint32_t* vals,
-                                   int H, int W, int s, int k, int batch) {
-    const size_t HW = (size_t)H * W;
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= HW * batch) return;
     const int b = (int)(i / HW);
     const int pix = (int)(i - (size_t)b * HW);
     const int y = pix / W, x = pix - y * W;
     const Targets t = targets(hyp, i, y, x, s, H, W);
-    keys[i] = (uint32_t)((size_t)b * HW + (size_t)t.y[k] * W + t.x[k]);
-    vals[i] = (uint32_t)i;
+    keys[e] = k * n + (uint32_t)((size_t)b * HW + (size_t)t.y[k] * W + t.x[k]);
+    vals[e] = i;
 }
 
-// start[c] = first position of sorted key >= c, for every cell c in [0, n].
-__global__ void cell_starts_kernel(const uint32_t* __restrict__ keys, uint32_t* start, size_t n) {
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i > n) return;
-    const int64_t k = i < n ? (int64_t)keys[i] : (int64_t)n;
-    const int64_t kp = i == 0 ? -1 : (int64_t)keys[i - 1];
-    for (int64_t c = kp + 1; c <= k; ++c) start[c] = (uint32_t)i;
+// Least-significant-digit radix sort of (key, value) pairs, 8-bit digits, one
+// pass = histogram per block, exclusive scan over (digit, block), stable
+// scatter.  Blocks of 256 threads take 16 rounds of 256 consecutive elements.
+constexpr int kSortTile = 4096;
+
+__global__ void __launch_bounds__(256) sort_hist_kernel(const uint32_t* __restrict__ keys, size_t N,
+                                                        int sh, uint32_t* __restrict__ hist,
+                                                        uint32_t nblk) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * kSortTile;
+    for (int j = 0; j < kSortTile / 256; ++j) {
+        const size_t i = base + (size_t)j * 256 + threadIdx.x;
+        if (i < N) atomicAdd(&h[(keys[i] >> sh) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// The target gradients gather the window rows in row_split(CF) parts of
-// consecutive rows, summed in part order: eight single rows up to 32 channels,
-// four pairs of rows at 64 (the CF / 4 lanes of every part of an entry share
-// one wave).
-constexpr int row_split(int cf) { return cf <= 32 ? 8 : 4; }
+// Exclusive prefix sum of v over the 1024 threads of the block; *total gets
+// the sum.
+__device__ uint32_t block_scan_1024(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t wsum[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(x, off);
+        if (lane >= off) x += t;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t y = lane < 16 ? wsum[lane] : 0u;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const uint32_t t = __shfl_up(y, off);
+            if (lane >= off) y += t;
+        }
+        if (lane < 16) wsum[lane] = y;  // inclusive
+    }
+    __syncthreads();
+    const uint32_t before = w ? wsum[w - 1] : 0u;
+    *total = wsum[15];
+    __syncthreads();  // wsum is reused by the next call
+    return before + x - v;
+}
 
-// Gradient of target map k: one thread per entry q of that map; gathers over
-// the centres t with clamp(t + w) = q and the pixels grouped at each centre.
+// Exclusive scan of h[0 .. total) in two steps: each block of 1024 threads
+// scans its chunk of 1024 entries in place and writes the chunk's sum; one
+// block then scans the chunk sums (sort_scan_sums_kernel).  A scanned entry
+// is h[i] + sums[i / 1024].
+__global__ void __launch_bounds__(1024) sort_scan_chunks_kernel(uint32_t* __restrict__ h, size_t total,
+                                                                uint32_t* __restrict__ sums) {
+    const size_t i = (size_t)blockIdx.x * 1024 + threadIdx.x;
+    const uint32_t v = i < total ? h[i] : 0u;
+    uint32_t sum;
+    const uint32_t ex = block_scan_1024(v, &sum);
+    if (i < total) h[i] = ex;
+    if (threadIdx.x == 0) sums[blockIdx.x] = sum;
+}
+
+__global__ void __launch_bounds__(1024) sort_scan_sums_kernel(uint32_t* __restrict__ sums, size_t nchunks) {
+    uint32_t run = 0;
+    for (size_t c = 0; c < nchunks; c += 1024) {
+        const size_t i = c + threadIdx.x;
+        const uint32_t v = i < nchunks ? sums[i] : 0u;
+        uint32_t sum;
+        const uint32_t ex = block_scan_1024(v, &sum);
+        if (i < nchunks) sums[i] = run + ex;
+        run += sum;
+    }
+}
+
+// Stable scatter of one pass: element order is (round, wave, lane), the input
+// order; the rank inside a wave comes from the lanes with the same digit.
+__global__ void __launch_bounds__(256) sort_scatter_kernel(const uint32_t* __restrict__ kin,
+                                                           const uint32_t* __restrict__ vin,
+                                                           uint32_t* __restrict__ kout,
+                                                           uint32_t* __restrict__ vout, size_t N,
+                                                           int sh, const uint32_t* __restrict__ scan,
+                                                           const uint32_t* __restrict__ sums,
+                                                           uint32_t nblk) {
+    __shared__ uint32_t off[256];
+    __shared__ uint32_t wc[4][256];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const size_t hi = (size_t)t * nblk + blockIdx.x;
+    off[t] = scan[hi] + sums[hi / 1024];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wc[q][t] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * kSortTile;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int j = 0; j < kSortTile / 256; ++j) {
+        const size_t i = base + (size_t)j * 256 + t;
+        const bool ok = i < N;
+        uint32_t key = 0, val = 0, d = 0;
+        if (ok) {
+            key = kin[i];
+            val = vin[i];
+            d = (key >> sh) & 255u;
+        }
+        uint64_t m = __ballot(ok);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1u;
+            const uint64_t bb = __ballot(on);
+            m &= on ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(m & below);
+        const uint32_t cnt = (uint32_t)__popcll(m);
+        if (ok && rank == cnt - 1) wc[w][d] = cnt;  // the group's last lane
+        __syncthreads();
+        if (ok) {
+            uint32_t pos = off[d] + rank;
+            for (int q = 0; q < w; ++q) pos += wc[q][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        off[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wc[q][t] = 0;
+        __syncthreads();
+    }
+}
+
+// start[c] = first position of a sorted key >= c, for every cell c in [0, N]
+// (binary search; any run of empty cells costs nothing extra).
+__global__ void cell_starts_kernel(const uint32_t* __restrict__ keys, uint32_t* __restrict__ start,
+                                   size_t N) {
+    const size_t c = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (c > N) return;
+    size_t lo = 0, hi = N;
+    while (lo < hi) {
+        const size_t mid = lo + (hi - lo) / 2;
+        if ((size_t)keys[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    start[c] = (uint32_t)lo;
+}
+
+// Gradient of target map k, one thread per entry q of that map (testing and
+// timing).  The terms of q are the (pixel, w) with clamp(centre + w) = q, in
+// the canonical order: window row wy ascending, cell row ty of its preimage
+// ascending, window column wx descending (cells by ascending x), cell column
+// tx of its preimage ascending, the pixels grouped at the cell in sorted
+// order.  Term i goes to accumulator i mod row_split(CF); the gradient is the
+// sum of the accumulators in order.  (Dealing the terms round-robin keeps the
+// tiled kernel's lanes busy however unevenly the pixels crowd the cells.)
 template <int CF>
-__global__ void __launch_bounds__(256) grad_target_kernel(CostArgs a, int k,
+__global__ void __launch_bounds__(256) grad_target_kernel(CostArgs a, int k, size_t n,
                                                           const uint32_t* __restrict__ start,
                                                           const uint32_t* __restrict__ order) {
     const int qx = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -318,132 +424,380 @@ __global__ void __launch_bounds__(256) grad_target_kernel(CostArgs a, int k,
     const float* base = a.feat + (size_t)b * 4 * HW * CF;
     const float* R = base + (size_t)view(a.s, 0) * HW * CF;
     const int mk = view(a.s, k + 1);
-    float fq[CF], acc[CF];
+    constexpr int S = row_split(CF);
+    float fq[CF], acc[S][CF];
     load_vec<CF>(base + ((size_t)mk * HW + (size_t)qy * W + qx) * CF, fq);
-    float4* o = reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mk * HW +
-                                                   (size_t)qy * W + qx) * CF);
-    // the window rows in kSplit parts of consecutive rows; the gradient is
-    // ((part 0 + part 1) + part 2) + ...
-    constexpr int kSplit = row_split(CF), kPartRows = (kWin1 - kWin0 + 1) / kSplit;
-    static_assert(kPartRows * kSplit == kWin1 - kWin0 + 1, "rows split evenly");
-    for (int part = 0; part < kSplit; ++part) {
 #pragma unroll
-        for (int c = 0; c < CF; ++c) acc[c] = 0.f;
-        for (int wy = kWin0 + part * kPartRows; wy < kWin0 + (part + 1) * kPartRows; ++wy) {
-            int ylo, yhi;
-            preimage(qy, wy, H, ylo, yhi);
-            for (int ty = ylo; ty <= yhi; ++ty)
-                for (int wx = kWin1; wx >= kWin0; --wx) {  // target cells in ascending x
-                    int xlo, xhi;
-                    preimage(qx, wx, W, xlo, xhi);
-                    for (int tx = xlo; tx <= xhi; ++tx) {
-                        const size_t cell = (size_t)b * HW + (size_t)ty * W + tx;
-                        const uint32_t e0 = start[cell], e1 = start[cell + 1];
-                        for (uint32_t e = e0; e < e1; ++e) {
-                            const uint32_t pix = order[e];
-                            const int pl = (int)(pix - (size_t)b * HW);
-                            const int py = pl / W, px = pl - py * W;
-                            const float g2 = 2.f * a.gcost[pix];
-                            float r[CF];
-                            load_vec<CF>(R + ((size_t)clampi(py + wy, 0, H - 1) * W +
-                                              clampi(px + wx, 0, W - 1)) * CF, r);
+    for (int t = 0; t < S; ++t)
 #pragma unroll
-                            for (int c = 0; c < CF; ++c) acc[c] = fmaf(-g2, r[c] - fq[c], acc[c]);
-                        }
+        for (int c = 0; c < CF; ++c) acc[t][c] = 0.f;
+    uint32_t i = 0;
+    for (int wy = kWin0; wy <= kWin1; ++wy) {
+        int ylo, yhi;
+        preimage(qy, wy, H, ylo, yhi);
+        for (int ty = ylo; ty <= yhi; ++ty)
+            for (int wx = kWin1; wx >= kWin0; --wx) {
+                int xlo, xhi;
+                preimage(qx, wx, W, xlo, xhi);
+                for (int tx = xlo; tx <= xhi; ++tx) {
+                    const size_t cell = (size_t)k * n + (size_t)b * HW + (size_t)ty * W + tx;
+                    const uint32_t e0 = start[cell], e1 = start[cell + 1];
+                    for (uint32_t e = e0; e < e1; ++e, ++i) {
+                        const uint32_t pix = order[e];
+                        const int pl = (int)(pix - (size_t)b * HW);
+                        const int py = pl / W, px = pl - py * W;
+                        const float g2 = 2.f * a.gcost[pix];
+                        float r[CF];
+                        load_vec<CF>(R + ((size_t)clampi(py + wy, 0, H - 1) * W +
+                                          clampi(px + wx, 0, W - 1)) * CF, r);
+                        float* ac = acc[i % S];
+#pragma unroll
+                        for (int c = 0; c < CF; ++c) ac[c] = fmaf(-g2, r[c] - fq[c], ac[c]);
                     }
                 }
-        }
-#pragma unroll
-        for (int kk = 0; kk < CF / 4; ++kk) {
-            float4 v = make_float4(acc[4 * kk], acc[4 * kk + 1], acc[4 * kk + 2], acc[4 * kk + 3]);
-            if (part) {
-                const float4 lo = o[kk];
-                v = make_float4(lo.x + v.x, lo.y + v.y, lo.z + v.z, lo.w + v.w);
             }
-            o[kk] = v;
-        }
+    }
+    float4* o = reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mk * HW +
+                                                   (size_t)qy * W + qx) * CF);
+#pragma unroll
+    for (int kk = 0; kk < CF / 4; ++kk) {
+        float4 v = make_float4(acc[0][4 * kk], acc[0][4 * kk + 1], acc[0][4 * kk + 2], acc[0][4 * kk + 3]);
+#pragma unroll
+        for (int t = 1; t < S; ++t)
+            v = make_float4(v.x + acc[t][4 * kk], v.y + acc[t][4 * kk + 1], v.z + acc[t][4 * kk + 2],
+                            v.w + acc[t][4 * kk + 3]);
+        o[kk] = v;
     }
 }
 
-// Blocks of the target-gradient launch (a multiple of 8): 32 per compute unit,
-// four times what is resident at once (8 per unit measured 7% slower, 16 to 64
-// the same).
-constexpr size_t kTgtBlocks = 256 * 32;
+// Tiled gradient kernels: a block takes kTileQ consecutive entries of one row
+// of one map and first stages in LDS what all of them read besides the
+// gathered feature vectors; then CF / 4 lanes (four channels each) per part
+// of the window rows and row_split(CF) parts per entry gather the vectors and
+// add the same terms in the same order as the one-thread kernels (each part
+// alone, then the parts in order by a shuffle), so the results are identical.
+// Tiles are numbered ((map * batch + b) * H + row) * tiles_x + column tile and
+// given out by XCD, so an XCD's L2 holds a band of rows.
+constexpr int kTileQ = 32;
+constexpr int kTileC = kTileQ + kWinN - 1;  // staged columns: the tile's and the window's
+constexpr int kStageCap = 2048;             // staged pixels per target-gradient tile
 
-// The same gradient with CF / 4 lanes per target entry, each owning four
-// channels: a gathered vector is CF / 4 consecutive 16-byte loads of
-// neighbouring lanes (a few cache lines per load instruction instead of one per
-// lane), a lane holds a float4 accumulator instead of CF, and a wave covers
-// 256 / (CF / 4) / 4 entries, so far fewer lanes wait on the slowest entry of
-// their wave.  row_split(CF) groups of CF / 4 lanes share an entry, each taking
-// one part of the window rows, which shortens the serial chain of each; every
-// channel adds the same terms in the same order as grad_target_kernel (each
-// part in turn, then their sum in part order), so the results are identical.
-template <int CF>
-__global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k,
-                                                               const uint32_t* __restrict__ start,
-                                                               const uint32_t* __restrict__ order) {
-    constexpr int kSplit = row_split(CF), kPartRows = (kWin1 - kWin0 + 1) / kSplit;
-    constexpr int L = CF / 4, G = kSplit * L, QPB = 256 / G;
-    static_assert(G <= 64, "the parts of an entry share one wave");
-    const int sub = threadIdx.x % L, part = (threadIdx.x / L) % kSplit;
-    const int wy0 = kWin0 + part * kPartRows, wy1 = wy0 + kPartRows - 1;  // this part's window rows
-    const int H = a.H, W = a.W, b = blockIdx.y;
+// Add the four-channel part of the terms of one pixel: fma(g, x - y, acc).
+__device__ __forceinline__ void fma4(float g, const float4& x, const float4& y, float4& acc) {
+    acc.x = fmaf(g, x.x - y.x, acc.x);
+    acc.y = fmaf(g, x.y - y.y, acc.y);
+    acc.z = fmaf(g, x.z - y.z, acc.z);
+    acc.w = fmaf(g, x.w - y.w, acc.w);
+}
+
+// One image's feature map read 16 bytes per lane.  BUF: a raw buffer with
+// 32-bit offsets (maps below 2 GiB), where a load flagged `skip` reads nothing
+// (its value is filled in by the caller); otherwise plain loads, `skip`
+// ignored.
+constexpr int kSkipOff = 0x7FFFFFF0;
+template <bool BUF>
+struct Vec4Map {
+    const float4* p;
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ __forceinline__ void init(const float* base, size_t bytes) {
+        p = reinterpret_cast<const float4*>(base);
+        if constexpr (BUF) {
+            const uint64_t a = reinterpret_cast<uint64_t>(base);
+            const uint64_t u = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a) |
+                               ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32)) << 32);
+            rs = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(u), (short)0,
+                                                   (int)__builtin_amdgcn_readfirstlane((uint32_t)bytes),
+                                                   0x00020000);
+        }
+    }
+    __device__ __forceinline__ float4 ld(uint32_t i, bool skip) const {
+        if constexpr (BUF) {
+            const uint4 v = __builtin_bit_cast(
+                uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, skip ? kSkipOff : (int)(i * 16u), 0, 0));
+            return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+                               __uint_as_float(v.w));
+        } else {
+            return p[i];
+        }
+    }
+};
+
+// Sum of the entry's parts, in part order, in the lanes of part 0.
+template <int kSplit, int L>
+__device__ __forceinline__ float4 sum_parts(const float4& acc) {
+    float4 sum = acc;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int g = 1; g < kSplit; ++g) {
+        const int src = lane + g * L;  // part g of this entry, for the lanes of part 0
+        sum.x += __shfl(acc.x, src);
+        sum.y += __shfl(acc.y, src);
+        sum.z += __shfl(acc.z, src);
+        sum.w += __shfl(acc.w, src);
+    }
+    return sum;
+}
+
+// Reference-map gradient: the tile stages 2 g and the three target centres of
+// the pixels its entries' windows reach (8 rows by kTileC columns).
+template <int CF, bool BUF>
+__global__ void __launch_bounds__(256) grad_ref_tile_kernel(CostArgs a, int tiles_x) {
+    constexpr int kSplit = row_split(CF), kPartRows = kWinN / kSplit;
+    constexpr int L = CF / 4, G = kSplit * L, EPB = 256 / G;
+    static_assert(G <= 64 && 64 % G == 0, "the parts of an entry share one wave");
+    __shared__ float s_g[kWinN][kTileC];
+    __shared__ uint32_t s_t[3][kWinN][kTileC];  // (ty << 16) | tx
+    const int H = a.H, W = a.W;
     const size_t HW = (size_t)H * W;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tq = tile % tiles_x, rest = tile / tiles_x;
+    const int qy = rest % H, b = rest / H;
+    const int qx0 = tq * kTileQ;
+    const int py0 = qy - kWin1, px0 = qx0 - kWin1;  // staged pixel (0, 0)
+    for (int idx = threadIdx.x; idx < kWinN * kTileC; idx += 256) {
+        const int r = idx / kTileC, c = idx - r * kTileC;
+        const int py = py0 + r, px = px0 + c;
+        if (py < 0 || py >= H || px < 0 || px >= W) continue;
+        const size_t pix = (size_t)b * HW + (size_t)py * W + px;
+        s_g[r][c] = 2.f * a.gcost[pix];
+        const Targets t = targets(a.hyp, pix, py, px, a.s, H, W);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s_t[k][r][c] = ((uint32_t)t.y[k] << 16) | (uint32_t)t.x[k];
+    }
+    __syncthreads();
     const float* base = a.feat + (size_t)b * 4 * HW * CF;
-    const float4* R = reinterpret_cast<const float4*>(base + (size_t)view(a.s, 0) * HW * CF) + sub;
-    const int mk = view(a.s, k + 1);
-    // A fixed grid (a multiple of 8 blocks) walks the tiles of QPB entries: the
-    // blocks of one XCD take that XCD's band of image rows in turn, so a wave
-    // handles many entries instead of one short entry each.
-    const int ntiles = (int)((HW + QPB - 1) / QPB);
-    const int xcd = blockIdx.x & 7, per = gridDim.x >> 3, nq = ntiles >> 3, rem = ntiles & 7;
-    const int t0 = xcd * nq + min(xcd, rem), t1 = t0 + nq + (xcd < rem ? 1 : 0);
-    for (int tile = t0 + (int)(blockIdx.x >> 3); tile < t1; tile += per) {
-        const size_t q = (size_t)tile * QPB + threadIdx.x / G;
-        if (q >= HW) continue;  // all G lanes of the entry together; only in the last tile
-        const int qy = (int)(q / W), qx = (int)(q - (size_t)qy * W);
-        const float4 fq = reinterpret_cast<const float4*>(base + ((size_t)mk * HW + q) * CF)[sub];
+    const int mR = view(a.s, 0);
+    Vec4Map<BUF> M[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[k].init(base + (size_t)view(a.s, k + 1) * HW * CF, HW * CF * 4);
+    const int sub = threadIdx.x % L, part = (threadIdx.x / L) % kSplit;
+    const int wy0 = kWin0 + part * kPartRows;
+    for (int e0 = 0; e0 < kTileQ; e0 += EPB) {
+        const int qx = qx0 + e0 + (int)threadIdx.x / G;
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-        auto add = [&](uint32_t pix, int wy, int wx) {
+        const bool live = qx < W && qx < qx0 + kTileQ;
+        const size_t q = (size_t)qy * W + qx;
+        float4 fq = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (live) fq = reinterpret_cast<const float4*>(base + ((size_t)mR * HW + q) * CF)[sub];
+        if (live && qy >= kWin1 && qy <= H - 1 + kWin0 && qx >= kWin1 && qx <= W - 1 + kWin0) {
+            // interior: the preimage of q under w is the one pixel q - w.  A
+            // gathered vector equal to the previous one of the same map (a
+            // locally constant field reads one vector for the whole row) is not
+            // loaded again but copied once all loads are back; the arithmetic
+            // is unchanged.
+            int pidx[3] = {-1, -1, -1};
+            float4 pv[3];
+            for (int wy = wy0; wy < wy0 + kPartRows; ++wy) {
+                const int r = qy - wy - py0;
+                float4 tg[kWinN][3];
+                float g2[kWinN];
+                int idx[kWinN][3];
+#pragma unroll
+                for (int j = 0; j < kWinN; ++j) {  // wx = kWin0 + j
+                    const int wx = kWin0 + j, c = qx - wx - px0;
+                    g2[j] = s_g[r][c];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const uint32_t t = s_t[k][r][c];
+                        idx[j][k] = clampi((int)(t >> 16) + wy, 0, H - 1) * W +
+                                    clampi((int)(t & 0xFFFFu) + wx, 0, W - 1);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kWinN; ++j)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        tg[j][k] = M[k].ld((uint32_t)idx[j][k] * L + sub,
+                                           idx[j][k] == (j ? idx[j - 1][k] : pidx[k]));
+                if constexpr (BUF) {
+#pragma unroll
+                    for (int j = 0; j < kWinN; ++j)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+                            if (idx[j][k] == (j ? idx[j - 1][k] : pidx[k])) tg[j][k] = j ? tg[j - 1][k] : pv[k];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        pidx[k] = idx[kWinN - 1][k];
+                        pv[k] = tg[kWinN - 1][k];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kWinN; ++j)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) fma4(g2[j], fq, tg[j][k], acc);
+            }
+        } else if (live) {
+            for (int wy = wy0; wy < wy0 + kPartRows; ++wy) {
+                int ylo, yhi;
+                preimage(qy, wy, H, ylo, yhi);
+                for (int py = ylo; py <= yhi; ++py)
+                    for (int wx = kWin0; wx <= kWin1; ++wx) {
+                        int xlo, xhi;
+                        preimage(qx, wx, W, xlo, xhi);
+                        for (int px = xlo; px <= xhi; ++px) {
+                            const int r = py - py0, c = px - px0;
+                            const float g2 = s_g[r][c];
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) {
+                                const uint32_t t = s_t[k][r][c];
+                                const int ty = (int)(t >> 16), tx = (int)(t & 0xFFFFu);
+                                const float4 tg = M[k].ld((uint32_t)(clampi(ty + wy, 0, H - 1) * W + clampi(tx + wx, 0, W - 1)) * L + sub, false);
+                                fma4(g2, fq, tg, acc);
+                            }
+                        }
+                    }
+            }
+        }
+        const float4 sum = sum_parts<kSplit, L>(acc);
+        if (live && part == 0)
+            reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mR * HW + q) * CF)[sub] = sum;
+    }
+}
+
+// Target-map gradients (all three maps in one launch): the tile stages the
+// pixels grouped at the centre cells its entries' windows reach (8 rows of
+// kTileC cells; position, 2 g and cell column of each, and the run bounds of
+// every cell).  A tile whose cells hold more than kStageCap pixels reads them
+// from the sorted lists in global memory instead, in the same order.  The
+// row_split(CF) groups of CF / 4 lanes of an entry are its accumulators (terms
+// dealt round-robin, as in grad_target_kernel).
+template <int CF, bool BUF>
+__global__ void __launch_bounds__(256) grad_target_tile_kernel(CostArgs a, int tiles_x, size_t n,
+                                                               const uint32_t* __restrict__ start,
+                                                               const uint32_t* __restrict__ skeys,
+                                                               const uint32_t* __restrict__ svals) {
+    constexpr int kSplit = row_split(CF);
+    constexpr int L = CF / 4, G = kSplit * L, EPB = 256 / G;
+    static_assert(G <= 64 && 64 % G == 0, "the parts of an entry share one wave");
+    __shared__ uint32_t s_st[kWinN][kTileC + 1];  // staged run start of each cell, and the row's end
+    __shared__ uint32_t s_row[kWinN + 1];         // staged offset of each row's run
+    __shared__ uint32_t s_gb[kWinN];              // sorted position of each row's run
+    __shared__ uint32_t s_pos[kStageCap];         // (py << 16) | px
+    __shared__ float s_g[kStageCap];
+    __shared__ uint8_t s_cx[kStageCap];           // cell column - tx_lo
+    const int H = a.H, W = a.W;
+    const size_t HW = (size_t)H * W;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tq = tile % tiles_x, rest = tile / tiles_x;
+    const int qy = rest % H, kb = rest / H;
+    const int b = kb % a.batch, k = kb / a.batch;
+    const int qx0 = tq * kTileQ;
+    const int ty0 = qy - kWin1;                                    // staged row 0
+    const int tx_lo = max(qx0 - kWin1, 0), tx_hi = min(qx0 + kTileQ - 1 - kWin0, W - 1);
+    const int ncol = tx_hi - tx_lo + 1;
+    const size_t cbase = (size_t)k * n + (size_t)b * HW;          // cell (0, 0) of map k, image b
+    if (threadIdx.x < kWinN) {
+        const int r = threadIdx.x, ty = ty0 + r;
+        uint32_t g0 = 0, len = 0;
+        if (ty >= 0 && ty < H) {
+            const size_t c0 = cbase + (size_t)ty * W + tx_lo;
+            g0 = start[c0];
+            len = start[c0 + ncol] - g0;
+        }
+        s_gb[r] = g0;
+        s_row[r + 1] = len;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_row[0] = 0;
+        for (int r = 0; r < kWinN; ++r) s_row[r + 1] += s_row[r];
+    }
+    __syncthreads();
+    const uint32_t total = s_row[kWinN];
+    const bool staged = total <= (uint32_t)kStageCap;
+    if (staged) {
+        for (int idx = threadIdx.x; idx < kWinN * (kTileC + 1); idx += 256) {
+            const int r = idx / (kTileC + 1), j = idx - r * (kTileC + 1), ty = ty0 + r;
+            if (j > ncol) continue;
+            uint32_t v = s_row[r];
+            if (ty >= 0 && ty < H) v += start[cbase + (size_t)ty * W + tx_lo + j] - s_gb[r];
+            s_st[r][j] = v;
+        }
+        for (uint32_t e = threadIdx.x; e < total; e += 256) {
+            int r = 0;
+#pragma unroll
+            for (int rr = 1; rr < kWinN; ++rr) r += e >= s_row[rr] ? 1 : 0;
+            const uint32_t ge = s_gb[r] + (e - s_row[r]);
+            const uint32_t pix = svals[ge];
+            const int cc = (int)((size_t)skeys[ge] - cbase - (size_t)(ty0 + r) * W);
             const int pl = (int)(pix - (size_t)b * HW);
             const int py = pl / W, px = pl - py * W;
-            const float g2 = 2.f * a.gcost[pix];
-            const float4 r = R[((size_t)clampi(py + wy, 0, H - 1) * W + clampi(px + wx, 0, W - 1)) * L];
-            acc.x = fmaf(-g2, r.x - fq.x, acc.x);
-            acc.y = fmaf(-g2, r.y - fq.y, acc.y);
-            acc.z = fmaf(-g2, r.z - fq.z, acc.z);
-            acc.w = fmaf(-g2, r.w - fq.w, acc.w);
-        };
-        constexpr int kN = kWin1 - kWin0 + 1;  // 8 window columns
-        if (qy >= kWin1 && qy <= H - 1 + kWin0 && qx >= kWin1 && qx <= W - 1 + kWin0) {
-            // interior: window row wy covers the centre cells (qy - wy, qx - 4 .. qx + 3), consecutive,
-            // so their pixels are one run [st[0], st[8]) of the sorted order; it is walked in that
-            // order (cells by ascending x, the order of the generic loop below) four at a time
-            for (int wy = wy0; wy <= wy1; ++wy) {
-                const size_t c0 = (size_t)b * HW + (size_t)(qy - wy) * W + (qx - kWin1);
-                uint32_t st[kN + 1];
+            s_pos[e] = ((uint32_t)py << 16) | (uint32_t)px;
+            s_g[e] = 2.f * a.gcost[pix];
+            s_cx[e] = (uint8_t)(cc - tx_lo);
+        }
+    }
+    __syncthreads();
+    const float* base = a.feat + (size_t)b * 4 * HW * CF;
+    Vec4Map<BUF> R;
+    R.init(base + (size_t)view(a.s, 0) * HW * CF, HW * CF * 4);
+    const int mk = view(a.s, k + 1);
+    const int sub = threadIdx.x % L, part = (threadIdx.x / L) % kSplit;  // part = accumulator
+    auto rvec = [&](int py, int px, int wy, int wx) {
+        return R.ld((uint32_t)(clampi(py + wy, 0, H - 1) * W + clampi(px + wx, 0, W - 1)) * L + sub, false);
+    };
+    for (int e0 = 0; e0 < kTileQ; e0 += EPB) {
+        const int qx = qx0 + e0 + (int)threadIdx.x / G;
+        const bool live = qx < W;
+        const size_t q = (size_t)qy * W + qx;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 fq = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (live) fq = reinterpret_cast<const float4*>(base + ((size_t)mk * HW + q) * CF)[sub];
+        const bool interior = qy >= kWin1 && qy <= H - 1 + kWin0 && qx >= kWin1 && qx <= W - 1 + kWin0;
+        if (live && staged && interior) {
+            // the terms are the runs of the window rows wy = -3 .. 4 (cells (qy - wy, qx - 4 ..
+            // qx + 3)), one after the other; this lane takes terms part, part + kSplit, ...,
+            // eight at a time.  A vector equal to this lane's previous one (a locally constant
+            // field reads one vector for the whole window) is not loaded again but copied once
+            // all loads are back; the arithmetic is unchanged.
+            const int j0 = qx - kWin1 - tx_lo;
+            uint32_t rb[kWinN], rend[kWinN];
+            uint32_t m = 0;
 #pragma unroll
-                for (int j = 0; j <= kN; ++j) st[j] = start[c0 + j];
-                for (uint32_t e = st[0]; e < st[kN]; e += 4) {
-                    uint32_t pv[4];
-                    int wxv[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const uint32_t eu = min(e + u, st[kN] - 1);
-                        pv[u] = order[eu];
-                        int j = 0;
-#pragma unroll
-                        for (int jj = 1; jj < kN; ++jj) j += eu >= st[jj] ? 1 : 0;
-                        wxv[u] = kWin1 - j;
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (e + u < st[kN]) add(pv[u], wy, wxv[u]);
-                }
+            for (int t = 0; t < kWinN; ++t) {
+                const int r = qy - (kWin0 + t) - ty0;
+                const uint32_t b0 = s_st[r][j0], b1 = s_st[r][j0 + kWinN];
+                rb[t] = b0 - m;  // staged index of term i of this row: rb[t] + i
+                m += b1 - b0;
+                rend[t] = m;
             }
-        } else {
-            for (int wy = wy0; wy <= wy1; ++wy) {
+            int pidx = -1;
+            float4 pv = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (uint32_t i0 = part; i0 < m; i0 += 8 * kSplit) {
+                float4 rv[8];
+                float gv[8];
+                int idx[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t ii = min(i0 + (uint32_t)(u * kSplit), m - 1);
+                    int t = 0;
+#pragma unroll
+                    for (int tt = 0; tt < kWinN - 1; ++tt) t += ii >= rend[tt] ? 1 : 0;
+                    const uint32_t e = rb[t] + ii;
+                    const uint32_t pos = s_pos[e];
+                    gv[u] = s_g[e];
+                    const int wy = kWin0 + t, wx = qx - tx_lo - (int)s_cx[e];
+                    idx[u] = clampi((int)(pos >> 16) + wy, 0, H - 1) * W +
+                             clampi((int)(pos & 0xFFFFu) + wx, 0, W - 1);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    rv[u] = R.ld((uint32_t)idx[u] * L + sub, idx[u] == (u ? idx[u - 1] : pidx));
+                if constexpr (BUF) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (idx[u] == (u ? idx[u - 1] : pidx)) rv[u] = u ? rv[u - 1] : pv;
+                    pidx = idx[7];
+                    pv = rv[7];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (i0 + (uint32_t)(u * kSplit) < m) fma4(-gv[u], rv[u], fq, acc);
+            }
+        } else if (live) {
+            // the canonical order term by term; this lane adds terms part, part + kSplit, ...
+            uint32_t i = 0;
+            for (int wy = kWin0; wy <= kWin1; ++wy) {
                 int ylo, yhi;
                 preimage(qy, wy, H, ylo, yhi);
                 for (int ty = ylo; ty <= yhi; ++ty)
@@ -451,50 +805,61 @@ __global__ void __launch_bounds__(256) grad_target_coop_kernel(CostArgs a, int k
                         int xlo, xhi;
                         preimage(qx, wx, W, xlo, xhi);
                         for (int tx = xlo; tx <= xhi; ++tx) {
-                            const size_t cell = (size_t)b * HW + (size_t)ty * W + tx;
-                            const uint32_t e0 = start[cell], e1 = start[cell + 1];
-                            for (uint32_t e = e0; e < e1; ++e) add(order[e], wy, wx);
+                            if (staged) {
+                                const int r = ty - ty0, j = tx - tx_lo;
+                                const uint32_t e0 = s_st[r][j], e1 = s_st[r][j + 1];
+                                for (uint32_t e = e0 + (part + kSplit - i % kSplit) % kSplit; e < e1; e += kSplit) {
+                                    const uint32_t pos = s_pos[e];
+                                    fma4(-s_g[e], rvec((int)(pos >> 16), (int)(pos & 0xFFFFu), wy, wx), fq, acc);
+                                }
+                                i += e1 - e0;
+                            } else {
+                                const size_t cell = cbase + (size_t)ty * W + tx;
+                                const uint32_t e0 = start[cell], e1 = start[cell + 1];
+                                for (uint32_t e = e0 + (part + kSplit - i % kSplit) % kSplit; e < e1; e += kSplit) {
+                                    const uint32_t pix = svals[e];
+                                    const int pl = (int)(pix - (size_t)b * HW);
+                                    const int py = pl / W, px = pl - py * W;
+                                    fma4(-2.f * a.gcost[pix], rvec(py, px, wy, wx), fq, acc);
+                                }
+                                i += e1 - e0;
+                            }
                         }
                     }
             }
         }
-        // ((part 0 + part 1) + part 2) + ..., as the one-lane kernel adds them
-        float4 sum = acc;
-        const int lane = threadIdx.x & 63;
-#pragma unroll
-        for (int g = 1; g < kSplit; ++g) {
-            const int src = lane + g * L;  // part g of this entry, for the lanes of part 0
-            sum.x += __shfl(acc.x, src);
-            sum.y += __shfl(acc.y, src);
-            sum.z += __shfl(acc.z, src);
-            sum.w += __shfl(acc.w, src);
-        }
-        if (part == 0)
+        const float4 sum = sum_parts<kSplit, L>(acc);
+        if (live && part == 0)
             reinterpret_cast<float4*>(a.out + ((size_t)b * 4 * HW + (size_t)mk * HW + q) * CF)[sub] = sum;
     }
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Workspace of the backward: the key/value lists (two buffers each for the
+// sort passes), the cell starts and the per-block digit counts.
 struct BwdWs {
-    size_t keys_in, vals_in, keys_out, order, start, temp, temp_bytes, total;
+    size_t N, nblk, keys_a, vals_a, keys_b, vals_b, start, hist, sums, total;
 };
 
-bool bwd_ws(size_t n, BwdWs* L) {
-    size_t temp = 0;
-    if (rocprim::radix_sort_pairs(nullptr, temp, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                  (uint32_t*)nullptr, (uint32_t*)nullptr, n) != hipSuccess)
-        return false;
-    L->keys_in = 0;
-    L->vals_in = L->keys_in + align256(n * 4);
-    L->keys_out = L->vals_in + align256(n * 4);
-    L->order = L->keys_out + align256(n * 4);
-    L->start = L->order + align256(n * 4);
-    L->temp = L->start + align256((n + 1) * 4);
-    L->temp_bytes = temp;
-    L->total = L->temp + align256(temp);
-    return true;
+BwdWs bwd_ws(size_t n) {
+    BwdWs L;
+    L.N = 3 * n;
+    L.nblk = (L.N + kSortTile - 1) / kSortTile;
+    L.keys_a = 0;
+    L.vals_a = L.keys_a + align256(L.N * 4);
+    L.keys_b = L.vals_a + align256(L.N * 4);
+    L.vals_b = L.keys_b + align256(L.N * 4);
+    L.start = L.vals_b + align256(L.N * 4);
+    L.hist = L.start + align256((L.N + 1) * 4);
+    L.sums = L.hist + align256(256 * L.nblk * 4);
+    L.total = L.sums + align256((256 * L.nblk + 1023) / 1024 * 4);
+    return L;
 }
+
+// Largest batch * H * W the backward takes: its lists hold 3 entries per pixel
+// with 32-bit positions.
+constexpr size_t kBwdMaxPixels = (size_t)1 << 30;
 
 bool shape_ok(int batch, int H, int W, int cf, int dir) {
     if (batch < 1 || H < 1 || W < 1 || H > 16384 || W > 16384) return false;
@@ -533,13 +898,23 @@ struct TgtK {
 };
 
 template <int CF>
-struct RefCoopK {
-    static constexpr auto fn = grad_ref_coop_kernel<CF>;
+struct RefTileK {
+    static constexpr auto fn = grad_ref_tile_kernel<CF, true>;
 };
 
 template <int CF>
-struct TgtCoopK {
-    static constexpr auto fn = grad_target_coop_kernel<CF>;
+struct TgtTileK {
+    static constexpr auto fn = grad_target_tile_kernel<CF, true>;
+};
+
+template <int CF>
+struct RefTileWideK {
+    static constexpr auto fn = grad_ref_tile_kernel<CF, false>;
+};
+
+template <int CF>
+struct TgtTileWideK {
+    static constexpr auto fn = grad_target_tile_kernel<CF, false>;
 };
 
 }  // namespace
@@ -566,10 +941,8 @@ extern "C" sff_status sff_cost_f32_fwd(int32_t batch, int32_t H, int32_t W, int3
 }
 
 extern "C" size_t sff_cost_f32_bwd_workspace_bytes(int32_t batch, int32_t H, int32_t W) {
-    if (batch < 1 || H < 1 || W < 1 || (size_t)batch * H * W >= (1ull << 31)) return 0;
-    BwdWs L;
-    if (!bwd_ws((size_t)batch * H * W, &L)) return 0;
-    return L.total;
+    if (batch < 1 || H < 1 || W < 1 || (size_t)batch * H * W > kBwdMaxPixels) return 0;
+    return bwd_ws((size_t)batch * H * W).total;
 }
 
 extern "C" sff_status sff_cost_f32_bwd(int32_t batch, int32_t H, int32_t W, int32_t cf,
@@ -583,43 +956,64 @@ extern "C" sff_status sff_cost_f32_bwd(int32_t batch, int32_t H, int32_t W, int3
         (reinterpret_cast<uintptr_t>(grad_feat) & 15) != 0)
         return SFF_ERR_INVALID_ARG;
     const size_t n = (size_t)batch * H * W;
-    BwdWs L;
-    if (!bwd_ws(n, &L)) return SFF_ERR_HIP;
+    if (n > kBwdMaxPixels) return SFF_ERR_UNSUPPORTED;
+    const BwdWs L = bwd_ws(n);
     if (!workspace || workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return SFF_ERR_WORKSPACE;
     hipStream_t st = as_stream(stream);
     uint8_t* ws = static_cast<uint8_t*>(workspace);
-    uint32_t* keys_in = reinterpret_cast<uint32_t*>(ws + L.keys_in);
-    uint32_t* vals_in = reinterpret_cast<uint32_t*>(ws + L.vals_in);
-    uint32_t* keys_out = reinterpret_cast<uint32_t*>(ws + L.keys_out);
-    uint32_t* order = reinterpret_cast<uint32_t*>(ws + L.order);
+    uint32_t* ka = reinterpret_cast<uint32_t*>(ws + L.keys_a);
+    uint32_t* va = reinterpret_cast<uint32_t*>(ws + L.vals_a);
+    uint32_t* kb = reinterpret_cast<uint32_t*>(ws + L.keys_b);
+    uint32_t* vb = reinterpret_cast<uint32_t*>(ws + L.vals_b);
     uint32_t* start = reinterpret_cast<uint32_t*>(ws + L.start);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + L.hist);
+    uint32_t* sums = reinterpret_cast<uint32_t*>(ws + L.sums);
+    const size_t nhist = 256 * L.nblk, nchunks = (nhist + 1023) / 1024;
     CostArgs a{feat, hyp, grad_cost, grad_feat, H, W, dir, batch};
-    const dim3 grid((W + 63) / 64, (H + 3) / 4, batch);
     // SFF_COST_F32_EVAL=lane: one lane per gradient entry (same results; testing and timing)
     const char* ev = std::getenv("SFF_COST_F32_EVAL");
     const bool lane_grad = ev && std::strcmp(ev, "lane") == 0;
-    const dim3 cgrid((unsigned)(((size_t)H * W * (cf / 4) + 255) / 256), batch);
+    const int tiles_x = (W + kTileQ - 1) / kTileQ;
+    const dim3 grid((W + 63) / 64, (H + 3) / 4, batch);
+    // maps below 2 GiB are read through 32-bit buffer offsets
+    const bool buf = (size_t)H * W * cf * 4 <= (size_t)kSkipOff;
     if (lane_grad)
         launch_cf<RefK>(cf, grid, st, a);
+    else if (buf)
+        launch_cf<RefTileK>(cf, dim3((unsigned)((size_t)batch * H * tiles_x)), st, a, tiles_x);
     else
-        launch_cf<RefCoopK>(cf, cgrid, st, a);
-    unsigned int bits = 1;
-    while (bits < 32 && (1ull << bits) < n) ++bits;
-    for (int k = 0; k < 3; ++k) {
-        hipLaunchKernelGGL(target_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                           hyp, keys_in, vals_in, H, W, dir, k, batch);
-        size_t temp = L.temp_bytes;
-        if (rocprim::radix_sort_pairs(ws + L.temp, temp, keys_in, keys_out, vals_in, order, n, 0,
-                                      bits, st) != hipSuccess)
-            return SFF_ERR_HIP;
-        hipLaunchKernelGGL(cell_starts_kernel, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0,
-                           st, keys_out, start, n);
-        if (lane_grad)
-            launch_cf<TgtK>(cf, grid, st, a, k, (const uint32_t*)start, (const uint32_t*)order);
-        else
-            launch_cf<TgtCoopK>(cf, dim3((unsigned)std::min<size_t>(((((size_t)H * W * (cf / 4) * row_split(cf) + 255) / 256) + 7) & ~(size_t)7, kTgtBlocks), batch),
-                                st, a, k, (const uint32_t*)start, (const uint32_t*)order);
+        launch_cf<RefTileWideK>(cf, dim3((unsigned)((size_t)batch * H * tiles_x)), st, a, tiles_x);
+    // group the pixels by target centre: keys, then a stable radix sort
+    const size_t N = L.N;
+    hipLaunchKernelGGL(target_keys_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, hyp,
+                       ka, va, H, W, dir, (uint32_t)n);
+    int bits = 1;
+    while (bits < 32 && (1ull << bits) < N) ++bits;
+    uint32_t *kin = ka, *vin = va, *kout = kb, *vout = vb;
+    for (int sh = 0; sh < bits; sh += 8) {
+        hipLaunchKernelGGL(sort_hist_kernel, dim3((unsigned)L.nblk), dim3(256), 0, st,
+                           (const uint32_t*)kin, N, sh, hist, (uint32_t)L.nblk);
+        hipLaunchKernelGGL(sort_scan_chunks_kernel, dim3((unsigned)nchunks), dim3(1024), 0, st, hist,
+                           nhist, sums);
+        hipLaunchKernelGGL(sort_scan_sums_kernel, dim3(1), dim3(1024), 0, st, sums, nchunks);
+        hipLaunchKernelGGL(sort_scatter_kernel, dim3((unsigned)L.nblk), dim3(256), 0, st,
+                           (const uint32_t*)kin, (const uint32_t*)vin, kout, vout, N, sh,
+                           (const uint32_t*)hist, (const uint32_t*)sums, (uint32_t)L.nblk);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    hipLaunchKernelGGL(cell_starts_kernel, dim3((unsigned)((N + 1 + 255) / 256)), dim3(256), 0, st,
+                       (const uint32_t*)kin, start, N);
+    if (lane_grad) {
+        for (int k = 0; k < 3; ++k)
+            launch_cf<TgtK>(cf, grid, st, a, k, n, (const uint32_t*)start, (const uint32_t*)vin);
+    } else if (buf) {
+        launch_cf<TgtTileK>(cf, dim3((unsigned)((size_t)3 * batch * H * tiles_x)), st, a, tiles_x, n,
+                            (const uint32_t*)start, (const uint32_t*)kin, (const uint32_t*)vin);
+    } else {
+        launch_cf<TgtTileWideK>(cf, dim3((unsigned)((size_t)3 * batch * H * tiles_x)), st, a, tiles_x, n,
+                                (const uint32_t*)start, (const uint32_t*)kin, (const uint32_t*)vin);
     }
     return launch_status();
 }

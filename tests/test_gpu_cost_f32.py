@@ -150,3 +150,39 @@ def test_kitti_size_c32_against_finite_differences(sff):
     got = np.array([grad[m, y, x, c] for (m, y, x, c) in ent])
     scale = np.abs(fd).mean()
     assert (np.abs(got - fd) <= 1e-4 * np.abs(fd) + 1e-4 * scale).all()
+
+
+def test_many_tiles_identical_to_one_lane(sff, monkeypatch):
+    """C = 32 at 1 x 200 x 200 (7 tiles of 32 entries a row, 1400 per map,
+    three target maps in one launch): the tiled gradient kernels against one
+    lane per entry, bit for bit, twice (deterministic)."""
+    F, hyp, g = _random_case(77, 1, 200, 200, 32, spread=12)
+    _say("cost_f32 many tiles C=32 200x200")
+    monkeypatch.delenv("SFF_COST_F32_EVAL", raising=False)
+    grad = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), 1, _dev(g)).cpu().numpy()
+    again = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), 1, _dev(g)).cpu().numpy()
+    monkeypatch.setenv("SFF_COST_F32_EVAL", "lane")
+    lane = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), 1, _dev(g)).cpu().numpy()
+    assert np.array_equal(grad, again)
+    assert np.array_equal(grad, lane)
+
+
+def test_crowded_centres_use_the_global_lists(sff, monkeypatch):
+    """Vectors that send whole rows to one centre cell (u far to the left,
+    clamped to column 0): the cells of the first tile of a row hold about
+    8 x 300 pixels, more than a tile stages, so that tile reads the sorted
+    lists from global memory; same bits as one lane per entry, and the FP64
+    oracle's gradient."""
+    B, H, W, C = 1, 12, 300, 8
+    F, hyp, g = _random_case(5, B, H, W, C, spread=3)
+    hyp[..., 0] = -1000
+    _say("cost_f32 crowded centres")
+    monkeypatch.delenv("SFF_COST_F32_EVAL", raising=False)
+    grad = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), 1, _dev(g)).cpu().numpy()
+    monkeypatch.setenv("SFF_COST_F32_EVAL", "lane")
+    lane = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), 1, _dev(g)).cpu().numpy()
+    assert np.array_equal(grad, lane)
+    Fb = [F[0, m].astype(np.float64) for m in range(4)]
+    G = ocf.window_cost_grad(Fb, hyp[0], 1, g[0])
+    for m in range(4):
+        assert _grad_close(grad[0, m], G[m]).all(), m
