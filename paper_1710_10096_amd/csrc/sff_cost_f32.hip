@@ -547,6 +547,7 @@ __global__ void __launch_bounds__(256) grad_ref_tile_kernel(CostArgs a, int tile
     static_assert(G <= 64 && 64 % G == 0, "the parts of an entry share one wave");
     __shared__ float s_g[kWinN][kTileC];
     __shared__ uint32_t s_t[3][kWinN][kTileC];  // (ty << 16) | tx
+    __shared__ float4 s_fq[kTileQ * L];         // the entries' own vectors
     const int H = a.H, W = a.W;
     const size_t HW = (size_t)H * W;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -564,9 +565,14 @@ __global__ void __launch_bounds__(256) grad_ref_tile_kernel(CostArgs a, int tile
 #pragma unroll
         for (int k = 0; k < 3; ++k) s_t[k][r][c] = ((uint32_t)t.y[k] << 16) | (uint32_t)t.x[k];
     }
-    __syncthreads();
     const float* base = a.feat + (size_t)b * 4 * HW * CF;
     const int mR = view(a.s, 0);
+    for (int idx = threadIdx.x; idx < kTileQ * L; idx += 256) {
+        const int qx = qx0 + idx / L;
+        if (qx < W)
+            s_fq[idx] = reinterpret_cast<const float4*>(base + ((size_t)mR * HW + (size_t)qy * W + qx) * CF)[idx % L];
+    }
+    __syncthreads();
     Vec4Map<BUF> M[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) M[k].init(base + (size_t)view(a.s, k + 1) * HW * CF, HW * CF * 4);
@@ -578,7 +584,7 @@ __global__ void __launch_bounds__(256) grad_ref_tile_kernel(CostArgs a, int tile
         const bool live = qx < W && qx < qx0 + kTileQ;
         const size_t q = (size_t)qy * W + qx;
         float4 fq = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (live) fq = reinterpret_cast<const float4*>(base + ((size_t)mR * HW + q) * CF)[sub];
+        if (live) fq = s_fq[(qx - qx0) * L + sub];
         if (live && qy >= kWin1 && qy <= H - 1 + kWin0 && qx >= kWin1 && qx <= W - 1 + kWin0) {
             // interior: the preimage of q under w is the one pixel q - w.  A
             // gathered vector equal to the previous one of the same map (a
@@ -675,6 +681,7 @@ __global__ void __launch_bounds__(256) grad_target_tile_kernel(CostArgs a, int t
     __shared__ uint32_t s_pos[kStageCap];         // (py << 16) | px
     __shared__ float s_g[kStageCap];
     __shared__ uint8_t s_cx[kStageCap];           // cell column - tx_lo
+    __shared__ float4 s_fq[kTileQ * L];           // the entries' own vectors
     const int H = a.H, W = a.W;
     const size_t HW = (size_t)H * W;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -727,8 +734,14 @@ __global__ void __launch_bounds__(256) grad_target_tile_kernel(CostArgs a, int t
             s_cx[e] = (uint8_t)(cc - tx_lo);
         }
     }
-    __syncthreads();
     const float* base = a.feat + (size_t)b * 4 * HW * CF;
+    for (int idx = threadIdx.x; idx < kTileQ * L; idx += 256) {
+        const int qx = qx0 + idx / L;
+        if (qx < W)
+            s_fq[idx] = reinterpret_cast<const float4*>(
+                base + ((size_t)view(a.s, k + 1) * HW + (size_t)qy * W + qx) * CF)[idx % L];
+    }
+    __syncthreads();
     Vec4Map<BUF> R;
     R.init(base + (size_t)view(a.s, 0) * HW * CF, HW * CF * 4);
     const int mk = view(a.s, k + 1);
@@ -742,57 +755,92 @@ __global__ void __launch_bounds__(256) grad_target_tile_kernel(CostArgs a, int t
         const size_t q = (size_t)qy * W + qx;
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
         float4 fq = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (live) fq = reinterpret_cast<const float4*>(base + ((size_t)mk * HW + q) * CF)[sub];
+        if (live) fq = s_fq[(qx - qx0) * L + sub];
         const bool interior = qy >= kWin1 && qy <= H - 1 + kWin0 && qx >= kWin1 && qx <= W - 1 + kWin0;
-        if (live && staged && interior) {
+        // the whole wave takes the interior path or none of it does (shuffles); a tile too
+        // crowded to stage reads the same terms from the sorted lists in global memory
+        if (__all(!live || interior)) {
             // the terms are the runs of the window rows wy = -3 .. 4 (cells (qy - wy, qx - 4 ..
-            // qx + 3)), one after the other; this lane takes terms part, part + kSplit, ...,
-            // eight at a time.  A vector equal to this lane's previous one (a locally constant
-            // field reads one vector for the whole window) is not loaded again but copied once
-            // all loads are back; the arithmetic is unchanged.
+            // qx + 3)), one after the other, in blocks of G: lane lg of the entry's G lanes
+            // finds term i0 + lg (row, staged pixel, gathered vector, 2 g) once, and the lanes of
+            // accumulator `part` take terms i0 + part, i0 + part + kSplit, ... from them by
+            // shuffles, all their loads in flight together.  A vector equal to the accumulator's
+            // previous one (a locally constant field reads one vector for the whole window) is not
+            // loaded again but copied once all loads are back; the arithmetic is unchanged.
+            constexpr int U = G / kSplit;  // terms per accumulator and block
+            const int lg = (int)threadIdx.x % G, gbase = ((int)threadIdx.x & 63) - lg;
             const int j0 = qx - kWin1 - tx_lo;
             uint32_t rb[kWinN], rend[kWinN];
             uint32_t m = 0;
 #pragma unroll
             for (int t = 0; t < kWinN; ++t) {
                 const int r = qy - (kWin0 + t) - ty0;
-                const uint32_t b0 = s_st[r][j0], b1 = s_st[r][j0 + kWinN];
-                rb[t] = b0 - m;  // staged index of term i of this row: rb[t] + i
+                uint32_t b0 = 0, b1 = 0;
+                if (live && staged) {
+                    b0 = s_st[r][j0];
+                    b1 = s_st[r][j0 + kWinN];
+                } else if (live) {
+                    const size_t c0 = cbase + (size_t)(ty0 + r) * W + (qx - kWin1);
+                    b0 = start[c0];
+                    b1 = start[c0 + kWinN];
+                }
+                rb[t] = b0 - m;  // staged (or sorted) index of term i of this row: rb[t] + i
                 m += b1 - b0;
                 rend[t] = m;
             }
             int pidx = -1;
             float4 pv = make_float4(0.f, 0.f, 0.f, 0.f);
-            for (uint32_t i0 = part; i0 < m; i0 += 8 * kSplit) {
-                float4 rv[8];
-                float gv[8];
-                int idx[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const uint32_t ii = min(i0 + (uint32_t)(u * kSplit), m - 1);
+            const uint32_t mmax = (uint32_t)__reduce_max_sync(~0ull, m);
+            for (uint32_t i0 = 0; i0 < mmax; i0 += G) {
+                const uint32_t it = i0 + (uint32_t)lg;
+                int tidx = 0;
+                float tg2 = 0.f;
+                if (it < m) {
                     int t = 0;
 #pragma unroll
-                    for (int tt = 0; tt < kWinN - 1; ++tt) t += ii >= rend[tt] ? 1 : 0;
-                    const uint32_t e = rb[t] + ii;
-                    const uint32_t pos = s_pos[e];
-                    gv[u] = s_g[e];
-                    const int wy = kWin0 + t, wx = qx - tx_lo - (int)s_cx[e];
-                    idx[u] = clampi((int)(pos >> 16) + wy, 0, H - 1) * W +
-                             clampi((int)(pos & 0xFFFFu) + wx, 0, W - 1);
+                    for (int tt = 0; tt < kWinN - 1; ++tt) t += it >= rend[tt] ? 1 : 0;
+                    const uint32_t e = rb[t] + it;
+                    const int wy = kWin0 + t;
+                    int py, px, wx;
+                    if (staged) {
+                        const uint32_t pos = s_pos[e];
+                        tg2 = s_g[e];
+                        py = (int)(pos >> 16);
+                        px = (int)(pos & 0xFFFFu);
+                        wx = qx - tx_lo - (int)s_cx[e];
+                    } else {
+                        const uint32_t pix = svals[e];
+                        const int cc = (int)((size_t)skeys[e] - cbase - (size_t)(qy - wy) * W);
+                        const int pl = (int)(pix - (size_t)b * HW);
+                        py = pl / W;
+                        px = pl - py * W;
+                        tg2 = 2.f * a.gcost[pix];
+                        wx = qx - cc;
+                    }
+                    tidx = clampi(py + wy, 0, H - 1) * W + clampi(px + wx, 0, W - 1);
+                }
+                float4 rv[U];
+                float gv[U];
+                int idx[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int src = gbase + u * kSplit + part;
+                    idx[u] = __shfl(tidx, src);
+                    gv[u] = __shfl(tg2, src);
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
+                for (int u = 0; u < U; ++u)
                     rv[u] = R.ld((uint32_t)idx[u] * L + sub, idx[u] == (u ? idx[u - 1] : pidx));
                 if constexpr (BUF) {
 #pragma unroll
-                    for (int u = 0; u < 8; ++u)
+                    for (int u = 0; u < U; ++u)
                         if (idx[u] == (u ? idx[u - 1] : pidx)) rv[u] = u ? rv[u - 1] : pv;
-                    pidx = idx[7];
-                    pv = rv[7];
+                    pidx = idx[U - 1];
+                    pv = rv[U - 1];
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (i0 + (uint32_t)(u * kSplit) < m) fma4(-gv[u], rv[u], fq, acc);
+                for (int u = 0; u < U; ++u)
+                    if (i0 + (uint32_t)(u * kSplit + part) < m) fma4(-gv[u], rv[u], fq, acc);
             }
         } else if (live) {
             // the canonical order term by term; this lane adds terms part, part + kSplit, ...
