@@ -591,46 +591,51 @@ __global__ void __launch_bounds__(256) grad_ref_tile_kernel(CostArgs a, int tile
             // locally constant field reads one vector for the whole row) is not
             // loaded again but copied once all loads are back; the arithmetic
             // is unchanged.
+            // (half a window row, 12 gathers, at a time: fewer registers, more waves)
+            constexpr int JH = kWinN / 2;
             int pidx[3] = {-1, -1, -1};
             float4 pv[3];
             for (int wy = wy0; wy < wy0 + kPartRows; ++wy) {
                 const int r = qy - wy - py0;
-                float4 tg[kWinN][3];
-                float g2[kWinN];
-                int idx[kWinN][3];
 #pragma unroll
-                for (int j = 0; j < kWinN; ++j) {  // wx = kWin0 + j
-                    const int wx = kWin0 + j, c = qx - wx - px0;
-                    g2[j] = s_g[r][c];
+                for (int h = 0; h < 2; ++h) {
+                    float4 tg[JH][3];
+                    float g2[JH];
+                    int idx[JH][3];
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const uint32_t t = s_t[k][r][c];
-                        idx[j][k] = clampi((int)(t >> 16) + wy, 0, H - 1) * W +
-                                    clampi((int)(t & 0xFFFFu) + wx, 0, W - 1);
+                    for (int jj = 0; jj < JH; ++jj) {  // wx = kWin0 + j
+                        const int j = h * JH + jj, wx = kWin0 + j, c = qx - wx - px0;
+                        g2[jj] = s_g[r][c];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            const uint32_t t = s_t[k][r][c];
+                            idx[jj][k] = clampi((int)(t >> 16) + wy, 0, H - 1) * W +
+                                         clampi((int)(t & 0xFFFFu) + wx, 0, W - 1);
+                        }
                     }
-                }
 #pragma unroll
-                for (int j = 0; j < kWinN; ++j)
-#pragma unroll
-                    for (int k = 0; k < 3; ++k)
-                        tg[j][k] = M[k].ld((uint32_t)idx[j][k] * L + sub,
-                                           idx[j][k] == (j ? idx[j - 1][k] : pidx[k]));
-                if constexpr (BUF) {
-#pragma unroll
-                    for (int j = 0; j < kWinN; ++j)
+                    for (int jj = 0; jj < JH; ++jj)
 #pragma unroll
                         for (int k = 0; k < 3; ++k)
-                            if (idx[j][k] == (j ? idx[j - 1][k] : pidx[k])) tg[j][k] = j ? tg[j - 1][k] : pv[k];
+                            tg[jj][k] = M[k].ld((uint32_t)idx[jj][k] * L + sub,
+                                                idx[jj][k] == (jj ? idx[jj - 1][k] : pidx[k]));
+                    if constexpr (BUF) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        pidx[k] = idx[kWinN - 1][k];
-                        pv[k] = tg[kWinN - 1][k];
+                        for (int jj = 0; jj < JH; ++jj)
+#pragma unroll
+                            for (int k = 0; k < 3; ++k)
+                                if (idx[jj][k] == (jj ? idx[jj - 1][k] : pidx[k])) tg[jj][k] = jj ? tg[jj - 1][k] : pv[k];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            pidx[k] = idx[JH - 1][k];
+                            pv[k] = tg[JH - 1][k];
+                        }
                     }
+#pragma unroll
+                    for (int jj = 0; jj < JH; ++jj)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) fma4(g2[jj], fq, tg[jj][k], acc);
                 }
-#pragma unroll
-                for (int j = 0; j < kWinN; ++j)
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) fma4(g2[j], fq, tg[j][k], acc);
             }
         } else if (live) {
             for (int wy = wy0; wy < wy0 + kPartRows; ++wy) {
