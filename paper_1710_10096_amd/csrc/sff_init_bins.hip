@@ -28,7 +28,8 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kQRows = 4;    // query rows per block (one 16-query MFMA tile each)
+constexpr int kQRows = 8;    // query rows per block (one 16-query MFMA tile each)
+constexpr int kParts = 256 / (16 * kQRows);  // threads per query in the epipolar searches
 constexpr int kWaves = 4;    // waves per block, splitting the candidate rows
 constexpr int kCentre = 510;  // bins lie in 0..1020
 
@@ -58,7 +59,7 @@ struct BinInitArgs {
 // p = i * Wk + j, Nk = Hk * Wk:
 //   c32[c][z][p][32], c16[z][p][16]: candidates b' (fp16), chunk c of K;
 //   q32, q16: queries -2 a' (fp16), same layout;
-//   sq[z][p] = |b'|^2; sqx[z][i][wx] the same norms with column j at
+//   sq[z][p] = |b'|^2; sqx[z][i][wx] the same norms as fp32 (exact) with column j at
 //   offx + j and the edge values repeated over 16+ columns on either side, so
 //   the 4 candidates of a lane are one aligned 16-byte load (offx = 16 +
 //   (F mod 4) makes offx + c0 + 4g a multiple of 4 for every tile start
@@ -66,7 +67,7 @@ struct BinInitArgs {
 struct OpPlanes {
     _Float16 *c32, *c16, *q32, *q16;
     uint32_t* sq;
-    uint32_t* sqx;
+    float* sqx;
     size_t nzk;  // nz * Nk
     int wx, offx;
 };
@@ -154,12 +155,13 @@ __global__ void __launch_bounds__(256) op_planes_kernel(BinInitArgs a, OpPlanes 
         }
     }
     P.sq[o] = sq;
-    uint32_t* row = P.sqx + ((size_t)z * a.Hk + i) * P.wx;
-    row[P.offx + j] = sq;
+    float* row = P.sqx + ((size_t)z * a.Hk + i) * P.wx;
+    const float sqf = (float)sq;  // exact: below 2^24
+    row[P.offx + j] = sqf;
     if (j == 0)
-        for (int x = 0; x < P.offx; ++x) row[x] = sq;
+        for (int x = 0; x < P.offx; ++x) row[x] = sqf;
     if (j == a.Wk - 1)
-        for (int x = P.offx + a.Wk; x < P.wx; ++x) row[x] = sq;
+        for (int x = P.offx + a.Wk; x < P.wx; ++x) row[x] = sqf;
 }
 
 // One block: kQRows rows x 16 consecutive columns of reference grid pixels of
@@ -184,8 +186,8 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
     __shared__ int res_u[kQRows][16][K], res_v[kQRows][16][K];
     __shared__ uint32_t res_t[kQRows][16][K];
     __shared__ int res_n[kQRows][16];
-    __shared__ unsigned long long red2[4][kQRows][16];
-    __shared__ unsigned long long redx[K][4][kQRows][16];
+    __shared__ unsigned long long red2[kParts][kQRows][16];
+    __shared__ unsigned long long redx[K][kParts][kQRows][16];
     const int lane = threadIdx.x & 63, w = wave_id();
     const int nq = lane & 15, g = lane >> 4;
     const int j0 = blockIdx.x * 16, i0 = blockIdx.y * kQRows;
@@ -219,13 +221,6 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
         for (int c = 0; c < KS::N32; ++c)
             q32[t][c] = *reinterpret_cast<const h8*>(P.q32 + ((size_t)c * P.nzk + o) * 32 + 8 * g);
         if constexpr (KS::N16 > 0) q16[t] = *reinterpret_cast<const h4*>(P.q16 + o * 16 + 4 * g);
-        best[t] = INT_MAX;
-        btile[t] = 0;
-#pragma unroll
-        for (int l = 0; l < K; ++l) {
-            tk[t][l] = INT_MAX;
-            ti[t][l] = 0;
-        }
     }
     // Scan: per query only the minimum key over this lane's candidates and the
     // first tile (in increasing target index) that reaches it are kept; the
@@ -241,7 +236,7 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
     struct Tile {
         h8 a32[KS::N32 > 0 ? KS::N32 : 1];
         h4 a16;
-        int bsq[4];
+        float bsq[4];  // |b'|^2, exact in fp32 (below 2^24)
     };
     // Loads of tile (r, ct); the scan issues those of the next tile before it
     // scores the current one.
@@ -254,103 +249,176 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
         for (int c = 0; c < KS::N32; ++c)
             T.a32[c] = *reinterpret_cast<const h8*>(P.c32 + ((size_t)c * P.nzk + oa) * 32 + 8 * g);
         if constexpr (KS::N16 > 0) T.a16 = *reinterpret_cast<const h4*>(P.c16 + oa * 16 + 4 * g);
-        const uint4 q = *reinterpret_cast<const uint4*>(P.sqx + (zTx + (size_t)r) * P.wx + P.offx + c0 + 4 * g);
-        T.bsq[0] = (int)q.x;
-        T.bsq[1] = (int)q.y;
-        T.bsq[2] = (int)q.z;
-        T.bsq[3] = (int)q.w;
+        const float4 q = *reinterpret_cast<const float4*>(P.sqx + (zTx + (size_t)r) * P.wx + P.offx + c0 + 4 * g);
+        T.bsq[0] = q.x;
+        T.bsq[1] = q.y;
+        T.bsq[2] = q.z;
+        T.bsq[3] = q.w;
         return T;
     };
-    Tile ta{}, tb{};
-    int r = rlo + w, ct = ct_lo;
-    if (total > 0) ta = load_tile(r, ct);
-    auto scan_one = [&](const Tile& cur, Tile& nxt, int q) {
-        int rn = r, ctn = ct + 1;
-        if (ctn > ct_hi) {
-            ctn = ct_lo;
-            rn += kWaves;
-        }
-        if (q + 1 < total) nxt = load_tile(rn, ctn);
-        const int c0 = j0 - F + 16 * ct;
-        const int tile_id = (r << 16) | ct;
-        // every query row of the block has row r inside its box (wave-uniform)
-        const bool all_rows = i0 + kQRows - 1 < Hk && r >= i0 + kQRows - 1 - F && r <= i0 + F;
-        // Keys of one tile for every query row.  Candidates outside the image
-        // or this lane's query box get INT_MAX (above any true key); interior
-        // tiles (every candidate inside every query's box) and rows inside
-        // every query row's box skip those tests.  Both conditions are
-        // wave-uniform.
-        auto score = [&](auto interior, auto rows_in) {
-            constexpr bool kInterior = decltype(interior)::value;
-            constexpr bool kRowsIn = decltype(rows_in)::value;
-            bool ok[4] = {true, true, true, true};
-            if constexpr (!kInterior) {
+    // The scan, with keys as fp32 (the fast form) or as int32 (exact for any
+    // key).  An fp32 key is the correctly rounded sum of two exact terms, so
+    // it is exact whenever the key is below 2^24 in magnitude, and a key at or
+    // above 2^24 rounds to a value at or above 2^24: the kept minimum (or the
+    // K kept keys) and their order are exact unless one of them is at or above
+    // 2^24, and then the block scans again with int32 keys.
+    auto run_scan = [&](auto key_tag, auto& S) {
+        using KT = decltype(key_tag);
+        constexpr bool kFloat = std::is_same<KT, float>::value;
+        const KT kNone = kFloat ? (KT)__builtin_huge_valf() : (KT)INT_MAX;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int jc = c0 + 4 * g + e;
-                    ok[e] = (unsigned)(jc - jq + F) <= (unsigned)(2 * F) && (unsigned)jc < (unsigned)Wk;
-                }
+        for (int t = 0; t < kQRows; ++t) {
+            S.best[t] = kNone;
+            S.btile[t] = 0;
+#pragma unroll
+            for (int l = 0; l < K; ++l) {
+                S.tk[t][l] = kNone;
+                S.ti[t][l] = 0;
             }
-#pragma unroll
-            for (int t = 0; t < kQRows; ++t) {
-                if constexpr (!kRowsIn) {
-                    const int iq = i0 + t;
-                    if (iq >= Hk || r < iq - F || r > iq + F) continue;
-                }
-                f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int c = 0; c < KS::N32; ++c)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(cur.a32[c], q32[t][c], acc, 0, 0, 0);
-                if constexpr (KS::N16 > 0)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(cur.a16, q16[t], acc, 0, 0, 0);
-                int k[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    // |b'|^2 + (-2 a'.b'), the product exact in fp32
-                    k[e] = cur.bsq[e] + (int)acc[e];
-                    if constexpr (!kInterior) k[e] = ok[e] ? k[e] : INT_MAX;
-                }
-                if constexpr (K == 1) {
-                    const int m = min(min(k[0], k[1]), min(k[2], k[3]));
-                    const bool better = m < best[t];
-                    btile[t] = better ? tile_id : btile[t];
-                    best[t] = better ? m : best[t];
-                } else {
-#pragma unroll
+        }
+        Tile ta{}, tb{};
+        int r = rlo + w, ct = ct_lo;
+        if (total > 0) ta = load_tile(r, ct);
+        auto scan_one = [&](const Tile& cur, Tile& nxt, int q) {
+            int rn = r, ctn = ct + 1;
+            if (ctn > ct_hi) {
+                ctn = ct_lo;
+                rn += kWaves;
+            }
+            if (q + 1 < total) nxt = load_tile(rn, ctn);
+            const int c0 = j0 - F + 16 * ct;
+            const int tile_id = (r << 16) | ct;
+            // every query row of the block has row r inside its box (wave-uniform)
+            const bool all_rows = i0 + kQRows - 1 < Hk && r >= i0 + kQRows - 1 - F && r <= i0 + F;
+            // Keys of one tile for every query row.  Candidates outside the image
+            // or this lane's query box get INT_MAX (above any true key); interior
+            // tiles (every candidate inside every query's box) and rows inside
+            // every query row's box skip those tests.  Both conditions are
+            // wave-uniform.
+            auto score = [&](auto interior, auto rows_in) {
+                constexpr bool kInterior = decltype(interior)::value;
+                constexpr bool kRowsIn = decltype(rows_in)::value;
+                bool ok[4] = {true, true, true, true};
+                if constexpr (!kInterior) {
+    #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        if (!__any(k[e] < tk[t][K - 1])) continue;  // wave-uniform
-                        int nk = k[e], ni = r * Wk + c0 + 4 * g + e;
-#pragma unroll
-                        for (int l = 0; l < K; ++l) {
-                            const bool lt = nk < tk[t][l];
-                            const int ok_ = tk[t][l], oi = ti[t][l];
-                            tk[t][l] = lt ? nk : ok_;
-                            ti[t][l] = lt ? ni : oi;
-                            nk = lt ? ok_ : nk;
-                            ni = lt ? oi : ni;
+                        const int jc = c0 + 4 * g + e;
+                        ok[e] = (unsigned)(jc - jq + F) <= (unsigned)(2 * F) && (unsigned)jc < (unsigned)Wk;
+                    }
+                }
+    #pragma unroll
+                for (int t = 0; t < kQRows; ++t) {
+                    if constexpr (!kRowsIn) {
+                        const int iq = i0 + t;
+                        if (iq >= Hk || r < iq - F || r > iq + F) continue;
+                    }
+                    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    #pragma unroll
+                    for (int c = 0; c < KS::N32; ++c)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(cur.a32[c], q32[t][c], acc, 0, 0, 0);
+                    if constexpr (KS::N16 > 0)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(cur.a16, q16[t], acc, 0, 0, 0);
+                    KT k[4];
+    #pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        // |b'|^2 + (-2 a'.b'), the product exact in fp32
+                        if constexpr (kFloat) {
+                            k[e] = cur.bsq[e] + acc[e];
+                        } else {
+                            k[e] = (int)cur.bsq[e] + (int)acc[e];
+                        }
+                        if constexpr (!kInterior) k[e] = ok[e] ? k[e] : kNone;
+                    }
+                    if constexpr (K == 1) {
+                        const KT m = min(min(k[0], k[1]), min(k[2], k[3]));
+                        const bool better = m < S.best[t];
+                        S.btile[t] = better ? tile_id : S.btile[t];
+                        S.best[t] = better ? m : S.best[t];
+                    } else {
+    #pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            if (!__any(k[e] < S.tk[t][K - 1])) continue;  // wave-uniform
+                            KT nk = k[e];
+                            int ni = r * Wk + c0 + 4 * g + e;
+    #pragma unroll
+                            for (int l = 0; l < K; ++l) {
+                                const bool lt = nk < S.tk[t][l];
+                                const KT ok_ = S.tk[t][l];
+                                const int oi = S.ti[t][l];
+                                S.tk[t][l] = lt ? nk : ok_;
+                                S.ti[t][l] = lt ? ni : oi;
+                                nk = lt ? ok_ : nk;
+                                ni = lt ? oi : ni;
+                            }
                         }
                     }
                 }
+            };
+            const bool interior = c0 >= 0 && c0 + 15 < Wk && c0 >= j0 + 15 - F && c0 + 15 <= j0 + F;
+            if (interior) {
+                if (all_rows)
+                    score(std::true_type{}, std::true_type{});
+                else
+                    score(std::true_type{}, std::false_type{});
+            } else {
+                if (all_rows)
+                    score(std::false_type{}, std::true_type{});
+                else
+                    score(std::false_type{}, std::false_type{});
             }
+            r = rn;
+            ct = ctn;
         };
-        const bool interior = c0 >= 0 && c0 + 15 < Wk && c0 >= j0 + 15 - F && c0 + 15 <= j0 + F;
-        if (interior) {
-            if (all_rows)
-                score(std::true_type{}, std::true_type{});
-            else
-                score(std::true_type{}, std::false_type{});
-        } else {
-            if (all_rows)
-                score(std::false_type{}, std::true_type{});
-            else
-                score(std::false_type{}, std::false_type{});
+        for (int q = 0; q < total; q += 2) {
+            scan_one(ta, tb, q);
+            if (q + 1 < total) scan_one(tb, ta, q + 1);
         }
-        r = rn;
-        ct = ctn;
     };
-    for (int q = 0; q < total; q += 2) {
-        scan_one(ta, tb, q);
-        if (q + 1 < total) scan_one(tb, ta, q + 1);
+    struct StateF {
+        float best[kQRows];
+        int btile[kQRows];
+        float tk[kQRows][K];
+        int ti[kQRows][K];
+    } SF;
+    run_scan(0.f, SF);
+    bool redo = false;
+    const float kExact = 16777216.f;  // 2^24
+#pragma unroll
+    for (int t = 0; t < kQRows; ++t) {
+        if constexpr (K == 1) redo = redo || (SF.best[t] >= kExact && SF.best[t] != __builtin_huge_valf());
+#pragma unroll
+        for (int l = 0; l < K; ++l)
+            if constexpr (K > 1) redo = redo || (SF.tk[t][l] >= kExact && SF.tk[t][l] != __builtin_huge_valf());
+    }
+    if (__syncthreads_or(redo)) {
+        struct StateI {
+            int best[kQRows];
+            int btile[kQRows];
+            int tk[kQRows][K];
+            int ti[kQRows][K];
+        } SI;
+        run_scan(0, SI);
+#pragma unroll
+        for (int t = 0; t < kQRows; ++t) {
+            best[t] = SI.best[t];
+            btile[t] = SI.btile[t];
+#pragma unroll
+            for (int l = 0; l < K; ++l) {
+                tk[t][l] = SI.tk[t][l];
+                ti[t][l] = SI.ti[t][l];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < kQRows; ++t) {
+            best[t] = SF.best[t] == __builtin_huge_valf() ? INT_MAX : (int)SF.best[t];
+            btile[t] = SF.btile[t];
+#pragma unroll
+            for (int l = 0; l < K; ++l) {
+                tk[t][l] = SF.tk[t][l] == __builtin_huge_valf() ? INT_MAX : (int)SF.tk[t][l];
+                ti[t][l] = SF.ti[t][l];
+            }
+        }
     }
     // the smallest target index of the winning tile that reaches the minimum
     // (exact bin-grid squared distances, equal to the MFMA identity's)
@@ -423,8 +491,8 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
     }
     __syncthreads();
 
-    // epipolar searches: 4 threads per query, candidates interleaved
-    const int q = threadIdx.x & 15, t = (threadIdx.x >> 4) & 3, part = threadIdx.x >> 6;
+    // epipolar searches: kParts threads per query, candidates interleaved
+    const int q = threadIdx.x & 15, t = (threadIdx.x >> 4) % kQRows, part = threadIdx.x / (16 * kQRows);
     const int iq = i0 + t, jqq = j0 + q;
     const bool live = iq < Hk && jqq < Wk;
     const int x = n * min(jqq, Wk - 1), y = n * min(iq, Hk - 1);
@@ -436,7 +504,7 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
     if (live) {
         const int txlo = s > 0 ? x - min(a.dm, x) : x;
         const int txhi = s > 0 ? x : x + min(a.dm, ((W - 1 - x) / n) * n);
-        for (int tx = txlo + n * part; tx <= txhi; tx += 4 * n) {
+        for (int tx = txlo + n * part; tx <= txhi; tx += kParts * n) {
             uint4 cg[2 * C];
             load_grid<C>(rS, addr(tx, y), cg);
             const unsigned long long k = ((unsigned long long)grid_ssd<C>(qg, cg) << 32) | (uint32_t)tx;
@@ -447,7 +515,7 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
     __syncthreads();
     unsigned long long mS = red2[0][t][q];
 #pragma unroll
-    for (int k = 1; k < 4; ++k) mS = red2[k][t][q] < mS ? red2[k][t][q] : mS;
+    for (int k = 1; k < kParts; ++k) mS = red2[k][t][q] < mS ? red2[k][t][q] : mS;
     __syncthreads();
     // cross partner of each temporal leaf on row y + v: target tx = x + u - s d1,
     // increasing tx
@@ -459,7 +527,7 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
             const int xc = x + res_u[t][q][l], yc = y + res_v[t][q][l];
             const int txlo = s > 0 ? xc - min(a.dm, xc) : xc;
             const int txhi = s > 0 ? xc : xc + min(a.dm, ((W - 1 - xc) / n) * n);
-            for (int tx = txlo + n * part; tx <= txhi; tx += 4 * n) {
+            for (int tx = txlo + n * part; tx <= txhi; tx += kParts * n) {
                 uint4 cg[2 * C];
                 load_grid<C>(rX, addr(tx, yc), cg);
                 const unsigned long long k = ((unsigned long long)grid_ssd<C>(qg, cg) << 32) | (uint32_t)tx;
@@ -479,7 +547,7 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
     for (int l = 0; l < nl; ++l) {
         unsigned long long mX = redx[l][0][t][q];
 #pragma unroll
-        for (int k = 1; k < 4; ++k) mX = redx[l][k][t][q] < mX ? redx[l][k][t][q] : mX;
+        for (int k = 1; k < kParts; ++k) mX = redx[l][k][t][q] < mX ? redx[l][k][t][q] : mX;
         const uint64_t joint = (uint64_t)res_t[t][q][l] + eS + (uint32_t)(mX >> 32);
         if (joint < bestJ) {
             bestJ = joint;
@@ -587,7 +655,7 @@ extern "C" sff_status sff_init_nn_bins(const sff_params* p, int32_t batch, int32
     P.q32 = reinterpret_cast<_Float16*>(ws + L.q32);
     P.q16 = reinterpret_cast<_Float16*>(ws + L.q16);
     P.sq = reinterpret_cast<uint32_t*>(ws + L.sq);
-    P.sqx = reinterpret_cast<uint32_t*>(ws + L.sqx);
+    P.sqx = reinterpret_cast<float*>(ws + L.sqx);
     P.nzk = L.nzk;
     P.wx = L.wx;
     P.offx = L.offx;

@@ -205,6 +205,26 @@ def test_init_bins_extreme_contrast(sff):
         assert np.array_equal(host(cost, u32=True)[di, 0], oc)
 
 
+def test_init_bins_large_keys(sff):
+    """Bright references against dark targets (views 0, 3 near 255, views 1, 2
+    near 0, small noise): every temporal key |a - b|^2 - |a'|^2 is far above
+    2^24, where fp32 keys round, so the scan must fall back to int32 keys; the
+    noise makes neighbouring keys differ by a few units."""
+    H, W, C = 24, 40, 4
+    rng = np.random.default_rng(21)
+    imgs = rng.integers(0, 4, (4, H, W, C)).astype(np.uint8)
+    imgs[0] = 255 - imgs[0]
+    imgs[3] = 255 - imgs[3]
+    p = params_dict(H, W, C, levels=1, iters=1, fmax=12, dmax=10)
+    D = _oracle_descs(imgs, 0)
+    _say("init bins large keys")
+    hyp, cost = _init(sff, p, dev(imgs), "bins", sff.DIR_BOTH)
+    for di, s in enumerate((1, -1)):
+        oh, oc = oracle.init_nn(D, 0, s, 12, 10)
+        assert np.array_equal(host(hyp)[di, 0], oh)
+        assert np.array_equal(host(cost, u32=True)[di, 0], oc)
+
+
 @pytest.mark.parametrize("maps", ["desc", "bins"])
 def test_init_nn_kitti_full(sff, maps):
     sc = make_scene(kitti_spec())
