@@ -488,6 +488,20 @@ sff_status sff_conv3x3_bf16_fwd(int32_t n, int32_t H, int32_t W, int32_t cin, in
                                 int32_t dil, int32_t relu, const uint16_t* x, const uint16_t* w,
                                 const float* bias, uint16_t* y, void* stream);
 
+/* The learned-feature network's forward pass in one launch (dilation 1):
+ * y = conv4(relu(conv3(relu(conv2(relu(conv1(x))))))), conv1 3 -> 32, conv2..4
+ * 32 -> 32, each a 3x3 convolution as sff_conv3x3_bf16_fwd computes it
+ * (weights w_l [32][3][3][cin], bias b_l [32] FP32 or NULL, zero padding),
+ * the activations between layers kept on chip.  x [n][H][W][3], y
+ * [n][H][W][32], BF16 bits.  Bit-identical to the four sff_conv3x3_bf16_fwd
+ * calls (each layer's output rounded to BF16 the same way).  y 8-byte aligned,
+ * w1..w3 16-byte aligned.  Errors: SFF_ERR_INVALID_ARG (shapes, NULL pointers,
+ * alignment), SFF_ERR_UNSUPPORTED (dil != 1: use the per-layer calls). */
+sff_status sff_featnet_fwd_bf16(int32_t n, int32_t H, int32_t W, int32_t dil, const uint16_t* x,
+                                const uint16_t* w0, const float* b0, const uint16_t* w1,
+                                const float* b1, const uint16_t* w2, const float* b2,
+                                const uint16_t* w3, const float* b3, uint16_t* y, void* stream);
+
 /* Device workspace (bytes) for sff_conv3x3_bf16_dgrad / _wgrad. */
 size_t sff_conv3x3_bf16_bwd_workspace_bytes(int32_t n, int32_t H, int32_t W, int32_t cin,
                                             int32_t cout);

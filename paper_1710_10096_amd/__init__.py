@@ -12,7 +12,7 @@ from .api import (DIR_BOTH, DIR_FORWARD, DIR_INVERSE,  # noqa: F401
                   sff_sift_workspace_bytes, sff_dense_sift, sff_sift_pca, sff_cost_sift, sff_match_sift, sff_sift_sqrt,
                   sff_version, sff_wht_features, sff_wht_workspace_bytes)
 from .api import (MatchCost, sff_cost_f32_bwd, sff_cost_f32_bwd_workspace_bytes,  # noqa: F401
-                  sff_cost_f32_fwd, sff_conv3x3_bf16_fwd, sff_conv3x3_bf16_dgrad,
+                  sff_cost_f32_fwd, sff_conv3x3_bf16_fwd, sff_featnet_fwd_bf16, sff_conv3x3_bf16_dgrad,
                   sff_conv3x3_bf16_wgrad, sff_smooth_level, sff_quantise_features,
                   sff_triplet_loss, sff_take_grad_bf16)
 from .pipeline import PairMatcher, match_pairs  # noqa: F401

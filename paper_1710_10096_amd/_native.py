@@ -35,7 +35,8 @@ EXPORTS = ("sff_status_string", "sff_version", "sff_desc_channels", "sff_lanczos
            "sff_sift_workspace_bytes", "sff_dense_sift", "sff_sift_pca", "sff_cost_sift",
            "sff_match_sift", "sff_sift_sqrt",
            "sff_cost_f32_fwd", "sff_cost_f32_bwd_workspace_bytes",
-           "sff_cost_f32_bwd", "sff_conv3x3_bf16_fwd", "sff_conv3x3_bf16_bwd_workspace_bytes",
+           "sff_cost_f32_bwd", "sff_conv3x3_bf16_fwd", "sff_featnet_fwd_bf16",
+           "sff_conv3x3_bf16_bwd_workspace_bytes",
            "sff_conv3x3_bf16_dgrad", "sff_conv3x3_bf16_wgrad", "sff_smooth_level",
            "sff_quantise_features", "sff_triplet_loss", "sff_take_grad_bf16", "sff_probe_copy",
            "sff_probe_gather")
@@ -120,6 +121,8 @@ def lib() -> ctypes.CDLL:
     L.sff_cost_f32_bwd.restype = i32
     L.sff_conv3x3_bf16_fwd.argtypes = [i32] * 7 + [P, P, P, P, P]
     L.sff_conv3x3_bf16_fwd.restype = i32
+    L.sff_featnet_fwd_bf16.argtypes = [i32] * 4 + [P] * 11
+    L.sff_featnet_fwd_bf16.restype = i32
     L.sff_conv3x3_bf16_bwd_workspace_bytes.argtypes = [i32] * 5
     L.sff_conv3x3_bf16_bwd_workspace_bytes.restype = ctypes.c_size_t
     L.sff_conv3x3_bf16_dgrad.argtypes = [i32] * 6 + [P, P, P, P, P, ctypes.c_size_t, P]

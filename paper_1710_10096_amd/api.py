@@ -529,6 +529,24 @@ def sff_conv3x3_bf16_fwd(x: torch.Tensor, w: torch.Tensor, bias: torch.Tensor | 
     return y
 
 
+def sff_featnet_fwd_bf16(x: torch.Tensor, ws, bs, dil: int = 1, y=None, stream=None):
+    """The four-layer network in one launch: x bf16 [n][H][W][3], ws four bf16
+    weight tensors ([32][3][3][3], then [32][3][3][32]), bs four f32 biases (or
+    None) -> y bf16 [n][H][W][32]."""
+    n, H, W, cin = x.shape
+    if cin != 3 or len(ws) != 4 or len(bs) != 4:
+        raise ValueError("x must have 3 channels; four weights and four biases")
+    if y is None:
+        y = torch.empty((n, H, W, 32), dtype=torch.bfloat16, device=x.device)
+    args = []
+    for w, b in zip(ws, bs):
+        args += [_ptr(w, torch.bfloat16, "w"), _ptr(b, torch.float32, "bias")]
+    _check(lib().sff_featnet_fwd_bf16(n, H, W, dil, _ptr(x, torch.bfloat16, "x"), *args,
+                                      _ptr(y, torch.bfloat16, "y"), _stream(stream)),
+           "sff_featnet_fwd_bf16")
+    return y
+
+
 def _conv_ws(n, H, W, cin, cout, device, workspace):
     if workspace is not None:
         return workspace

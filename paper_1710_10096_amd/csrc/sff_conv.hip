@@ -27,11 +27,12 @@ typedef uint16_t bf16_t;  // raw bfloat16 bits in memory
 
 __device__ __forceinline__ float bf2f(bf16_t v) { return __uint_as_float((uint32_t)v << 16); }
 
-// round to nearest even
+// round to nearest even (infinities kept, NaNs kept quiet); selects, no branch
 __device__ __forceinline__ bf16_t f2bf(float f) {
     const uint32_t u = __float_as_uint(f);
-    if ((u & 0x7F800000u) == 0x7F800000u) return (bf16_t)((u >> 16) | ((u & 0xFFFF) ? 0x40 : 0));
-    return (bf16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    const uint32_t special = (u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u);
+    const uint32_t rounded = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    return (bf16_t)((u & 0x7F800000u) == 0x7F800000u ? special : rounded);
 }
 
 constexpr int kTilePx = 64;  // output pixels per block (one row segment)
@@ -499,6 +500,184 @@ bool staged_conv_enabled() {
     return !(e && std::strcmp(e, "1") == 0);
 }
 
+// ------------------------------------------------------- fused 4 layers --
+// The whole network (3 -> 32 -> 32 -> 32 -> 32, ReLU after the first three,
+// dilation 1) for one kFusedY x kFusedX output tile per block, the layers'
+// activations kept in LDS: layer l is computed on the tile grown by 3 - l
+// pixels on every side (its inputs' halo), from the LDS region the layer
+// before it left there; only the three-channel input is read from and the
+// 32-channel output written to HBM.  Positions outside the image are stored
+// as zeros (the zero padding the next layer reads), every layer's output is
+// rounded to BF16 as the per-layer kernels store it, and each output element
+// is the same MFMAs in the same order on the same values as conv3_fwd_kernel
+// and conv32_fwd_kernel, so the results are identical (tested).
+constexpr int kFusedX = 64, kFusedY = 8;
+constexpr int kFIn[2] = {kFusedY + 8, kFusedX + 8};   // input region (3 channels, packed)
+constexpr int kF1[2] = {kFusedY + 6, kFusedX + 6};    // layer-1 output (and layer 3's, in place later)
+constexpr int kF2[2] = {kFusedY + 4, kFusedX + 4};    // layer-2 output
+constexpr int kFPx = 40;                              // bf16 per staged pixel (32 used): 80-byte stride
+
+// This lane's biases: output channels 16 t + 4 (l / 16) + e (zero without bias).
+__device__ __forceinline__ void fused_bias(const float* __restrict__ bias, float (&bz)[2][4]) {
+    const int g = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bz[t][e] = bias ? bias[t * 16 + 4 * g + e] : 0.f;
+}
+
+// Round acc + bias, ReLU, to BF16 pairs for output channels 16 t + 4 g .. + 3.
+__device__ __forceinline__ uint2 fused_pack(const v4f& acc, const float (&bz)[4], bool relu) {
+    uint32_t packed[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        float v0 = acc[2 * h] + bz[2 * h];
+        float v1 = acc[2 * h + 1] + bz[2 * h + 1];
+        if (relu) {
+            v0 = fmaxf(v0, 0.f);
+            v1 = fmaxf(v1, 0.f);
+        }
+        packed[h] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+    }
+    return make_uint2(packed[0], packed[1]);
+}
+
+// The 18 weight fragments of a 32 -> 32 layer for this lane: output channel
+// 16 t + l % 16, tap, input channels 8 (l / 16) .. + 7.
+__device__ __forceinline__ void fused_weights(const bf16_t* __restrict__ w, v8bf (&a)[2][9]) {
+    const int lane = threadIdx.x & 63, ln = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+            a[t][tap] = *reinterpret_cast<const v8bf*>(w + ((size_t)(t * 16 + ln) * 9 + tap) * 32 + 8 * g);
+}
+
+// One 32 -> 32 layer from LDS region `in` (OH + 2) x (OW + 2) to region `out`
+// OH x OW (or, for the last layer, to y), the region's pixel (0, 0) at image
+// (oy, ox).  Work items are (row, 16-pixel group), dealt to the 8 waves, two
+// at a time per wave (four independent accumulator chains in flight).
+template <int OH, int OW, bool LAST>
+__device__ __forceinline__ void fused_layer32(const bf16_t* in, bf16_t* out, const v8bf (&a)[2][9],
+                                              const float (&bz)[2][4], bool relu, int oy, int ox,
+                                              int H, int W, bf16_t* __restrict__ y, size_t img) {
+    constexpr int IW = OW + 2, NG = (OW + 15) / 16, NI = OH * NG;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ln = lane & 15, g = lane >> 4;
+    for (int i0 = wv; i0 < NI; i0 += 16) {
+        int r[2], p[2];
+        v4f acc[2][2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int item = min(i0 + 8 * h, NI - 1);  // a missing second item repeats the last
+            r[h] = item / NG;
+            p[h] = (item - r[h] * NG) * 16 + ln;
+            acc[h][0] = v4f{0.f, 0.f, 0.f, 0.f};
+            acc[h][1] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int ky = tap / 3, kx = tap - 3 * ky;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int pr = min(p[h], OW - 1);  // lanes past the row read a valid pixel
+                const v8bf bv = *reinterpret_cast<const v8bf*>(in + ((r[h] + ky) * IW + pr + kx) * kFPx + 8 * g);
+                acc[h][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][tap], bv, acc[h][0], 0, 0, 0);
+                acc[h][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][tap], bv, acc[h][1], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (p[h] >= OW || (h == 1 && i0 + 8 >= NI)) continue;
+            const int iy = oy + r[h], ix = ox + p[h];
+            const bool inside = iy >= 0 && iy < H && ix >= 0 && ix < W;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const uint2 v = inside ? fused_pack(acc[h][t], bz[t], relu) : make_uint2(0u, 0u);
+                if constexpr (LAST) {
+                    if (inside) *reinterpret_cast<uint2*>(y + (img + (size_t)iy * W + ix) * 32 + t * 16 + 4 * g) = v;
+                } else {
+                    *reinterpret_cast<uint2*>(out + (r[h] * OW + p[h]) * kFPx + t * 16 + 4 * g) = v;
+                }
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(512) featnet_fwd_kernel(const bf16_t* __restrict__ x,
+                                                          const bf16_t* __restrict__ w0, const float* __restrict__ b0,
+                                                          const bf16_t* __restrict__ w1, const float* __restrict__ b1,
+                                                          const bf16_t* __restrict__ w2, const float* __restrict__ b2,
+                                                          const bf16_t* __restrict__ w3, const float* __restrict__ b3,
+                                                          bf16_t* __restrict__ y, int H, int W) {
+    __shared__ __align__(16) bf16_t xin[kFIn[0] * kFIn[1] * 3];
+    __shared__ __align__(16) bf16_t bufA[kF1[0] * kF1[1] * kFPx];
+    __shared__ __align__(16) bf16_t bufB[kF2[0] * kF2[1] * kFPx];
+    const int x0 = blockIdx.x * kFusedX, y0 = blockIdx.y * kFusedY, n = blockIdx.z;
+    const size_t img = (size_t)n * H * W;
+    v8bf wa[2][9];
+    float bz0[2][4], bz[2][4];
+    fused_weights(w1, wa);  // layer 2's, in flight during the staging and layer 1
+    fused_bias(b0, bz0);
+    fused_bias(b1, bz);
+    // input region: image rows y0 - 4 .., columns x0 - 4 .., zero outside
+    for (int e = threadIdx.x; e < kFIn[0] * kFIn[1] * 3; e += 512) {
+        const int px = e / 3, ci = e - 3 * px, r = px / kFIn[1], c = px - r * kFIn[1];
+        const int iy = y0 - 4 + r, ix = x0 - 4 + c;
+        xin[e] = (iy >= 0 && iy < H && ix >= 0 && ix < W) ? x[(img + (size_t)iy * W + ix) * 3 + ci] : (bf16_t)0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ln = lane & 15, g = lane >> 4;
+    // layer 1 (3 -> 32, K = 27 in one MFMA step) into bufA: kF1 region at image (y0 - 3, x0 - 3)
+    {
+        v8bf a[2];
+        int koff[8];  // offset of K value 8 g + e from the lane's pixel in xin (-1: zero padding)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 8 * g + e;
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                a[t][e] = __builtin_bit_cast(__bf16, k < 27 ? w0[(size_t)(t * 16 + ln) * 27 + k] : (bf16_t)0);
+            const int tap = k / 3, ci = k - 3 * tap, ky = tap / 3, kx = tap - 3 * ky;
+            koff[e] = k < 27 ? (ky * kFIn[1] + kx) * 3 + ci : -1;
+        }
+        constexpr int NG = (kF1[1] + 15) / 16;
+        for (int item = wv; item < kF1[0] * NG; item += 8) {
+            const int r = item / NG, p = (item - r * NG) * 16 + ln;
+            const int pr = min(p, kF1[1] - 1);
+            const bf16_t* src = xin + (r * kFIn[1] + pr) * 3;
+            v8bf bv;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bv[e] = __builtin_bit_cast(__bf16, koff[e] >= 0 ? src[koff[e]] : (bf16_t)0);
+            v4f acc[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], bv, v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            if (p >= kF1[1]) continue;
+            const int iy = y0 - 3 + r, ix = x0 - 3 + p;
+            const bool inside = iy >= 0 && iy < H && ix >= 0 && ix < W;
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                *reinterpret_cast<uint2*>(bufA + (r * kF1[1] + p) * kFPx + t * 16 + 4 * g) =
+                    inside ? fused_pack(acc[t], bz0[t], true) : make_uint2(0u, 0u);
+        }
+    }
+    __syncthreads();
+    // the next layer's weight fragments are loaded while this one computes
+    v8bf wb[2][9];
+    float bz2[2][4];
+    fused_weights(w2, wb);
+    fused_bias(b2, bz2);
+    fused_layer32<kF2[0], kF2[1], false>(bufA, bufB, wa, bz, true, y0 - 2, x0 - 2, H, W, nullptr, img);
+    __syncthreads();
+    fused_weights(w3, wa);
+    fused_bias(b3, bz);
+    fused_layer32<kFusedY + 2, kFusedX + 2, false>(bufB, bufA, wb, bz2, true, y0 - 1, x0 - 1, H, W, nullptr, img);
+    __syncthreads();
+    fused_layer32<kFusedY, kFusedX, true>(bufA, nullptr, wa, bz, false, y0, x0, H, W, y, img);
+}
+
 bool use_conv32(const void* x, const void* mask) {
     if ((reinterpret_cast<uintptr_t>(x) & 15) != 0 || (reinterpret_cast<uintptr_t>(mask) & 15) != 0) return false;
     return staged_conv_enabled();
@@ -593,5 +772,21 @@ extern "C" sff_status sff_conv3x3_bf16_wgrad(int32_t n, int32_t H, int32_t W, in
     const int cpad = (cin + 15) / 16 * 16;
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((cout * 9 * cin + cout + kRedOut - 1) / kRedOut), dim3(256), 0,
                        st, part, dw, db, nblk, cin, cout, cpad);
+    return launch_status();
+}
+
+extern "C" sff_status sff_featnet_fwd_bf16(int32_t n, int32_t H, int32_t W, int32_t dil,
+                                           const uint16_t* x, const uint16_t* w0, const float* b0,
+                                           const uint16_t* w1, const float* b1, const uint16_t* w2,
+                                           const float* b2, const uint16_t* w3, const float* b3,
+                                           uint16_t* y, void* stream) {
+    if (!conv_shape_ok(n, H, W, 3, 32, dil) || !x || !w0 || !w1 || !w2 || !w3 || !y)
+        return SFF_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(y) & 7) != 0 || (reinterpret_cast<uintptr_t>(w1) & 15) != 0 ||
+        (reinterpret_cast<uintptr_t>(w2) & 15) != 0 || (reinterpret_cast<uintptr_t>(w3) & 15) != 0)
+        return SFF_ERR_INVALID_ARG;
+    if (dil != 1) return SFF_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(featnet_fwd_kernel, dim3((W + kFusedX - 1) / kFusedX, (H + kFusedY - 1) / kFusedY, n),
+                       dim3(512), 0, as_stream(stream), x, w0, b0, w1, b1, w2, b2, w3, b3, y, H, W);
     return launch_status();
 }

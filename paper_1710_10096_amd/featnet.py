@@ -45,8 +45,12 @@ class FeatNet:
         return [self.params[2 * l].to(torch.bfloat16).contiguous() for l in range(4)]
 
     def forward(self, x: torch.Tensor, dil: int = 1, keep: bool = False, wb=None):
-        """x bf16 [n][H][W][3] -> bf16 [n][H][W][32] (and the activations)."""
+        """x bf16 [n][H][W][3] -> bf16 [n][H][W][32] (and the activations).
+        Without `keep`, at dilation 1, the four layers run as one launch with the
+        activations on chip (same bits as the per-layer calls)."""
         wb = wb if wb is not None else self.weights_bf16()
+        if not keep and dil == 1:
+            return api.sff_featnet_fwd_bf16(x, wb, [self.params[2 * l + 1] for l in range(4)])
         acts = [x]
         h = x
         for l in range(4):

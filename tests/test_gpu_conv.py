@@ -159,3 +159,36 @@ def test_first_layer_kernel_same_as_im2col(sff, case, monkeypatch):
     ref = ofn.bf16_round(ofn.conv3x3(x, w, b.astype(np.float64), dil, True))
     S = ofn.conv3x3(np.abs(x), np.abs(w), np.abs(b.astype(np.float64)), dil)
     assert _within_bf16_ulp(_np(y), ref, S).all()
+
+
+FUSED_CASES = [(1, 1, 1), (2, 9, 70), (1, 8, 64), (1, 17, 131), (3, 23, 200), (1, 40, 270)]
+
+
+@pytest.mark.parametrize("case", FUSED_CASES, ids=[str(c) for c in FUSED_CASES])
+def test_fused_network_forward_same_as_layers(sff, case):
+    """The four layers in one launch (activations on chip, tiles of 8 x 64
+    outputs, ragged edges) against the four per-layer calls, bit for bit;
+    the last layer against the FP64 oracle on the per-layer path's layer-3
+    output."""
+    import torch
+    n, H, W = case
+    rng = np.random.default_rng(H * 7 + W + n)
+    x = ofn.bf16_round(rng.standard_normal((n, H, W, 3)) * 2.0)
+    ws, bs = [], []
+    for cin in (3, 32, 32, 32):
+        ws.append(ofn.bf16_round(rng.standard_normal((32, 3, 3, cin)) / np.sqrt(9 * cin)))
+        bs.append(rng.standard_normal(32).astype(np.float32).astype(np.float64) * 0.1)
+    wt = [_bf(w) for w in ws]
+    bt = [torch.from_numpy(b.astype(np.float32)).cuda() for b in bs]
+    _say("fused network", case)
+    y = sff.sff_featnet_fwd_bf16(_bf(x), wt, bt)
+    h = _bf(x)
+    acts = []
+    for l in range(4):
+        h = sff.sff_conv3x3_bf16_fwd(h, wt[l], bt[l], 1, l < 3)
+        acts.append(h)
+    assert np.array_equal(_np(y), _np(h))
+    x3 = _np(acts[2])
+    ref = ofn.bf16_round(ofn.conv3x3(x3, ws[3], bs[3], 1, False))
+    S = ofn.conv3x3(np.abs(x3), np.abs(ws[3]), np.abs(bs[3]), 1)
+    assert _within_bf16_ulp(_np(y), ref, S).all()
