@@ -27,13 +27,9 @@ typedef uint16_t bf16_t;  // raw bfloat16 bits in memory
 
 __device__ __forceinline__ float bf2f(bf16_t v) { return __uint_as_float((uint32_t)v << 16); }
 
-// round to nearest even (infinities kept, NaNs kept quiet); selects, no branch
-__device__ __forceinline__ bf16_t f2bf(float f) {
-    const uint32_t u = __float_as_uint(f);
-    const uint32_t special = (u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u);
-    const uint32_t rounded = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-    return (bf16_t)((u & 0x7F800000u) == 0x7F800000u ? special : rounded);
-}
+// round to nearest even: the conversion instruction of gfx950
+// (v_cvt_pk_bf16_f32; infinities kept, NaNs quiet)
+__device__ __forceinline__ bf16_t f2bf(float f) { return __builtin_bit_cast(bf16_t, (__bf16)f); }
 
 constexpr int kTilePx = 64;  // output pixels per block (one row segment)
 constexpr int kMaxDil = 16;  // largest dilation
