@@ -31,6 +31,13 @@ __device__ __forceinline__ float bf2f(bf16_t v) { return __uint_as_float((uint32
 // (v_cvt_pk_bf16_f32; infinities kept, NaNs quiet)
 __device__ __forceinline__ bf16_t f2bf(float f) { return __builtin_bit_cast(bf16_t, (__bf16)f); }
 
+// Two values rounded the same way, packed (lo, hi) in one conversion.
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){lo, hi}, v2bf));
+}
+
 constexpr int kTilePx = 64;  // output pixels per block (one row segment)
 constexpr int kMaxDil = 16;  // largest dilation
 
@@ -99,7 +106,7 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(const bf16_t* __restrict_
                 v0 = fmaxf(v0, 0.f);
                 v1 = fmaxf(v1, 0.f);
             }
-            packed[h] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+            packed[h] = f2bf2(v0, v1);
         }
         *reinterpret_cast<uint2*>(out + t * 16 + 4 * g) = make_uint2(packed[0], packed[1]);
     }
@@ -193,7 +200,7 @@ __global__ void __launch_bounds__(256) conv32_fwd_kernel(const bf16_t* __restric
                             v0 = fmaxf(v0, 0.f);
                             v1 = fmaxf(v1, 0.f);
                         }
-                        packed[h] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+                        packed[h] = f2bf2(v0, v1);
                     }
                     *reinterpret_cast<uint2*>(out + t * 16 + 4 * g) = make_uint2(packed[0], packed[1]);
                 }
@@ -266,7 +273,7 @@ __global__ void __launch_bounds__(256) conv3_fwd_kernel(const bf16_t* __restrict
                             v0 = fmaxf(v0, 0.f);
                             v1 = fmaxf(v1, 0.f);
                         }
-                        packed[h] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+                        packed[h] = f2bf2(v0, v1);
                     }
                     *reinterpret_cast<uint2*>(out + t * 16 + 4 * g) = make_uint2(packed[0], packed[1]);
                 }
@@ -533,7 +540,7 @@ __device__ __forceinline__ uint2 fused_pack(const v4f& acc, const float (&bz)[4]
             v0 = fmaxf(v0, 0.f);
             v1 = fmaxf(v1, 0.f);
         }
-        packed[h] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+        packed[h] = f2bf2(v0, v1);
     }
     return make_uint2(packed[0], packed[1]);
 }
@@ -558,16 +565,21 @@ __device__ __forceinline__ void fused_layer32(const bf16_t* in, bf16_t* out, con
                                               const float (&bz)[2][4], bool relu, int oy, int ox,
                                               int H, int W, bf16_t* __restrict__ y, size_t img) {
     constexpr int IW = OW + 2, NG = (OW + 15) / 16, NI = OH * NG;
+    typedef const v8bf __attribute__((address_space(3)))* lds_v8;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ln = lane & 15, g = lane >> 4;
     for (int i0 = wv; i0 < NI; i0 += 16) {
         int r[2], p[2];
+        lds_v8 src[2];
         v4f acc[2][2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int item = min(i0 + 8 * h, NI - 1);  // a missing second item repeats the last
             r[h] = item / NG;
             p[h] = (item - r[h] * NG) * 16 + ln;
+            const int pr = min(p[h], OW - 1);  // lanes past the row read a valid pixel
+            // 32-bit LDS addresses; the taps are constant offsets from the lane's first one
+            src[h] = (lds_v8)((const __attribute__((address_space(3))) bf16_t*)in + (r[h] * IW + pr) * kFPx + 8 * g);
             acc[h][0] = v4f{0.f, 0.f, 0.f, 0.f};
             acc[h][1] = v4f{0.f, 0.f, 0.f, 0.f};
         }
@@ -576,8 +588,7 @@ __device__ __forceinline__ void fused_layer32(const bf16_t* in, bf16_t* out, con
             const int ky = tap / 3, kx = tap - 3 * ky;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int pr = min(p[h], OW - 1);  // lanes past the row read a valid pixel
-                const v8bf bv = *reinterpret_cast<const v8bf*>(in + ((r[h] + ky) * IW + pr + kx) * kFPx + 8 * g);
+                const v8bf bv = src[h][(ky * IW + kx) * kFPx / 8];
                 acc[h][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][tap], bv, acc[h][0], 0, 0, 0);
                 acc[h][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][tap], bv, acc[h][1], 0, 0, 0);
             }
