@@ -277,47 +277,89 @@ void launch_smooth(const sff_params& p, int nimg, int level, const uint8_t* img,
                        dim3(256), 0, st, A, S, H, W, C, g.n, g.Hk, g.Wk, T);
 }
 
-// Bin-sum planes (layout in BinGeom): one thread per extended position
-// (ex, ey), so a wave reads consecutive source pixels; its bin goes to slot i
-// of entry (ey / P - i, ex / P) of plane (ey mod P, ex mod P), i = 0..3.
+// Bin-sum planes (layout in BinGeom), by tiles: a block takes the entries of
+// entry rows r0 .. r0 + R - 1 and entry columns q0 .. q0 + Q - 1 of every plane.
+// It first forms in LDS the bins of the extended rows those entries span,
+// (R + 3) P of them, over the tile's kQP = Q P extended columns (each bin the
+// 2x2 sum of samples n apart, clamped to the image), then writes the entries
+// as the contiguous runs they are in memory (plane, row r: Q entries), 8 bytes
+// per lane: consecutive lanes write consecutive words, so the stores are whole
+// lines instead of the 2-byte pieces of every entry's four slots.
+constexpr int kBinTileBins = 4864;  // bins staged per block: (R + 3) P kQP
+__host__ __device__ constexpr int bin_tile_qp(int P) { return P * P >= 256 ? P : 256 / P; }
+__host__ __device__ constexpr int bin_tile_rows(int P) { return kBinTileBins / (P * bin_tile_qp(P)) - 3; }
+
 template <int C>
-__global__ void __launch_bounds__(256) bins_kernel(const uint8_t* __restrict__ S,
-                                                   uint16_t* __restrict__ bins, int H, int W, int n,
-                                                   int sh, int Hq, int Wq) {
-    const int P = 1 << sh;
-    const int ex = blockIdx.x * blockDim.x + threadIdx.x, ey = blockIdx.y, m = blockIdx.z;
-    if (ex >= P * Wq) return;
-    const int X0 = ex - 3 * n, Y0 = ey - 3 * n;
-    const int x0 = clampi(X0, 0, W - 1), x1 = clampi(X0 + n, 0, W - 1);
-    const int y0 = clampi(Y0, 0, H - 1), y1 = clampi(Y0 + n, 0, H - 1);
+__global__ void __launch_bounds__(256) bins_tile_kernel(const uint8_t* __restrict__ S,
+                                                        uint16_t* __restrict__ bins, int H, int W,
+                                                        int n, int sh, int Hq, int Wq) {
+    __shared__ uint16_t lb[kBinTileBins * C];
+    const int P = 1 << sh, QP = bin_tile_qp(P), R = bin_tile_rows(P), Q = QP / P;
+    const int lqp = __builtin_ctz(QP);  // QP is a power of two
+    const int q0 = blockIdx.x * Q, r0 = blockIdx.y * R, m = blockIdx.z;
     const uint8_t* src = S + (size_t)m * H * W * C;
-    const uint8_t* r0 = src + (size_t)y0 * W * C;
-    const uint8_t* r1 = src + (size_t)y1 * W * C;
-    uint16_t v[C];
+    // bins of extended rows r0 P .. (r0 + R + 3) P - 1, columns q0 P .. q0 P + QP - 1
+    const int nb = (R + 3) * P * QP;
+#pragma unroll 4
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        const int ly = b >> lqp, lx = b & (QP - 1);
+        const int X0 = q0 * P + lx - 3 * n, Y0 = r0 * P + ly - 3 * n;
+        const int x0 = clampi(X0, 0, W - 1), x1 = clampi(X0 + n, 0, W - 1);
+        const int y0 = clampi(Y0, 0, H - 1), y1 = clampi(Y0 + n, 0, H - 1);
+        const uint8_t* s0 = src + (size_t)y0 * W * C;
+        const uint8_t* s1 = src + (size_t)y1 * W * C;
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-        v[c] = (uint16_t)((int)r0[x0 * C + c] + (int)r0[x1 * C + c] + (int)r1[x0 * C + c] +
-                          (int)r1[x1 * C + c]);
-    const int plane = ((ey & (P - 1)) << sh) + (ex & (P - 1));
+        for (int c = 0; c < C; ++c)
+            lb[b * C + c] = (uint16_t)((int)s0[x0 * C + c] + (int)s0[x1 * C + c] + (int)s1[x0 * C + c] +
+                                       (int)s1[x1 * C + c]);
+    }
+    __syncthreads();
+    // entry (r, q) of plane (py, px): slot t holds the bins of extended row
+    // (r + t) P + py at extended column q P + px; an entry is C words of 8 bytes
+    // (four uint16 each, slot-major then channel).  A run (plane, row) is nq C
+    // consecutive words; the block's threads take runs_per_pass runs at a time.
+    const int nq = min(Q, Wq - q0), nr = min(R, Hq - r0);
+    const int words_run = nq * C;
+    const int runs_per_pass = max(1, 256 / words_run);
+    const int k = (int)threadIdx.x % words_run, rsub = (int)threadIdx.x / words_run;
+    const int e = k / C, j = k - e * C;  // entry within the run, word within the entry
+    const int nruns = P * P * nr;
+    uint2* out = reinterpret_cast<uint2*>(bins);
+    if (rsub < runs_per_pass && k < words_run) {
+        int plane = 0, rr = rsub;  // run = plane * nr + rr, advanced by runs_per_pass
+        while (rr >= nr) {
+            rr -= nr;
+            ++plane;
+        }
+        for (int run = rsub; run < nruns; run += runs_per_pass) {
+            const int py = plane >> sh, px = plane & (P - 1);
+            uint32_t v[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = (ey >> sh) - i;
-        if (r < 0 || r >= Hq) continue;
-        uint16_t* o = bins + (((((size_t)m * P * P + plane) * Hq + r) * Wq + (ex >> sh)) * 4 + i) * C;
-#pragma unroll
-        for (int c = 0; c < C; ++c) o[c] = v[c];
+            for (int u = 0; u < 4; ++u) {
+                const int t = 4 * j + u, slot = t / C, c = t - slot * C;
+                v[u] = lb[((((rr + slot) * P + py) << lqp) + e * P + px) * C + c];
+            }
+            const size_t o = ((((size_t)m * P * P + plane) * Hq + (r0 + rr)) * Wq + q0 + e) * C + j;
+            out[o] = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
+            rr += runs_per_pass;
+            while (rr >= nr) {
+                rr -= nr;
+                ++plane;
+            }
+        }
     }
 }
 
 void launch_bins(const sff_params& p, int nimg, int level, const uint8_t* S, uint16_t* bins,
                  hipStream_t st) {
     const BinGeom g = bin_geom(p, level);
-    const dim3 grid((g.P * g.Wq + 255) / 256, g.P * (g.Hq + 3), nimg);
+    const int QP = bin_tile_qp(g.P), R = bin_tile_rows(g.P), Q = QP / g.P;
+    const dim3 grid((g.Wq + Q - 1) / Q, (g.Hq + R - 1) / R, nimg);
     switch (p.C) {
-        case 1: hipLaunchKernelGGL(bins_kernel<1>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
-        case 2: hipLaunchKernelGGL(bins_kernel<2>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
-        case 3: hipLaunchKernelGGL(bins_kernel<3>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
-        default: hipLaunchKernelGGL(bins_kernel<4>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
+        case 1: hipLaunchKernelGGL(bins_tile_kernel<1>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
+        case 2: hipLaunchKernelGGL(bins_tile_kernel<2>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
+        case 3: hipLaunchKernelGGL(bins_tile_kernel<3>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
+        default: hipLaunchKernelGGL(bins_tile_kernel<4>, grid, dim3(256), 0, st, S, bins, p.H, p.W, g.n, g.sh, g.Hq, g.Wq); break;
     }
 }
 
