@@ -77,8 +77,8 @@ __global__ void area_kernel(const uint8_t* __restrict__ img, uint8_t* __restrict
                 s += src[((size_t)y * W + x) * C + c];
             }
         }
-        const int nn = n * n;
-        A[(((size_t)m * Hk + i) * Wk + j) * C + c] = (uint8_t)((s + nn / 2) / nn);
+        const int nn = n * n;  // a power of two: the rounded mean by a shift
+        A[(((size_t)m * Hk + i) * Wk + j) * C + c] = (uint8_t)((s + nn / 2) >> (2 * __builtin_ctz(n)));
     }
 }
 
@@ -100,10 +100,11 @@ __global__ void __launch_bounds__(256) lanczos_hv_kernel(const uint8_t* __restri
     const int y0 = blockIdx.y * kBandRows, m = blockIdx.z;
     const int y1 = min(y0 + kBandRows, H);
     // vertical taps of rows y0..y1-1 reach block-mean rows y/n - 3 .. y/n + 3
-    const int ilo = y0 / n - 3, ihi = (y1 - 1) / n + 3;
+    const int ln = __builtin_ctz(n);  // n is a power of two: phases and blocks by masks and shifts
+    const int ilo = (y0 >> ln) - 3, ihi = ((y1 - 1) >> ln) + 3;
     const bool live = xc < W * C;
     const int x = live ? xc / C : 0, c = xc - x * C;
-    const int ph = x % n, jh = x / n + T.base[ph];
+    const int ph = x & (n - 1), jh = (x >> ln) + T.base[ph];
     const uint8_t* Am = A + (size_t)m * Hk * Wk * C;
     for (int r = 0; r <= ihi - ilo; ++r) {
         const uint8_t* row = Am + (size_t)clampi(ilo + r, 0, Hk - 1) * Wk * C;
@@ -114,7 +115,7 @@ __global__ void __launch_bounds__(256) lanczos_hv_kernel(const uint8_t* __restri
     }
     if (!live) return;  // no barrier follows: each thread reads only its own column
     for (int y = y0; y < y1; ++y) {
-        const int pv = y % n, ib = y / n + T.base[pv] - ilo;
+        const int pv = y & (n - 1), ib = (y >> ln) + T.base[pv] - ilo;
         int acc = 8192;
 #pragma unroll
         for (int t = 0; t < 6; ++t) acc += T.w[pv][t] * hb[ib + t][threadIdx.x];
