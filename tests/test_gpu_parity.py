@@ -112,7 +112,9 @@ def _bins_expected(S, level):
 
 
 BIN_CASES = [("ragged_c3", 37, 53, 3, 3), ("c1_l2", 29, 71, 1, 3), ("c2", 20, 24, 2, 2),
-             ("c4", 13, 40, 4, 2), ("one_pixel", 1, 1, 3, 2)]
+             ("c4", 13, 40, 4, 2), ("one_pixel", 1, 1, 3, 2),
+             # every tile shape of the plane kernel (P = 2 .. 32), several tiles a level
+             ("c1_l5", 40, 300, 1, 5), ("c2_l4", 70, 150, 2, 4)]
 
 
 @pytest.mark.parametrize("case", BIN_CASES, ids=[c[0] for c in BIN_CASES])
