@@ -27,7 +27,7 @@
  *    Cp = sff_desc_channels(C) = 1, 2, 4, 4 for C = 1..4: each pixel's record
  *    is padded to 32, 64 or 128 bytes so that it never straddles a 128-byte
  *    cache line.  Channels C..Cp-1 are never written nor read by the library.
- *  - bins   uint16 level-k bin-sum planes, sff_bin_bytes(p, k) bytes per image:
+ *  - bins   level-k bin-sum planes, sff_bin_bytes(p, k) bytes per image:
  *    the 2 x 2-bin sums the WHT descriptors are formed from.  The descriptor
  *    block is the 4-point Hadamard transform (both axes) of a pixel's 4 x 4
  *    grid of bin sums, so descriptor squared distances are exactly 16 times
@@ -37,10 +37,12 @@
  *    ((W - 1) / P + 4) rounded up to a multiple of 16, an image is P * P
  *    planes (py * P + px) of Hq x Wq entries; entry (r, q) of plane (py, px)
  *    holds the bins at extended column q P + px and extended rows (r + m) P +
- *    py, m = 0..3 (extended coordinate = coordinate + 3n), C uint16 each, in
- *    the order m, channel: 8 C bytes.  The 4 x 4 grid of pixel (X, Y) is then
- *    the 4 consecutive entries q = X / P .. + 3 of row Y / P of plane
- *    (Y mod P, X mod P): 32 C contiguous bytes.
+ *    py, m = 0..3 (extended coordinate = coordinate + 3n), in the order m,
+ *    channel: C uint16 per bin, 8 C bytes per entry; for C = 3 one uint32
+ *    per bin with channel c at bits 10 c .. 10 c + 9 (a bin is at most 1020),
+ *    16 bytes per entry.  The 4 x 4 grid of pixel (X, Y) is then the 4
+ *    consecutive entries q = X / P .. + 3 of row Y / P of plane
+ *    (Y mod P, X mod P): 4 entries of contiguous bytes.
  *  - the four views of a pair are stored consecutively in the canonical order
  *    (I_l^0, I_l^1, I_r^0, I_r^1); `batch` pairs make n = 4 * batch images.
  *  - hyp    int16  [ndir][batch][Hk][Wk][4]     (u, v, d0, d1), full-res px

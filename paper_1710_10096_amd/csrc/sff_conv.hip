@@ -27,11 +27,8 @@ typedef uint16_t bf16_t;  // raw bfloat16 bits in memory
 
 __device__ __forceinline__ float bf2f(bf16_t v) { return __uint_as_float((uint32_t)v << 16); }
 
-// round to nearest even: the conversion instruction of gfx950
-// (v_cvt_pk_bf16_f32; infinities kept, NaNs quiet)
-__device__ __forceinline__ bf16_t f2bf(float f) { return __builtin_bit_cast(bf16_t, (__bf16)f); }
-
-// Two values rounded the same way, packed (lo, hi) in one conversion.
+// Two values rounded to nearest even by the conversion instruction of gfx950
+// (v_cvt_pk_bf16_f32; infinities kept, NaNs quiet), packed (lo, hi).
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {

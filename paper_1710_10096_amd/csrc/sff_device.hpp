@@ -84,4 +84,47 @@ struct BinAddr {
     }
 };
 
+// A 16-byte piece of a bin patch in the form its squared distances are taken
+// from: as stored (8 uint16 bins) for C != 3; for C = 3 (four packed bins)
+// unpacked to six uint16 pairs: channels 0 and 1 of each bin, then channel 2
+// of bins 0 and 1 and of bins 2 and 3.
+template <int C>
+struct BinRef {
+    uint32_t w[4];
+};
+template <>
+struct BinRef<3> {
+    uint32_t w[6];
+};
+
+template <int C>
+__device__ __forceinline__ BinRef<C> bin_ref(uint4 v) {
+    BinRef<C> r;
+    const uint32_t t[4] = {v.x, v.y, v.z, v.w};
+    if constexpr (C == 3) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) r.w[m] = (t[m] & 0x3FFu) | ((t[m] << 6) & 0x3FF0000u);
+        r.w[4] = (t[0] >> 20) | ((t[1] >> 4) & 0x3FF0000u);
+        r.w[5] = (t[2] >> 20) | ((t[3] >> 4) & 0x3FF0000u);
+    } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) r.w[m] = t[m];
+    }
+    return r;
+}
+
+// acc + squared distance of two pieces (bins are at most 1020, so every
+// difference fits int16).
+template <int C>
+__device__ __forceinline__ int bin_piece_ssd(const BinRef<C>& a, uint4 b, int acc) {
+    const BinRef<C> u = bin_ref<C>(b);
+    constexpr int NW = C == 3 ? 6 : 4;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const short2v d = __builtin_bit_cast(short2v, a.w[k]) - __builtin_bit_cast(short2v, u.w[k]);
+        acc = __builtin_amdgcn_sdot2(d, d, acc, false);
+    }
+    return acc;
+}
+
 }  // namespace sff

@@ -316,14 +316,16 @@ __global__ void __launch_bounds__(256) bins_tile_kernel(const uint8_t* __restric
     }
     __syncthreads();
     // entry (r, q) of plane (py, px): slot t holds the bins of extended row
-    // (r + t) P + py at extended column q P + px; an entry is C words of 8 bytes
-    // (four uint16 each, slot-major then channel).  A run (plane, row) is nq C
+    // (r + t) P + py at extended column q P + px; an entry is WPE words of 8
+    // bytes (four uint16 each, slot-major then channel; for C = 3 two packed
+    // bins each, channels at bits 0, 10 and 20).  A run (plane, row) is nq WPE
     // consecutive words; the block's threads take runs_per_pass runs at a time.
+    constexpr int WPE = bin_entry_bytes(C) / 8;
     const int nq = min(Q, Wq - q0), nr = min(R, Hq - r0);
-    const int words_run = nq * C;
+    const int words_run = nq * WPE;
     const int runs_per_pass = max(1, 256 / words_run);
     const int k = (int)threadIdx.x % words_run, rsub = (int)threadIdx.x / words_run;
-    const int e = k / C, j = k - e * C;  // entry within the run, word within the entry
+    const int e = k / WPE, j = k - e * WPE;  // entry within the run, word within the entry
     const int nruns = P * P * nr;
     uint2* out = reinterpret_cast<uint2*>(bins);
     if (rsub < runs_per_pass && k < words_run) {
@@ -334,14 +336,24 @@ __global__ void __launch_bounds__(256) bins_tile_kernel(const uint8_t* __restric
         }
         for (int run = rsub; run < nruns; run += runs_per_pass) {
             const int py = plane >> sh, px = plane & (P - 1);
-            uint32_t v[4];
+            const size_t o = ((((size_t)m * P * P + plane) * Hq + (r0 + rr)) * Wq + q0 + e) * WPE + j;
+            if constexpr (C == 3) {
+                uint32_t d[2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int t = 4 * j + u, slot = t / C, c = t - slot * C;
-                v[u] = lb[((((rr + slot) * P + py) << lqp) + e * P + px) * C + c];
+                for (int u = 0; u < 2; ++u) {
+                    const uint16_t* b = lb + ((((rr + 2 * j + u) * P + py) << lqp) + e * P + px) * 3;
+                    d[u] = (uint32_t)b[0] | ((uint32_t)b[1] << 10) | ((uint32_t)b[2] << 20);
+                }
+                out[o] = make_uint2(d[0], d[1]);
+            } else {
+                uint32_t v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int t = 4 * j + u, slot = t / C, c = t - slot * C;
+                    v[u] = lb[((((rr + slot) * P + py) << lqp) + e * P + px) * C + c];
+                }
+                out[o] = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
             }
-            const size_t o = ((((size_t)m * P * P + plane) * Hq + (r0 + rr)) * Wq + q0 + e) * C + j;
-            out[o] = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
             rr += runs_per_pass;
             while (rr >= nr) {
                 rr -= nr;

@@ -83,20 +83,30 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const uint8_t* M, u
                                              (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 
-// The 2C 16-byte pieces of the bin grid of (X, Y).
+// The 16-byte pieces of the bin grid of (X, Y) as stored.
 template <int C>
-__device__ __forceinline__ void load_grid(__amdgpu_buffer_rsrc_t rs, int off, uint4 (&v)[2 * C]) {
+__device__ __forceinline__ void load_grid(__amdgpu_buffer_rsrc_t rs, int off, uint4 (&v)[bin_pieces(C)]) {
 #pragma unroll
-    for (int k = 0; k < 2 * C; ++k)
+    for (int k = 0; k < bin_pieces(C); ++k)
         v[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16 * k, 0, 0));
 }
 
 template <int C>
-__device__ __forceinline__ uint32_t grid_ssd(const uint4 (&a)[2 * C], const uint4 (&b)[2 * C]) {
+__device__ __forceinline__ uint32_t grid_ssd(const uint4 (&a)[bin_pieces(C)], const uint4 (&b)[bin_pieces(C)]) {
     int acc = 0;
 #pragma unroll
-    for (int k = 0; k < 2 * C; ++k) acc = piece_ssd(a[k], b[k], acc);
+    for (int k = 0; k < bin_pieces(C); ++k) acc = bin_piece_ssd<C>(bin_ref<C>(a[k]), b[k], acc);
     return (uint32_t)acc;
+}
+
+// Bin value k of a grid (entry k / 4C, plane row (k / C) mod 4, channel k mod
+// C) as stored at g; the operand planes take the values in this order.
+template <int C>
+__device__ __forceinline__ int grid_value(const uint8_t* g, int k) {
+    if constexpr (C == 3)
+        return (int)((reinterpret_cast<const uint32_t*>(g)[k / 3] >> (10 * (k % 3))) & 0x3FFu);
+    else
+        return (int)reinterpret_cast<const uint16_t*>(g)[k];
 }
 
 // One thread per (z, grid pixel): its bin grid into the operand planes.
@@ -111,13 +121,12 @@ __global__ void __launch_bounds__(256) op_planes_kernel(BinInitArgs a, OpPlanes 
     addr.sh = a.sh;
     addr.Hq = a.Hq;
     addr.RS = a.Wq * bin_entry_bytes(C);
-    const uint16_t* g = reinterpret_cast<const uint16_t*>(a.bins + (size_t)z * a.img_bytes +
-                                                          addr(a.n * j, a.n * i));
+    const uint8_t* g = a.bins + (size_t)z * a.img_bytes + addr(a.n * j, a.n * i);
     _Float16 b[KS::KP], q[KS::KP];
     uint32_t sq = 0;
 #pragma unroll
     for (int k = 0; k < KS::KP; ++k) {
-        const int v = k < KS::K ? (int)g[k] - kCentre : 0;  // padding adds nothing
+        const int v = k < KS::K ? grid_value<C>(g, k) - kCentre : 0;  // padding adds nothing
         sq += (uint32_t)(v * v);
         b[k] = (_Float16)v;
         q[k] = (_Float16)(-2 * v);
@@ -441,7 +450,7 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
         uint32_t bssd = 0xFFFFFFFFu, bidx = 0;
         if (best[t] != INT_MAX) {
             const int r = btile[t] >> 16, c0 = j0 - F + 16 * (btile[t] & 0xFFFF);
-            uint4 qg[2 * C];
+            uint4 qg[bin_pieces(C)];
             load_grid<C>(rR, addr(n * jq, n * min(i0 + t, Hk - 1)), qg);
             const uint32_t asq = P.sq[zR + (size_t)min(i0 + t, Hk - 1) * Wk + jq];
             bssd = (uint32_t)best[t] + asq;
@@ -451,7 +460,7 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
                 const int jc = c0 + 4 * g + e;
                 const bool ok = (unsigned)(jc - jq + F) <= (unsigned)(2 * F) && (unsigned)jc < (unsigned)Wk;
                 if (ok && !found) {
-                    uint4 cg[2 * C];
+                    uint4 cg[bin_pieces(C)];
                     load_grid<C>(rT, addr(n * jc, n * r), cg);
                     if (grid_ssd<C>(qg, cg) == bssd) {
                         found = true;
@@ -496,7 +505,7 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
     const int iq = i0 + t, jqq = j0 + q;
     const bool live = iq < Hk && jqq < Wk;
     const int x = n * min(jqq, Wk - 1), y = n * min(iq, Hk - 1);
-    uint4 qg[2 * C];
+    uint4 qg[bin_pieces(C)];
     load_grid<C>(rR, addr(x, y), qg);
     const int W = a.W;
     // stereo partner on row y: target tx = x - s d0, increasing tx
@@ -505,7 +514,7 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
         const int txlo = s > 0 ? x - min(a.dm, x) : x;
         const int txhi = s > 0 ? x : x + min(a.dm, ((W - 1 - x) / n) * n);
         for (int tx = txlo + n * part; tx <= txhi; tx += kParts * n) {
-            uint4 cg[2 * C];
+            uint4 cg[bin_pieces(C)];
             load_grid<C>(rS, addr(tx, y), cg);
             const unsigned long long k = ((unsigned long long)grid_ssd<C>(qg, cg) << 32) | (uint32_t)tx;
             kS = k < kS ? k : kS;
@@ -528,7 +537,7 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
             const int txlo = s > 0 ? xc - min(a.dm, xc) : xc;
             const int txhi = s > 0 ? xc : xc + min(a.dm, ((W - 1 - xc) / n) * n);
             for (int tx = txlo + n * part; tx <= txhi; tx += kParts * n) {
-                uint4 cg[2 * C];
+                uint4 cg[bin_pieces(C)];
                 load_grid<C>(rX, addr(tx, yc), cg);
                 const unsigned long long k = ((unsigned long long)grid_ssd<C>(qg, cg) << 32) | (uint32_t)tx;
                 kX = k < kX ? k : kX;

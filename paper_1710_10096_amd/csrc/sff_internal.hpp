@@ -38,8 +38,12 @@ inline LevelGeom level_geom(const sff_params& p, int level) {
 // consecutive positions of one plane: columns X / 2n .. + 3 of plane X mod 2n,
 // rows Y / 2n .. + 3 of plane Y mod 2n.  Plane (py, px) = py * 2n + px holds
 // Hq x Wq entries; entry (r, q) holds the bins of plane rows r .. r + 3 at
-// column q (each bin stored in four entries), C uint16 channels per bin, so a
-// patch is one contiguous run of 4 entries = 32 C bytes (16-byte pieces: 2 C).
+// column q (each bin stored in four entries), so a patch is one contiguous run
+// of 4 entries.  A bin is C uint16 channels, except for C = 3, where it is one
+// 32-bit word holding the three channels at bits 0, 10 and 20 (a bin sums four
+// bytes, at most 1020): 16-byte entries and 64-byte patches instead of 24 and
+// 96, so a patch spans fewer cache lines and a gather moves two thirds of the
+// bytes.  Patch = bin_pieces(C) pieces of 16 bytes.
 struct BinGeom {
     int n, sh, P, Hq, Wq;  // n = 2^k, P = 2n = 1 << sh
 };
@@ -54,8 +58,10 @@ inline BinGeom bin_geom(const sff_params& p, int level) {
     return g;
 }
 
-// Bytes of one entry (4 plane rows of C channels) and of one image's planes.
-__host__ __device__ constexpr int bin_entry_bytes(int C) { return 8 * C; }
+// Bytes of one entry (4 plane rows of C channels), 16-byte pieces of a patch
+// (4 entries), and bytes of one image's planes.
+__host__ __device__ constexpr int bin_entry_bytes(int C) { return C == 3 ? 16 : 8 * C; }
+__host__ __device__ constexpr int bin_pieces(int C) { return bin_entry_bytes(C) / 4; }
 inline size_t bin_image_bytes(const sff_params& p, int level) {
     const BinGeom g = bin_geom(p, level);
     return (size_t)g.P * g.P * g.Hq * g.Wq * bin_entry_bytes(p.C);

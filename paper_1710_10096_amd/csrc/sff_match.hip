@@ -357,8 +357,9 @@ struct CoopEval {
 
 // Bin-plane evaluators: eq. (1) as 16 x the bin-grid squared distance of the
 // reference patch and the three target patches, with the same early-out and
-// view order as the descriptor evaluators.  A patch is P = 2C pieces of 16
-// bytes, contiguous (4 entries of 4 plane rows).
+// view order as the descriptor evaluators.  A patch is P = bin_pieces(C)
+// pieces of 16 bytes, contiguous (4 entries of 4 plane rows; 4 pieces of
+// packed bins for C = 3).
 //
 // BinLane: each lane gathers its own patches (fewest instructions and the
 // shortest chain of round trips; for launches too small to fill the chip).
@@ -370,7 +371,7 @@ struct CoopEval {
 // past the map's range (the load returns zeros without a memory access).
 template <int C>
 struct BinLane {
-    static constexpr int P = 2 * C;
+    static constexpr int P = bin_pieces(C);
     static constexpr int kOwners = 64;
     static constexpr int kLdsWords = 1;
     static constexpr int kPG = 1, kRG = 1;
@@ -378,7 +379,7 @@ struct BinLane {
     __amdgpu_buffer_rsrc_t rR, rT, rS, rX;
     BinAddr<C> addr;
     int H, W, s;
-    uint4 ref[P];
+    BinRef<C> ref[P];
 
     __device__ __forceinline__ void setup(const MatchArgs& a, int b, int sd) {
         const Views v(a, b, sd);
@@ -403,7 +404,10 @@ struct BinLane {
 
     template <class F>
     __device__ __forceinline__ void init(int x, int y, int, uint32_t*, F) {
-        load(rR, addr(x, y), ref);
+        uint4 v[P];
+        load(rR, addr(x, y), v);
+#pragma unroll
+        for (int k = 0; k < P; ++k) ref[k] = bin_ref<C>(v[k]);
     }
 
     __device__ __forceinline__ uint32_t view_cost(__amdgpu_buffer_rsrc_t rs, int X, int Y) const {
@@ -411,7 +415,7 @@ struct BinLane {
         load(rs, addr(X, Y), v);
         int acc = 0;
 #pragma unroll
-        for (int k = 0; k < P; ++k) acc = piece_ssd(ref[k], v[k], acc);
+        for (int k = 0; k < P; ++k) acc = bin_piece_ssd<C>(ref[k], v[k], acc);
         return 16u * (uint32_t)acc;
     }
 
@@ -431,20 +435,21 @@ struct BinLane {
                                                 uint32_t, uint32_t (&)[N]) {}
 };
 
-template <int C, int PG, int RG, int O = 64>
+template <int C, int PG, int RG, int O = 64, bool XTS = false>
 struct BinCoop {
-    static_assert(O == 64 || O == 32, "owners per wave");
-    static constexpr int P = 2 * C;
+    static_assert(O == 64 || O == 32 || O == 16, "owners per wave");
+    static_assert(O * bin_pieces(C) % 64 == 0, "whole loads per gather");
+    static constexpr int P = bin_pieces(C);
     static constexpr int K = O * P / 64;  // wave-wide loads per patch gather
     static constexpr int kOwners = O;
     static constexpr int kPG = PG, kRG = RG;
     static constexpr int kGroup = PG > RG ? PG : RG;
-    static constexpr int kLdsWords = kGroup * 64 * K;
+    static constexpr int kLdsWords = kGroup * (XTS ? 3 : 1) * 64 * K;
     static constexpr bool kGroups = true;
     __amdgpu_buffer_rsrc_t rR, rT, rS, rX;
     BinAddr<C> addr;
     int H, W, s;
-    uint4 refp[K];   // reference piece of slot k
+    BinRef<C> refp[K];  // reference piece of slot k
     uint32_t* part;  // this wave's LDS slice
     int lane;
 
@@ -480,14 +485,16 @@ struct BinCoop {
         const int ob = addr(x, y);
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            refp[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rR, slot_off(ob, k), 0, 0));
+            refp[k] = bin_ref<C>(
+                __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rR, slot_off(ob, k), 0, 0)));
     }
 
     // Squared distances (x 16) of N patches per owner, all gathers in flight
     // together; ob[m] < 0 marks no target (result 0).  Must be called by all
     // lanes of the wave.
-    template <int N>
-    __device__ __forceinline__ void ssdN(__amdgpu_buffer_rsrc_t rs, const int (&ob)[N], uint32_t (&c)[N]) {
+    // Patch m is read through rs_of(m) (views may differ between patches).
+    template <int N, class RS>
+    __device__ __forceinline__ void ssdN(RS rs_of, const int (&ob)[N], uint32_t (&c)[N]) {
         uint4 v[N][K];
         int so[N][K];
 #pragma unroll
@@ -498,11 +505,12 @@ struct BinCoop {
         for (int m = 0; m < N; ++m)
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                v[m][k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, so[m][k], 0, 0));
+                v[m][k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs_of(m), so[m][k], 0, 0));
 #pragma unroll
         for (int m = 0; m < N; ++m)
 #pragma unroll
-            for (int k = 0; k < K; ++k) part[64 * (m * K + k) + lane] = (uint32_t)piece_ssd(refp[k], v[m][k], 0);
+            for (int k = 0; k < K; ++k)
+                part[64 * (m * K + k) + lane] = (uint32_t)bin_piece_ssd<C>(refp[k], v[m][k], 0);
         wave_sync();
         const int ol = lane & (O - 1);  // lanes past the owners read a valid slot
 #pragma unroll
@@ -525,7 +533,10 @@ struct BinCoop {
     }
 
     // cost_below for N candidates of each lane, their gathers issued together
-    // view by view; same results as N calls with the same bound.
+    // view by view with the early-out between views, or (XTS) all three views
+    // in one round; same results as N calls with the same bound: a candidate
+    // stopped at a view has a partial cost at or above the bound, one that
+    // passes (or is scored in full) its exact cost.
     template <int N>
     __device__ __forceinline__ void cost_belowN(const bool (&w)[N], const Hyp (&h)[N], int x, int y,
                                                 uint32_t bound, uint32_t (&c)[N]) {
@@ -537,7 +548,21 @@ struct BinCoop {
             ty[m] = clampi(y + h[m].v, 0, H - 1);
             ob[m] = w[m] ? addr(clampi(x + h[m].u - dirmul(s, h[m].d1), 0, W - 1), ty[m]) : -1;
         }
-        ssdN<N>(rX, ob, c);
+        if constexpr (XTS) {
+            int o3[3 * N];
+            uint32_t c3[3 * N];
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                o3[m] = ob[m];
+                o3[N + m] = w[m] ? addr(clampi(x + h[m].u, 0, W - 1), ty[m]) : -1;
+                o3[2 * N + m] = w[m] ? addr(clampi(x - dirmul(s, h[m].d0), 0, W - 1), y) : -1;
+            }
+            ssdN<3 * N>([&](int m) { return m < N ? rX : m < 2 * N ? rT : rS; }, o3, c3);
+#pragma unroll
+            for (int m = 0; m < N; ++m) c[m] = c3[m] + c3[N + m] + c3[2 * N + m];
+            return;
+        }
+        ssdN<N>([&](int) { return rX; }, ob, c);
 #pragma unroll
         for (int m = 0; m < N; ++m) {
             al[m] = w[m] && c[m] < bound;
@@ -546,7 +571,7 @@ struct BinCoop {
         }
         if (!__any(any)) return;
         uint32_t d[N];
-        ssdN<N>(rT, ob, d);
+        ssdN<N>([&](int) { return rT; }, ob, d);
         any = false;
 #pragma unroll
         for (int m = 0; m < N; ++m) {
@@ -556,7 +581,7 @@ struct BinCoop {
             ob[m] = al[m] ? addr(clampi(x - dirmul(s, h[m].d0), 0, W - 1), y) : -1;
         }
         if (!__any(any)) return;
-        ssdN<N>(rS, ob, d);
+        ssdN<N>([&](int) { return rS; }, ob, d);
 #pragma unroll
         for (int m = 0; m < N; ++m) c[m] += d[m];
     }
@@ -808,43 +833,52 @@ sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
 }
 
 // Bin-plane evaluators by launch size (updates per launch), measured on the
-// KITTI-size pair with every shape giving identical fields:
+// KITTI-size pair (C = 3, packed bins) with every shape giving identical
+// fields; ms per level:
 //  - level 2 (29,328 updates, under one wave per SIMD): all 4 neighbours and
-//    all 6 samples in one group each, 32 owners per wave: 0.190 ms per level
-//    against 0.221 with groups of 2 and 3 (the chain of dependent round trips
-//    and instructions of a lone wave is what these launches wait on);
-//  - level 1 (116,936 updates): 4 neighbours, 3 samples, 32 owners: 0.364 vs
-//    0.379 ms;
-//  - level 0 (465,750 updates): 2 neighbours, 3 samples, 64 owners, 82-85 us
-//    per launch, bound by the texture path (TA 68 %, TD 79 % busy; about
-//    2.5 clocks per distinct 128-byte line a wave-wide load touches); wider
-//    groups cost occupancy (1.04-1.22 ms).
-// Issuing the temporal and stereo gathers with the cross one (no early-out
-// between views) was slower at every level (level 0: 1.10-2.11 ms), and so
-// were other tile orders (row-major 1.10 ms, no XCD grouping 1.37 ms).
-// Below 20,000 updates each lane gathers its own patches.  SFF_MATCH_EVAL =
-// "lane", "coop" (2/3, 64 owners), "coop-32" (2/3, 32 owners), "coop-43-32"
-// or "coop-46-32" forces one (all give identical results); anything else:
-// auto.
-constexpr long kBinWideMaxUpdates = 262144;
+//    all 6 samples in one group each, every view in one round, 16 owners per
+//    wave: 0.165 (the same with 32 owners and the early-out: 0.184; groups of
+//    2 and 3 with 64 owners: 0.25) -- a lone wave's chain of dependent round
+//    trips is what these launches wait on, so the shape with the fewest
+//    rounds and the most waves wins;
+//  - level 1 (116,936 updates) and level 0 (465,750): one candidate at a
+//    time with its three views in one round, 64 owners: 0.347 and 0.962
+//    (groups of 2 and 3 with the early-out between views: 0.352-0.37 and
+//    0.98-1.05; 4 and 3 with 32 owners: 0.372 and 1.13).  The early-out
+//    rejects only ~15 % of candidates at the cross view, so a round per view
+//    buys little texture-path work and costs two round trips.
+// Other tile orders were slower (row-major 1.10 ms at level 0, no XCD
+// grouping 1.37 ms).  Below 20,000 updates each lane gathers its own patches.
+// SFF_MATCH_EVAL = "lane", "coop" (2/3, 64 owners, early-out), "coop-32",
+// "coop-43-32", "coop-46-32" (32 owners, early-out), "coop-xts" (1/1, 64
+// owners, three views a round) or "coop-46-16-xts" forces one (all give
+// identical results; 16-owner shapes need 4 pieces a patch, C >= 2, and fall
+// back to "coop-46-32" otherwise); anything else: auto.
 template <int C>
 sff_status run_bin_level(const MatchArgs& a, int iters, hipStream_t st) {
     const long updates = (long)a.ndir * a.batch * a.Hk * ((a.Wk + 1) / 2);
-    int pick = updates < kCoopMinUpdates ? 0 : updates < kHalfOwnersMaxUpdates ? 4 : updates < kBinWideMaxUpdates ? 3 : 1;
+    int pick = updates < kCoopMinUpdates ? 0 : updates < kHalfOwnersMaxUpdates ? 6 : 5;
     if (const char* e = std::getenv("SFF_MATCH_EVAL")) {
         if (std::strcmp(e, "lane") == 0) pick = 0;
         if (std::strcmp(e, "coop") == 0) pick = 1;
         if (std::strcmp(e, "coop-32") == 0) pick = 2;
         if (std::strcmp(e, "coop-43-32") == 0) pick = 3;
         if (std::strcmp(e, "coop-46-32") == 0) pick = 4;
+        if (std::strcmp(e, "coop-xts") == 0) pick = 5;
+        if (std::strcmp(e, "coop-46-16-xts") == 0) pick = 6;
     }
     switch (pick) {
         case 0: return launch_level<C, BinLane<C>>(a, iters, st);
         case 1: return launch_level<C, BinCoop<C, 2, 3>>(a, iters, st);
         case 2: return launch_level<C, BinCoop<C, 2, 3, 32>>(a, iters, st);
         case 3: return launch_level<C, BinCoop<C, 4, 3, 32>>(a, iters, st);
-        default: return launch_level<C, BinCoop<C, 4, 6, 32>>(a, iters, st);
+        case 5: return launch_level<C, BinCoop<C, 1, 1, 64, true>>(a, iters, st);
+        case 6:
+            if constexpr (bin_pieces(C) >= 4) return launch_level<C, BinCoop<C, 4, 6, 16, true>>(a, iters, st);
+            break;
+        default: break;
     }
+    return launch_level<C, BinCoop<C, 4, 6, 32>>(a, iters, st);
 }
 
 }  // namespace

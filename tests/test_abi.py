@@ -71,15 +71,17 @@ def test_descriptor_record_channels():
 
 def test_bin_plane_sizes():
     """Bytes of one image's bin-sum planes: P^2 planes of Hq x Wq entries of
-    8 C bytes, P = 2^(level+1), Hq = (H-1)/P + 1, Wq = (W-1)/P + 4 rounded up
-    to 16 (the layout include/sff.h documents)."""
+    8 C bytes (16 for C = 3, whose bins are packed in one word), P =
+    2^(level+1), Hq = (H-1)/P + 1, Wq = (W-1)/P + 4 rounded up to 16 (the
+    layout include/sff.h documents)."""
     L = _native.lib()
     for H, W, C, lv in ((375, 1242, 3, 0), (375, 1242, 3, 2), (1, 1, 1, 0), (29, 71, 2, 3)):
         p = SffParams(H=H, W=W, C=C, levels=lv + 1, iters=1, rs_r0=32, rs_samples=6, fmax=8,
                       dmax=8, tau=1)
         P = 2 << lv
         Hq, Wq = (H - 1) // P + 1, -(-((W - 1) // P + 4) // 16) * 16
-        assert L.sff_bin_bytes(ctypes.byref(p), lv) == P * P * Hq * Wq * 8 * C
+        entry = 16 if C == 3 else 8 * C
+        assert L.sff_bin_bytes(ctypes.byref(p), lv) == P * P * Hq * Wq * entry
         assert L.sff_bin_bytes(ctypes.byref(p), lv + 1) == 0
 
 

@@ -92,7 +92,8 @@ def _bins_expected(S, level):
     include/sff.h, from the plain definition: bin at extended position
     (ex, ey) = (X + 3n, Y + 3n) sums S at X + {0, n}, Y + {0, n} (clamped);
     entry (r, q) of plane (py, px) holds extended rows (r + m) P + py, m = 0..3,
-    at extended column q P + px."""
+    at extended column q P + px; C uint16 channels per bin, or for C = 3 one
+    uint32 with the channels at bits 0, 10 and 20."""
     H, W, C = S.shape
     n, P = 1 << level, 2 << level
     Hq, Wq = (H - 1) // P + 1, -(-((W - 1) // P + 4) // 16) * 16
@@ -108,6 +109,9 @@ def _bins_expected(S, level):
         for px in range(P):
             for m in range(4):
                 out[py, px, :, :, m] = b[(np.arange(Hq) + m) * P + py][:, np.arange(Wq) * P + px]
+    if C == 3:
+        w = out.astype(np.uint32)
+        return w[..., 0] | (w[..., 1] << 10) | (w[..., 2] << 20)
     return out
 
 
@@ -135,7 +139,7 @@ def test_wht_bins_layout(sff, case):
         for m in range(4):
             S = imgs[m] if lv == 0 else oracle.smooth(imgs[m], 1 << lv)
             exp = _bins_expected(S, lv)
-            g = host(bins)[m * nb:(m + 1) * nb].view(np.uint16).reshape(exp.shape)
+            g = host(bins)[m * nb:(m + 1) * nb].view(exp.dtype).reshape(exp.shape)
             assert np.array_equal(g, exp), (name, lv, m)
             assert np.array_equal(d[m][:, :, :C], oracle.features(imgs[m], lv)), (name, lv, m)
         only = host(sff.sff_wht_features(p, dev(imgs), lv, want_desc=False))
@@ -263,7 +267,7 @@ LEVEL_CASES = [
 MATCH_KERNELS = [("desc", "lane"), ("desc", "coop-narrow"), ("desc", "coop-wide"),
                  ("desc", "coop-narrow-32"), ("desc", "coop-wide-32"),
                  ("bins", "lane"), ("bins", "coop"), ("bins", "coop-32"), ("bins", "coop-43-32"),
-                 ("bins", "coop-46-32")]
+                 ("bins", "coop-46-32"), ("bins", "coop-xts"), ("bins", "coop-46-16-xts")]
 
 
 @pytest.mark.parametrize("kernel", MATCH_KERNELS, ids=[f"{a}-{b}" for a, b in MATCH_KERNELS])
@@ -272,7 +276,9 @@ def test_match_level_parity(sff, case, kernel, monkeypatch):
     """Every gather kernel against the oracle: descriptor records (per-lane;
     wave-cooperative scoring 2 neighbours and 3 samples, or 4 and 3, at a
     time, with 64 or 32 pixels per wave) and bin-sum planes (per-lane;
-    cooperative with 64 or 32 pixels per wave); SFF_MATCH_EVAL forces one."""
+    cooperative with 64, 32 or 16 pixels per wave, one view a round with the
+    early-out between views or all three views in one round); SFF_MATCH_EVAL
+    forces one."""
     import torch
     maps, evaluator = kernel
     monkeypatch.setenv("SFF_MATCH_EVAL", evaluator)
@@ -391,7 +397,8 @@ def test_pipeline_ragged_batch_on_side_stream(sff):
 
 
 PIPE_KERNELS = [("bins", "auto"), ("bins", "lane"), ("bins", "coop"), ("bins", "coop-32"),
-                ("bins", "coop-43-32"), ("bins", "coop-46-32"),
+                ("bins", "coop-43-32"), ("bins", "coop-46-32"), ("bins", "coop-xts"),
+                ("bins", "coop-46-16-xts"),
                 ("desc", "auto"), ("desc", "lane"), ("desc", "coop-narrow"), ("desc", "coop-wide"),
                 ("desc", "coop-narrow-32"), ("desc", "coop-wide-32")]
 
