@@ -393,6 +393,11 @@ def probes(reps: int = 5) -> dict:
     return res
 
 
+# Pixel updates per half-step (both fields) from which the library runs the
+# forward and inverse fields on two streams.
+SPLIT_MIN_UPDATES = 100000
+
+
 def half_step_bytes(p, B: int) -> list:
     """Algorithmic bytes of the propagation / random-search launches per level
     (both fields, B pairs): per level-iteration and grid pixel 128 C + 32, plus
@@ -519,17 +524,26 @@ def main():
     evals = eval_count(p) * B
 
     # dominant kernel: the propagation / random-search half-step, 2 * iters
-    # launches per level (the hand-off is fused into each level's first launch)
+    # per level (the hand-off is fused into each level's first one).  A
+    # half-step of both fields is one dispatch, or, from SPLIT_MIN_UPDATES
+    # pixel updates, two concurrent dispatches (one field each) on the
+    # launching stream and the library's helper stream; its duration is the
+    # level's time on the launching stream (which waits for the helper) over
+    # the half-steps.
     K = p["levels"]
     launches = 0
+    dispatches = 0
     hs_bytes = 0.0
     hs_ms = 0.0
     levels = {}
     for k, b_k in enumerate(half_step_bytes(p, B)):
         t_k = stage_ms[f"match:L{k}"]
+        Hk, Wk = grid(p, k)
+        per = 2 if 2 * B * Hk * ((Wk + 1) // 2) >= SPLIT_MIN_UPDATES else 1
         levels[f"L{k}"] = {"avg_launch_us": t_k * 1e3 / (2 * p["iters"]),
-                           "GBps": b_k / (t_k * 1e-3) / 1e9}
+                           "GBps": b_k / (t_k * 1e-3) / 1e9, "dispatches_per_half_step": per}
         launches += 2 * p["iters"]
+        dispatches += 2 * p["iters"] * per
         hs_bytes += b_k
         hs_ms += t_k
     avg_us = hs_ms * 1e3 / launches
@@ -543,7 +557,10 @@ def main():
                               "Cache hits included; TCC_EA0_RDREQ_DRAM reads the same as "
                               "TCC_EA0_RDREQ here, so the HBM share is not separable",
             "algorithmic_bytes_per_launch": hs_bytes / launches,
-            "launches_per_step": launches, "avg_launch_us": avg_us, "levels": levels}
+            "launches_per_step": launches, "avg_launch_us": avg_us,
+            "launch_means": "half-step of both fields (one dispatch, or two concurrent "
+                            "dispatches on two streams)",
+            "dispatches_per_step": dispatches, "levels": levels}
 
     out = {
         "metric": "matched_px_per_s", "value": npx / (ms * 1e-3), "unit": "px/s",

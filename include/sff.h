@@ -17,7 +17,10 @@
  *    every output untouched.  A launch failure reported by the runtime after
  *    enqueueing returns SFF_ERR_HIP; faults inside kernels surface at the
  *    caller's next synchronisation.
- *  - The library is stateless and thread-safe.
+ *  - The library is thread-safe.  Its state, per device, is the fixed scratch
+ *    array of sff_wht_features_noalloc and one helper stream with two events
+ *    (sff_match_level_bins), created on first use and kept until the process
+ *    ends.
  *
  * Data layouts (row-major)
  *  - image  uint8  [n][H][W][C]                 C = 1..4 channels
@@ -255,9 +258,16 @@ sff_status sff_match_level(const sff_params* p, int32_t batch, int32_t dir, int3
  * descriptors).  bins: level-k planes of the 4 views of each pair,
  * [batch][4] images of sff_bin_bytes(p, level) bytes (sff_wht_features),
  * 16-byte aligned.  Other arguments as for sff_match_level.  Wave-cooperative
- * gathers from 20000 pixel updates per launch (32 pixels per wave below
- * 50000, 64 above), one lane per pixel below; SFF_MATCH_EVAL=lane|coop|coop-32
- * forces one (identical results).
+ * gathers from 20000 pixel updates per launch (below 50000: 16 pixels per
+ * wave, all 4 neighbours and all samples at once; above: 64 pixels per wave,
+ * one candidate at a time), one lane per pixel below;
+ * SFF_MATCH_EVAL=lane|coop|coop-32|coop-43-32|coop-46-32|coop-xts|
+ * coop-46-16-xts forces one (identical results).  With dir = SFF_DIR_BOTH
+ * and 100000 or more updates the two fields run on two streams: `stream` and
+ * a helper stream of the library, which waits for the work enqueued on
+ * `stream` before the call, and which `stream` waits for after it (so the
+ * call is ordered on `stream` as any other); SFF_MATCH_SPLIT=0|1 forces one
+ * sequence or the split (identical results).
  * Errors: as sff_match_level; SFF_ERR_UNSUPPORTED when an image's planes
  *   reach 2 GiB (32-bit gather offsets). */
 sff_status sff_match_level_bins(const sff_params* p, int32_t batch, int32_t dir, int32_t level,

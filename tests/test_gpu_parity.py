@@ -267,7 +267,9 @@ LEVEL_CASES = [
 MATCH_KERNELS = [("desc", "lane"), ("desc", "coop-narrow"), ("desc", "coop-wide"),
                  ("desc", "coop-narrow-32"), ("desc", "coop-wide-32"),
                  ("bins", "lane"), ("bins", "coop"), ("bins", "coop-32"), ("bins", "coop-43-32"),
-                 ("bins", "coop-46-32"), ("bins", "coop-xts"), ("bins", "coop-46-16-xts")]
+                 ("bins", "coop-46-32"), ("bins", "coop-xts"), ("bins", "coop-46-16-xts"),
+                 # the two fields on two streams (forced; by default only for large launches)
+                 ("bins", "coop-xts+split"), ("bins", "coop-46-16-xts+split"), ("bins", "lane+split")]
 
 
 @pytest.mark.parametrize("kernel", MATCH_KERNELS, ids=[f"{a}-{b}" for a, b in MATCH_KERNELS])
@@ -278,10 +280,12 @@ def test_match_level_parity(sff, case, kernel, monkeypatch):
     time, with 64 or 32 pixels per wave) and bin-sum planes (per-lane;
     cooperative with 64, 32 or 16 pixels per wave, one view a round with the
     early-out between views or all three views in one round); SFF_MATCH_EVAL
-    forces one."""
+    forces one, SFF_MATCH_SPLIT=1 the two fields on two streams."""
     import torch
     maps, evaluator = kernel
+    evaluator, _, split = evaluator.partition("+")
     monkeypatch.setenv("SFF_MATCH_EVAL", evaluator)
+    monkeypatch.setenv("SFF_MATCH_SPLIT", "1" if split else "0")
     name, H, W, C, levels, level, iters, rs, B = case
     fmax, dmax = 16, 12
     p = params_dict(H, W, C, levels=levels, iters=iters, rs_samples=rs, fmax=fmax, dmax=dmax)
@@ -385,18 +389,25 @@ def test_pipeline_tiny(sff):
     _check_pipeline(sff, [make_scene(tiny_spec())], tiny_params(), [1])
 
 
-def test_pipeline_ragged_batch_on_side_stream(sff):
+@pytest.mark.parametrize("split", ["auto", "1"])
+def test_pipeline_ragged_batch_on_side_stream(sff, split, monkeypatch):
+    """The whole stage on a stream other than the current one; with the two
+    fields on two streams forced at every level, the helper stream must wait
+    for the features and init on that stream and the consistency check for it."""
     import torch
+    if split != "auto":
+        monkeypatch.setenv("SFF_MATCH_SPLIT", split)
     p = params_dict(53, 91, 3, levels=3, iters=3, fmax=24, dmax=20)
     scenes = [make_scene(small_spec(53, 91, 3, 300 + b, flow_max=12, d_range=(0, 16)))
               for b in range(3)]
     st = torch.cuda.Stream()
-    _say("pipeline ragged batch 3 on side stream")
+    _say("pipeline ragged batch 3 on side stream, split", split)
     with torch.cuda.stream(st):
         _check_pipeline(sff, scenes, p, [5, 6, 7], stream=st)
 
 
-PIPE_KERNELS = [("bins", "auto"), ("bins", "lane"), ("bins", "coop"), ("bins", "coop-32"),
+PIPE_KERNELS = [("bins", "auto"), ("bins", "auto+nosplit"), ("bins", "lane"), ("bins", "coop"),
+                ("bins", "coop-32"),
                 ("bins", "coop-43-32"), ("bins", "coop-46-32"), ("bins", "coop-xts"),
                 ("bins", "coop-46-16-xts"),
                 ("desc", "auto"), ("desc", "lane"), ("desc", "coop-narrow"), ("desc", "coop-wide"),
@@ -405,8 +416,14 @@ PIPE_KERNELS = [("bins", "auto"), ("bins", "lane"), ("bins", "coop"), ("bins", "
 
 @pytest.mark.parametrize("kernel", PIPE_KERNELS, ids=[f"{a}-{b}" for a, b in PIPE_KERNELS])
 def test_pipeline_kitti_full(sff, kernel, monkeypatch):
+    """The KITTI-size pair end to end against the oracle with every gather
+    kernel; by default levels 0 and 1 run the two fields on two streams,
+    "+nosplit" runs them in one launch sequence."""
     maps, evaluator = kernel
+    evaluator, _, split = evaluator.partition("+")
     monkeypatch.setenv("SFF_MATCH_EVAL", evaluator)
+    if split:
+        monkeypatch.setenv("SFF_MATCH_SPLIT", "0")
     _say("pipeline kitti 1242x375", maps, evaluator)
     _check_pipeline(sff, [make_scene(kitti_spec())], kitti_params(), [2], maps=maps)
 
