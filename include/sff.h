@@ -41,9 +41,13 @@
  *    planes (py * P + px) of Hq x Wq entries; entry (r, q) of plane (py, px)
  *    holds the bins at extended column q P + px and extended rows (r + m) P +
  *    py, m = 0..3 (extended coordinate = coordinate + 3n), in the order m,
- *    channel: C uint16 per bin, 8 C bytes per entry; for C = 3 one uint32
- *    per bin with channel c at bits 10 c .. 10 c + 9 (a bin is at most 1020),
- *    16 bytes per entry.  The 4 x 4 grid of pixel (X, Y) is then the 4
+ *    channel: C uint16 per bin, 8 C bytes per entry; for C = 3 the entry's
+ *    bins b_m (10-bit channels b_m[c], at most 1020) are packed into four
+ *    uint32 words: word 0 = b_0[0] | b_1[0] << 16, word 1 = b_2[0] | b_3[0] <<
+ *    16, word 2 = b_0[1] | b_1[1] << 16, word 3 = b_2[1] | b_3[1] << 16, plus
+ *    channel 2: the low 6 bits of b_0[2] and b_1[2] at bits 10 and 26 of word
+ *    0 and their high 4 bits at bits 10 and 26 of word 1, b_2[2] and b_3[2]
+ *    likewise in words 2 and 3 (16 bytes per entry).  The 4 x 4 grid of pixel (X, Y) is then the 4
  *    consecutive entries q = X / P .. + 3 of row Y / P of plane
  *    (Y mod P, X mod P): 4 entries of contiguous bytes.
  *  - the four views of a pair are stored consecutively in the canonical order

@@ -85,9 +85,14 @@ struct BinAddr {
 };
 
 // A 16-byte piece of a bin patch in the form its squared distances are taken
-// from: as stored (8 uint16 bins) for C != 3; for C = 3 (four packed bins)
-// unpacked to six uint16 pairs: channels 0 and 1 of each bin, then channel 2
-// of bins 0 and 1 and of bins 2 and 3.
+// from: as stored (8 uint16 bins) for C != 3; for C = 3 (one entry: four bins
+// m = 0..3 of three 10-bit channels, packed as the bin planes store it)
+// unpacked to six uint16 pairs.  The packing puts channel 0 of bins (0, 1) and
+// (2, 3) and channel 1 of bins (0, 1) and (2, 3) in the low 10 bits of the two
+// halves of words 0..3, and splits channel 2 of bins (0, 1) over the spare
+// bits 10..15 of both halves of word 0 (low 6 bits) and word 1 (high 4), of
+// bins (2, 3) over words 2 and 3; so each pair costs one mask, or two shifts
+// and two masks for the channel-2 pairs.
 template <int C>
 struct BinRef {
     uint32_t w[4];
@@ -103,9 +108,9 @@ __device__ __forceinline__ BinRef<C> bin_ref(uint4 v) {
     const uint32_t t[4] = {v.x, v.y, v.z, v.w};
     if constexpr (C == 3) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) r.w[m] = (t[m] & 0x3FFu) | ((t[m] << 6) & 0x3FF0000u);
-        r.w[4] = (t[0] >> 20) | ((t[1] >> 4) & 0x3FF0000u);
-        r.w[5] = (t[2] >> 20) | ((t[3] >> 4) & 0x3FF0000u);
+        for (int m = 0; m < 4; ++m) r.w[m] = t[m] & 0x03FF03FFu;
+        r.w[4] = ((t[0] >> 10) & 0x003F003Fu) | ((t[1] >> 4) & 0x03C003C0u);
+        r.w[5] = ((t[2] >> 10) & 0x003F003Fu) | ((t[3] >> 4) & 0x03C003C0u);
     } else {
 #pragma unroll
         for (int m = 0; m < 4; ++m) r.w[m] = t[m];

@@ -317,8 +317,8 @@ __global__ void __launch_bounds__(256) bins_tile_kernel(const uint8_t* __restric
     __syncthreads();
     // entry (r, q) of plane (py, px): slot t holds the bins of extended row
     // (r + t) P + py at extended column q P + px; an entry is WPE words of 8
-    // bytes (four uint16 each, slot-major then channel; for C = 3 two packed
-    // bins each, channels at bits 0, 10 and 20).  A run (plane, row) is nq WPE
+    // bytes (four uint16 each, slot-major then channel; for C = 3 the packed
+    // entry of the matcher's unpacking, two of its words each).  A run (plane, row) is nq WPE
     // consecutive words; the block's threads take runs_per_pass runs at a time.
     constexpr int WPE = bin_entry_bytes(C) / 8;
     const int nq = min(Q, Wq - q0), nr = min(R, Hq - r0);
@@ -338,13 +338,20 @@ __global__ void __launch_bounds__(256) bins_tile_kernel(const uint8_t* __restric
             const int py = plane >> sh, px = plane & (P - 1);
             const size_t o = ((((size_t)m * P * P + plane) * Hq + (r0 + rr)) * Wq + q0 + e) * WPE + j;
             if constexpr (C == 3) {
-                uint32_t d[2];
+                // word j holds words 2 j and 2 j + 1 of the packed entry: channel j
+                // of bins (0, 1) and (2, 3) in the halves' low 10 bits, and channel 2
+                // of bins (2 j, 2 j + 1) split low 6 / high 4 bits over their spare
+                // bits 10..15
+                uint32_t ch[4], c2[2];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const uint16_t* b = lb + ((((rr + 2 * j + u) * P + py) << lqp) + e * P + px) * 3;
-                    d[u] = (uint32_t)b[0] | ((uint32_t)b[1] << 10) | ((uint32_t)b[2] << 20);
+                for (int u = 0; u < 4; ++u) {
+                    const uint16_t* b = lb + ((((rr + u) * P + py) << lqp) + e * P + px) * 3;
+                    ch[u] = b[j];
+                    if (u >> 1 == j) c2[u & 1] = b[2];
                 }
-                out[o] = make_uint2(d[0], d[1]);
+                const uint32_t lo = ((c2[0] & 0x3Fu) << 10) | ((c2[1] & 0x3Fu) << 26);
+                const uint32_t hi = ((c2[0] >> 6) << 10) | ((c2[1] >> 6) << 26);
+                out[o] = make_uint2(ch[0] | (ch[1] << 16) | lo, ch[2] | (ch[3] << 16) | hi);
             } else {
                 uint32_t v[4];
 #pragma unroll

@@ -99,14 +99,19 @@ __device__ __forceinline__ uint32_t grid_ssd(const uint4 (&a)[bin_pieces(C)], co
     return (uint32_t)acc;
 }
 
-// Bin value k of a grid (entry k / 4C, plane row (k / C) mod 4, channel k mod
-// C) as stored at g; the operand planes take the values in this order.
+// Bin value k of a grid as stored at g: uint16 k (entry k / 4C, plane row
+// (k / C) mod 4, channel k mod C), or for C = 3 half k mod 2 of pair (k mod
+// 12) / 2 of entry k / 12 as the matcher unpacks it; the operand planes take
+// the values in this order (the same for queries and candidates).
 template <int C>
 __device__ __forceinline__ int grid_value(const uint8_t* g, int k) {
-    if constexpr (C == 3)
-        return (int)((reinterpret_cast<const uint32_t*>(g)[k / 3] >> (10 * (k % 3))) & 0x3FFu);
-    else
+    if constexpr (C == 3) {
+        const uint4 v = reinterpret_cast<const uint4*>(g)[k / 12];
+        const BinRef<3> u = bin_ref<3>(v);
+        return (int)((u.w[(k % 12) >> 1] >> (16 * (k & 1))) & 0xFFFFu);
+    } else {
         return (int)reinterpret_cast<const uint16_t*>(g)[k];
+    }
 }
 
 // One thread per (z, grid pixel): its bin grid into the operand planes.

@@ -39,11 +39,11 @@ inline LevelGeom level_geom(const sff_params& p, int level) {
 // rows Y / 2n .. + 3 of plane Y mod 2n.  Plane (py, px) = py * 2n + px holds
 // Hq x Wq entries; entry (r, q) holds the bins of plane rows r .. r + 3 at
 // column q (each bin stored in four entries), so a patch is one contiguous run
-// of 4 entries.  A bin is C uint16 channels, except for C = 3, where it is one
-// 32-bit word holding the three channels at bits 0, 10 and 20 (a bin sums four
-// bytes, at most 1020): 16-byte entries and 64-byte patches instead of 24 and
-// 96, so a patch spans fewer cache lines and a gather moves two thirds of the
-// bytes.  Patch = bin_pieces(C) pieces of 16 bytes.
+// of 4 entries.  A bin is C uint16 channels, except for C = 3, where an
+// entry's four bins of three 10-bit channels (a bin sums four bytes, at most
+// 1020) are packed into 16 bytes (layout at BinRef<3>): 64-byte patches instead
+// of 96, so a patch spans fewer cache lines and a gather moves two thirds of
+// the bytes.  Patch = bin_pieces(C) pieces of 16 bytes.
 struct BinGeom {
     int n, sh, P, Hq, Wq;  // n = 2^k, P = 2n = 1 << sh
 };

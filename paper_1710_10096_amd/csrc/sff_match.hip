@@ -864,7 +864,7 @@ sff_status launch_bin_pick(int pick, const MatchArgs& a, int iters, hipStream_t 
         case 3: return launch_level<C, BinCoop<C, 4, 3, 32>>(a, iters, st);
         case 5: return launch_level<C, BinCoop<C, 1, 1, 64, true>>(a, iters, st);
         case 6:
-            if constexpr (bin_pieces(C) >= 4) return launch_level<C, BinCoop<C, 4, 6, 16, true>>(a, iters, st);
+            if constexpr (16 * bin_pieces(C) % 64 == 0) return launch_level<C, BinCoop<C, 4, 6, 16, true>>(a, iters, st);
             break;
         default: break;
     }

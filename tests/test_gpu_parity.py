@@ -92,8 +92,10 @@ def _bins_expected(S, level):
     include/sff.h, from the plain definition: bin at extended position
     (ex, ey) = (X + 3n, Y + 3n) sums S at X + {0, n}, Y + {0, n} (clamped);
     entry (r, q) of plane (py, px) holds extended rows (r + m) P + py, m = 0..3,
-    at extended column q P + px; C uint16 channels per bin, or for C = 3 one
-    uint32 with the channels at bits 0, 10 and 20."""
+    at extended column q P + px; C uint16 channels per bin, or for C = 3 the
+    four bins b_0..b_3 of an entry packed into four uint32 words (channels 0
+    and 1 in the halves' low 10 bits, channel 2 split over their bits 10..15:
+    the layout include/sff.h documents)."""
     H, W, C = S.shape
     n, P = 1 << level, 2 << level
     Hq, Wq = (H - 1) // P + 1, -(-((W - 1) // P + 4) // 16) * 16
@@ -110,8 +112,15 @@ def _bins_expected(S, level):
             for m in range(4):
                 out[py, px, :, :, m] = b[(np.arange(Hq) + m) * P + py][:, np.arange(Wq) * P + px]
     if C == 3:
-        w = out.astype(np.uint32)
-        return w[..., 0] | (w[..., 1] << 10) | (w[..., 2] << 20)
+        b = out.astype(np.uint32)  # [..., m, c]
+        c2 = b[..., 2]
+        lo, hi = c2 & 0x3F, c2 >> 6
+        w = np.empty(out.shape[:4] + (4,), np.uint32)
+        w[..., 0] = b[..., 0, 0] | (b[..., 1, 0] << 16) | (lo[..., 0] << 10) | (lo[..., 1] << 26)
+        w[..., 1] = b[..., 2, 0] | (b[..., 3, 0] << 16) | (hi[..., 0] << 10) | (hi[..., 1] << 26)
+        w[..., 2] = b[..., 0, 1] | (b[..., 1, 1] << 16) | (lo[..., 2] << 10) | (lo[..., 3] << 26)
+        w[..., 3] = b[..., 2, 1] | (b[..., 3, 1] << 16) | (hi[..., 2] << 10) | (hi[..., 3] << 26)
+        return w
     return out
 
 
