@@ -472,11 +472,12 @@ struct BinCoop {
     __device__ __forceinline__ static int owner(int k, int l) { return (64 * k + l) / P; }
     __device__ __forceinline__ static int piece(int k, int l) { return (64 * k + l) % P; }
 
-    // Offset of slot (k, lane): piece of its owner's patch at ob, or past the
-    // map's range when the owner has no target (ob < 0).
+    // Offset of slot (k, lane): piece of its owner's patch at ob; an owner
+    // without a target has ob = kNoTarget, and its slots, kNoTarget plus at
+    // most 16 (P - 1) as unsigned 32-bit offsets, lie past every map's range
+    // (maps are at most kNoTarget bytes), so their loads return zeros.
     __device__ __forceinline__ int slot_off(int ob, int k) const {
-        const int oo = __shfl(ob, owner(k, lane));
-        return oo >= 0 ? oo + piece(k, lane) * 16 : kNoTarget;
+        return (int)((uint32_t)__shfl(ob, owner(k, lane)) + (uint32_t)(piece(k, lane) * 16));
     }
 
     template <class F>
@@ -491,7 +492,7 @@ struct BinCoop {
     }
 
     // Squared distances (x 16) of N patches per owner, all gathers in flight
-    // together; ob[m] < 0 marks no target (result 0).  Must be called by all
+    // together; ob[m] = kNoTarget marks no target (result 0).  Must be called by all
     // lanes of the wave.
     // Patch m is read through rs_of(m) (views may differ between patches).
     template <int N, class RS>
@@ -519,7 +520,7 @@ struct BinCoop {
             uint32_t t = 0;
 #pragma unroll
             for (int w = 0; w < P; ++w) t += part[64 * K * m + ol * P + w];
-            c[m] = ob[m] >= 0 ? 16u * t : 0u;
+            c[m] = ob[m] != kNoTarget ? 16u * t : 0u;
         }
         wave_sync();
     }
@@ -547,7 +548,7 @@ struct BinCoop {
 #pragma unroll
         for (int m = 0; m < N; ++m) {
             ty[m] = clampi(y + h[m].v, 0, H - 1);
-            ob[m] = w[m] ? addr(clampi(x + h[m].u - dirmul(s, h[m].d1), 0, W - 1), ty[m]) : -1;
+            ob[m] = w[m] ? addr(clampi(x + h[m].u - dirmul(s, h[m].d1), 0, W - 1), ty[m]) : kNoTarget;
         }
         if constexpr (XTS) {
             int o3[3 * N];
@@ -555,8 +556,8 @@ struct BinCoop {
 #pragma unroll
             for (int m = 0; m < N; ++m) {
                 o3[m] = ob[m];
-                o3[N + m] = w[m] ? addr(clampi(x + h[m].u, 0, W - 1), ty[m]) : -1;
-                o3[2 * N + m] = w[m] ? addr(clampi(x - dirmul(s, h[m].d0), 0, W - 1), y) : -1;
+                o3[N + m] = w[m] ? addr(clampi(x + h[m].u, 0, W - 1), ty[m]) : kNoTarget;
+                o3[2 * N + m] = w[m] ? addr(clampi(x - dirmul(s, h[m].d0), 0, W - 1), y) : kNoTarget;
             }
             ssdN<3 * N>([&](int m) { return m < N ? rX : m < 2 * N ? rT : rS; }, o3, c3);
 #pragma unroll
@@ -568,7 +569,7 @@ struct BinCoop {
         for (int m = 0; m < N; ++m) {
             al[m] = w[m] && c[m] < bound;
             any = any || al[m];
-            ob[m] = al[m] ? addr(clampi(x + h[m].u, 0, W - 1), ty[m]) : -1;
+            ob[m] = al[m] ? addr(clampi(x + h[m].u, 0, W - 1), ty[m]) : kNoTarget;
         }
         if (!__any(any)) return;
         uint32_t d[N];
@@ -579,7 +580,7 @@ struct BinCoop {
             c[m] += d[m];
             al[m] = al[m] && c[m] < bound;
             any = any || al[m];
-            ob[m] = al[m] ? addr(clampi(x - dirmul(s, h[m].d0), 0, W - 1), y) : -1;
+            ob[m] = al[m] ? addr(clampi(x - dirmul(s, h[m].d0), 0, W - 1), y) : kNoTarget;
         }
         if (!__any(any)) return;
         ssdN<N>([&](int) { return rS; }, ob, d);
