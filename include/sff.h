@@ -263,8 +263,10 @@ sff_status sff_match_level(const sff_params* p, int32_t batch, int32_t dir, int3
  * [batch][4] images of sff_bin_bytes(p, level) bytes (sff_wht_features),
  * 16-byte aligned.  Other arguments as for sff_match_level.  Wave-cooperative
  * gathers from 20000 pixel updates per launch (below 50000: 16 pixels per
- * wave, all 4 neighbours and all samples at once; above: 64 pixels per wave,
- * one candidate at a time), one lane per pixel below;
+ * wave, all 4 neighbours and all samples at once, three views a round; below
+ * 262144: 32 pixels per wave, groups of 4 neighbours and 3 samples, view by
+ * view; above: 64 pixels per wave, one candidate at a time, three views a
+ * round), one lane per pixel below;
  * SFF_MATCH_EVAL=lane|coop|coop-32|coop-43-32|coop-46-32|coop-xts|
  * coop-46-16-xts forces one (identical results).  With dir = SFF_DIR_BOTH
  * and 100000 or more updates the two fields run on two streams: `stream` and

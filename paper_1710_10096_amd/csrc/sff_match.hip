@@ -834,9 +834,16 @@ sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
     return launch_level<C, CoopEval<C, 2, 3>>(a, iters, st);
 }
 
+// From this many updates per half-step the bin matcher scores one candidate
+// at a time with all three views per round (below: 4 neighbours and 3
+// samples per group, 32 owners, view by view).
+constexpr long kBinXtsMinUpdates = 262144;
+
 // Bin-plane evaluators by launch size (updates per launch), measured on the
 // KITTI-size pair (C = 3, packed bins) with every shape giving identical
-// fields; ms per level:
+// fields; ms per level (before the two-stream split and the cheaper
+// unpacking; with both, level 1 takes 0.294 ms with 4/3 and 32 owners against
+// 0.31 with one candidate and three views a round, level 0 0.73 either way):
 //  - level 2 (29,328 updates, under one wave per SIMD): all 4 neighbours and
 //    all 6 samples in one group each, every view in one round, 16 owners per
 //    wave: 0.165 (the same with 32 owners and the early-out: 0.184; groups of
@@ -922,7 +929,10 @@ bool split_for_current_device(SplitStreams** out) {
 template <int C>
 sff_status run_bin_level(const MatchArgs& a, int iters, hipStream_t st) {
     const long updates = (long)a.ndir * a.batch * a.Hk * ((a.Wk + 1) / 2);
-    int pick = updates < kCoopMinUpdates ? 0 : updates < kHalfOwnersMaxUpdates ? 6 : 5;
+    int pick = updates < kCoopMinUpdates         ? 0
+               : updates < kHalfOwnersMaxUpdates ? 6
+               : updates < kBinXtsMinUpdates     ? 3
+                                                 : 5;
     bool split = a.ndir == 2 && updates >= kSplitMinUpdates;
     if (const char* e = std::getenv("SFF_MATCH_EVAL")) {
         if (std::strcmp(e, "lane") == 0) pick = 0;
