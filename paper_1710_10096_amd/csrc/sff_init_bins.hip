@@ -344,10 +344,11 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
                         if constexpr (!kInterior) k[e] = ok[e] ? k[e] : kNone;
                     }
                     if constexpr (K == 1) {
-                        const KT m = min(min(k[0], k[1]), min(k[2], k[3]));
-                        const bool better = m < S.best[t];
-                        S.btile[t] = better ? tile_id : S.btile[t];
-                        S.best[t] = better ? m : S.best[t];
+                        // the running minimum folded in (two 3-input minima), the
+                        // tile recorded when it strictly decreases
+                        const KT nb = min(min(S.best[t], k[0]), min(min(k[1], k[2]), k[3]));
+                        S.btile[t] = nb < S.best[t] ? tile_id : S.btile[t];
+                        S.best[t] = nb;
                     } else {
     #pragma unroll
                         for (int e = 0; e < 4; ++e) {
