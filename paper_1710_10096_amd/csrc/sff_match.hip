@@ -713,14 +713,16 @@ __global__ void __launch_bounds__(64) half_step_kernel(MatchArgs a, int it, int 
         const Hyp centre = best;
         const uint64_t seed = a.seeds[b];
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-        auto sample = [&](int t) {
-            const int r = max(1, a.rs_r0 >> t) * n;
+        auto draw = [&](int t, int col) {  // the Philox draws of sample t at grid column col
             U4 ctr;
-            ctr.x = (uint32_t)(i * a.Wk + jj);
+            ctr.x = (uint32_t)(i * a.Wk + col);
             ctr.y = (uint32_t)it;
             ctr.z = ((uint32_t)a.level << 16) | ((uint32_t)t << 8) | (s < 0 ? 1u : 0u);
             ctr.w = 0u;
-            const U4 rnd = philox4x32_10(ctr, k0, k1);
+            return philox4x32_10(ctr, k0, k1);
+        };
+        auto offset = [&](int t, const U4& rnd) {
+            const int r = max(1, a.rs_r0 >> t) * n;
             Hyp c;
             c.u = clampi(centre.u + uniform_offset(rnd.x, r), -a.fmax, a.fmax);
             c.v = clampi(centre.v + uniform_offset(rnd.y, r), -a.fmax, a.fmax);
@@ -728,15 +730,40 @@ __global__ void __launch_bounds__(64) half_step_kernel(MatchArgs a, int it, int 
             c.d1 = clampi(centre.d1 + uniform_offset(rnd.w, r), 0, a.dmax);
             return c;
         };
+        auto sample = [&](int t) { return offset(t, draw(t, jj)); };
         constexpr int kRS = E::kRG;
         for (int t = 0; t < a.rs_samples; t += kRS) {
             if (kRS > 1 && t + kRS <= a.rs_samples) {
                 Hyp cg[kRS];
                 bool wg[kRS];
                 bool any = false;
+                if constexpr (O < 64) {
+                    // the lanes past the owners draw too: lane group g = lane / O
+                    // draws sample t + LG p + g of owner lane mod O in pass p, and
+                    // each owner collects its draws by shuffles (the same numbers,
+                    // fewer Philox evaluations per lane)
+                    constexpr int LG = 64 / O, NP = (kRS + LG - 1) / LG;
+                    const int og = lane % O, grp = lane / O;
+                    const int col = min(step * (tx * O + og) + par, a.Wk - 1);
+                    U4 rr[NP];
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) rr[p] = draw(t + LG * p + grp, col);
+#pragma unroll
+                    for (int m = 0; m < kRS; ++m) {
+                        const int src = (m % LG) * O + og;
+                        U4 d;
+                        d.x = (uint32_t)__shfl((int)rr[m / LG].x, src);
+                        d.y = (uint32_t)__shfl((int)rr[m / LG].y, src);
+                        d.z = (uint32_t)__shfl((int)rr[m / LG].z, src);
+                        d.w = (uint32_t)__shfl((int)rr[m / LG].w, src);
+                        cg[m] = offset(t + m, d);
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < kRS; ++m) cg[m] = sample(t + m);
+                }
 #pragma unroll
                 for (int m = 0; m < kRS; ++m) {
-                    cg[m] = sample(t + m);
                     wg[m] = act && !same(cg[m], centre);
                     any = any || wg[m];
                 }
