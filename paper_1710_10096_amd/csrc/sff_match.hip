@@ -445,7 +445,7 @@ struct BinCoop {
     static constexpr int kOwners = O;
     static constexpr int kPG = PG, kRG = RG;
     static constexpr int kGroup = PG > RG ? PG : RG;
-    static constexpr int kLdsWords = kGroup * (XTS ? 3 : 1) * 64 * K;
+    static constexpr int kLdsWords = kGroup * 64 * K;
     static constexpr bool kGroups = true;
     __amdgpu_buffer_rsrc_t rR, rT, rS, rX;
     BinAddr<C> addr;
@@ -525,6 +525,46 @@ struct BinCoop {
         wave_sync();
     }
 
+    // The cross, temporal and stereo distances (x 16) summed, of N candidates
+    // per owner: the 3 N patches of ob (cross ones first, then temporal, then
+    // stereo; a candidate without a target has kNoTarget in all three, result
+    // 0) gathered together, and a slot's three pieces summed before the
+    // partials go through LDS.  Must be called by all lanes of the wave.
+    template <int N>
+    __device__ __forceinline__ void ssd_views(const int (&ob)[3 * N], uint32_t (&c)[3 * N]) {
+        uint4 v[3 * N][K];
+        int so[3 * N][K];
+#pragma unroll
+        for (int m = 0; m < 3 * N; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k) so[m][k] = slot_off(ob[m], k);
+#pragma unroll
+        for (int m = 0; m < 3 * N; ++m) {
+            const __amdgpu_buffer_rsrc_t rs = m < N ? rX : m < 2 * N ? rT : rS;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                v[m][k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, so[m][k], 0, 0));
+        }
+#pragma unroll
+        for (int m = 0; m < N; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                int acc = bin_piece_ssd<C>(refp[k], v[m][k], 0);
+                acc = bin_piece_ssd<C>(refp[k], v[N + m][k], acc);
+                part[64 * (m * K + k) + lane] = (uint32_t)bin_piece_ssd<C>(refp[k], v[2 * N + m][k], acc);
+            }
+        wave_sync();
+        const int ol = lane & (O - 1);  // lanes past the owners read a valid slot
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int w = 0; w < P; ++w) t += part[64 * K * m + ol * P + w];
+            c[m] = ob[m] != kNoTarget ? 16u * t : 0u;
+        }
+        wave_sync();
+    }
+
     __device__ __forceinline__ uint32_t cost_below(bool want, int x, int y, const Hyp& h,
                                                    uint32_t bound) {
         bool w[1] = {want};
@@ -559,9 +599,9 @@ struct BinCoop {
                 o3[N + m] = w[m] ? addr(clampi(x + h[m].u, 0, W - 1), ty[m]) : kNoTarget;
                 o3[2 * N + m] = w[m] ? addr(clampi(x - dirmul(s, h[m].d0), 0, W - 1), y) : kNoTarget;
             }
-            ssdN<3 * N>([&](int m) { return m < N ? rX : m < 2 * N ? rT : rS; }, o3, c3);
+            ssd_views<N>(o3, c3);
 #pragma unroll
-            for (int m = 0; m < N; ++m) c[m] = c3[m] + c3[N + m] + c3[2 * N + m];
+            for (int m = 0; m < N; ++m) c[m] = c3[m];
             return;
         }
         ssdN<N>([&](int) { return rX; }, ob, c);
