@@ -27,20 +27,29 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak, vendor figure
 # Per-launch HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs, calibrated against a copy of known size.  The file records a
-# hash of the kernel sources it was measured with; any later edit of those
-# sources makes the figure stale and it is reported as null.
+# hash of the kernel sources it was measured with (their code: comments and
+# blank space are left out); any later change of that code makes the figure
+# stale and it is reported as null.
 KERNEL_COUNTERS = os.path.join(ROOT, "profiles", "half_step_kernel_kitti_counters.txt")
 KERNEL_SOURCES = ["paper_1710_10096_amd/csrc/sff_match.hip",
                   "paper_1710_10096_amd/csrc/sff_device.hpp",
                   "paper_1710_10096_amd/csrc/sff_internal.hpp"]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank space (string literals kept)."""
+    import re
+    pat = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\])*"', re.S)
+    text = pat.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

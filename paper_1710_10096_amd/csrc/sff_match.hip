@@ -906,30 +906,31 @@ sff_status run_level(const MatchArgs& a, int iters, hipStream_t st) {
 // samples per group, 32 owners, view by view).
 constexpr long kBinXtsMinUpdates = 262144;
 
-// Bin-plane evaluators by launch size (updates per launch), measured on the
-// KITTI-size pair (C = 3, packed bins) with every shape giving identical
-// fields; ms per level (before the two-stream split and the cheaper
-// unpacking; with both, level 1 takes 0.294 ms with 4/3 and 32 owners against
-// 0.31 with one candidate and three views a round, level 0 0.73 either way):
+// Bin-plane evaluators by launch size (updates per half-step), measured on the
+// KITTI-size pair (C = 3, packed bins, fields on two streams from 100,000
+// updates) with every shape giving identical fields; ms per level:
 //  - level 2 (29,328 updates, under one wave per SIMD): all 4 neighbours and
 //    all 6 samples in one group each, every view in one round, 16 owners per
-//    wave: 0.165 (the same with 32 owners and the early-out: 0.184; groups of
-//    2 and 3 with 64 owners: 0.25) -- a lone wave's chain of dependent round
-//    trips is what these launches wait on, so the shape with the fewest
-//    rounds and the most waves wins;
-//  - level 1 (116,936 updates) and level 0 (465,750): one candidate at a
-//    time with its three views in one round, 64 owners: 0.347 and 0.962
-//    (groups of 2 and 3 with the early-out between views: 0.352-0.37 and
-//    0.98-1.05; 4 and 3 with 32 owners: 0.372 and 1.13).  The early-out
-//    rejects only ~15 % of candidates at the cross view, so a round per view
-//    buys little texture-path work and costs two round trips.
+//    wave: 0.16 (32 owners with the view-by-view early-out: 0.18; groups of
+//    2 and 3 with 64 owners: 0.24) -- a lone wave's chain of dependent round
+//    trips is what these launches wait on, so the fewest rounds and the most
+//    waves win;
+//  - level 1 (116,936 updates): groups of 4 neighbours and 3 samples, view by
+//    view, 32 owners: 0.29 (one candidate with three views a round, 64
+//    owners: 0.31);
+//  - level 0 (465,750 updates): one candidate at a time with its three views
+//    in one round, 64 owners: 0.73 (groups of 2 and 3 with the early-out:
+//    0.73; 32 owners: 0.88-0.97).  This level is bound by the vector ALU
+//    (unpacking and squared distances of the gathered pieces), and the
+//    early-out rejects only ~15 % of candidates at the cross view, so a round
+//    per view saves little.
 // Other tile orders were slower (row-major 1.10 ms at level 0, no XCD
-// grouping 1.37 ms).  Below 20,000 updates each lane gathers its own patches.
-// SFF_MATCH_EVAL = "lane", "coop" (2/3, 64 owners, early-out), "coop-32",
-// "coop-43-32", "coop-46-32" (32 owners, early-out), "coop-xts" (1/1, 64
-// owners, three views a round) or "coop-46-16-xts" forces one (all give
-// identical results; 16-owner shapes need 4 pieces a patch, C >= 2, and fall
-// back to "coop-46-32" otherwise); anything else: auto.
+// grouping 1.37 ms, with unpacked patches).  Below 20,000 updates each lane
+// gathers its own patches.  SFF_MATCH_EVAL = "lane", "coop" (2/3, 64 owners,
+// early-out), "coop-32", "coop-43-32", "coop-46-32" (32 owners, early-out),
+// "coop-xts" (1/1, 64 owners, three views a round) or "coop-46-16-xts" forces
+// one (all give identical results; 16-owner shapes need 4 pieces a patch,
+// C >= 2, and fall back to "coop-46-32" otherwise); anything else: auto.
 template <int C>
 sff_status launch_bin_pick(int pick, const MatchArgs& a, int iters, hipStream_t st) {
     switch (pick) {
@@ -952,9 +953,10 @@ sff_status launch_bin_pick(int pick, const MatchArgs& a, int iters, hipStream_t 
 // the library, joined to the caller's by events before and after.  A launch
 // that drains (its last waves finishing while most compute units idle) then
 // overlaps the other field's launch instead of the next half-step waiting for
-// it: level 0 of the KITTI-size pair 0.96 -> 0.82 ms, level 1 0.345 -> 0.334;
-// below ~100,000 updates (level 2: 0.167 vs 0.176 ms) one launch per
-// half-step for both fields is faster.  Identical fields either way.
+// it: level 0 of the KITTI-size pair 0.96 -> 0.82 ms, level 1 0.345 -> 0.334
+// (measured with 18-operation unpacking); below ~100,000 updates (level 2:
+// 0.167 vs 0.176 ms) one launch per half-step for both fields is faster.
+// Identical fields either way.
 constexpr long kSplitMinUpdates = 100000;
 
 constexpr int kMaxSplitDevices = 64;
