@@ -580,14 +580,27 @@ __device__ __forceinline__ void fused_layer32(const bf16_t* in, bf16_t* out, con
             acc[h][0] = v4f{0.f, 0.f, 0.f, 0.f};
             acc[h][1] = v4f{0.f, 0.f, 0.f, 0.f};
         }
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
+        // the B operands of tap t + kAhead are read from LDS while tap t's
+        // products run (a ring of kAhead + 1 taps), so the LDS latency is not
+        // waited on at every tap
+        constexpr int kAhead = 3;
+        v8bf bv[kAhead + 1][2];
+        auto read_tap = [&](int tap, v8bf (&b)[2]) {
             const int ky = tap / 3, kx = tap - 3 * ky;
 #pragma unroll
+            for (int h = 0; h < 2; ++h) b[h] = src[h][(ky * IW + kx) * kFPx / 8];
+        };
+#pragma unroll
+        for (int tap = 0; tap < kAhead; ++tap) read_tap(tap, bv[tap]);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            if (tap + kAhead < 9) read_tap(tap + kAhead, bv[(tap + kAhead) % (kAhead + 1)]);
+            __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the products
+            const v8bf (&b)[2] = bv[tap % (kAhead + 1)];
+#pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const v8bf bv = src[h][(ky * IW + kx) * kFPx / 8];
-                acc[h][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][tap], bv, acc[h][0], 0, 0, 0);
-                acc[h][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][tap], bv, acc[h][1], 0, 0, 0);
+                acc[h][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][tap], b[h], acc[h][0], 0, 0, 0);
+                acc[h][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][tap], b[h], acc[h][1], 0, 0, 0);
             }
         }
 #pragma unroll
