@@ -511,7 +511,12 @@ bool staged_conv_enabled() {
 // rounded to BF16 as the per-layer kernels store it, and each output element
 // is the same MFMAs in the same order on the same values as conv3_fwd_kernel
 // and conv32_fwd_kernel, so the results are identical (tested).
-constexpr int kFusedX = 64, kFusedY = 8;
+// Tiles are 26 wide so that every layer's region is at most two 16-pixel
+// groups wide (32, 30, 28 and 26 pixels: 15 % of the computed groups fall
+// outside a region, against 22 % for 64-wide tiles) and 24 tall, the most that
+// fits 150 KB of LDS with that width (four KITTI-size images: 0.35 ms with
+// 64 x 8 tiles, 0.31 with 58 x 10, 0.28 with 42 x 15, 0.27 with 26 x 24).
+constexpr int kFusedX = 26, kFusedY = 24;
 constexpr int kFIn[2] = {kFusedY + 8, kFusedX + 8};   // input region (3 channels, packed)
 constexpr int kF1[2] = {kFusedY + 6, kFusedX + 6};    // layer-1 output (and layer 3's, in place later)
 constexpr int kF2[2] = {kFusedY + 4, kFusedX + 4};    // layer-2 output

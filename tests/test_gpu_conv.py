@@ -161,12 +161,14 @@ def test_first_layer_kernel_same_as_im2col(sff, case, monkeypatch):
     assert _within_bf16_ulp(_np(y), ref, S).all()
 
 
-FUSED_CASES = [(1, 1, 1), (2, 9, 70), (1, 8, 64), (1, 17, 131), (3, 23, 200), (1, 40, 270)]
+FUSED_CASES = [(1, 1, 1), (2, 9, 70), (1, 8, 64), (1, 17, 131), (3, 23, 200), (1, 40, 270),
+               # exact tiles of 24 x 26 outputs, one pixel past them, several of each
+               (1, 24, 26), (2, 25, 27), (1, 49, 79), (1, 72, 52)]
 
 
 @pytest.mark.parametrize("case", FUSED_CASES, ids=[str(c) for c in FUSED_CASES])
 def test_fused_network_forward_same_as_layers(sff, case):
-    """The four layers in one launch (activations on chip, tiles of 8 x 64
+    """The four layers in one launch (activations on chip, tiles of 24 x 26
     outputs, ragged edges) against the four per-layer calls, bit for bit;
     the last layer against the FP64 oracle on the per-layer path's layer-3
     output."""
