@@ -79,3 +79,15 @@ def test_host_cpu_record():
     h = bench.host_cpu()
     assert isinstance(h["model"], str) and h["model"]
     assert h["logical_cpus"] >= h["usable_cpus"] >= 1
+
+
+def test_source_hash_ignores_comments_only():
+    """The traffic figure is keyed to the kernel code: comments and blank
+    space do not change the hash, code (string literals included) does."""
+    a = 'int f(int x) {  // doubled\n    return 2 * x; /* fast */ }\nconst char* s = "//kept";\n'
+    b = 'int f(int x) {\n\n  return 2 * x;  }\nconst char* s = "//kept";  // new note\n'
+    c = 'int f(int x) { return 3 * x; }\nconst char* s = "//kept";\n'
+    d = 'int f(int x) { return 2 * x; }\nconst char* s = "//other";\n'
+    assert bench._code_only(a) == bench._code_only(b)
+    assert bench._code_only(a) != bench._code_only(c)
+    assert bench._code_only(a) != bench._code_only(d)
