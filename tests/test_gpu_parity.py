@@ -415,6 +415,41 @@ def test_pipeline_ragged_batch_on_side_stream(sff, split, monkeypatch):
         _check_pipeline(sff, scenes, p, [5, 6, 7], stream=st)
 
 
+def test_pipeline_graph_replay(sff, monkeypatch):
+    """The whole stage captured in a HIP graph (the two fields of every level
+    on two streams, forced, so the helper stream joins the capture) and
+    replayed three times, with eager work and synchronisations between the
+    replays: every replay equals the eager run, which equals the oracle."""
+    import torch
+    monkeypatch.setenv("SFF_MATCH_SPLIT", "1")
+    p = params_dict(53, 91, 3, levels=3, iters=2, fmax=24, dmax=20)
+    scenes = [make_scene(small_spec(53, 91, 3, 700 + b, flow_max=12, d_range=(0, 16))) for b in range(2)]
+    _say("pipeline graph replay, split forced")
+    out = _check_pipeline(sff, scenes, p, [8, 9])
+    m = sff.PairMatcher(p, 2)
+    imgs = dev(_imgs_stack(scenes))
+    seeds = dev(np.array([8, 9], np.int64))
+    m.run(imgs, seeds)  # eager first: the library's helper stream exists before capture
+    torch.cuda.synchronize()
+    ref = {k: host(v).copy() for k, v in out.items() if k in ("hyp", "cost", "valid", "err")}
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            m.run(imgs, seeds, stream=s)
+    torch.cuda.synchronize()
+    for i in range(3):
+        m.hyp[0].zero_()
+        m.valid.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in ref:
+            v = {"hyp": m.hyp[0], "cost": m.cost[0], "valid": m.valid, "err": m.err}[k]
+            assert np.array_equal(host(v), ref[k]), (i, k)
+
+
 PIPE_KERNELS = [("bins", "auto"), ("bins", "auto+nosplit"), ("bins", "lane"), ("bins", "coop"),
                 ("bins", "coop-32"),
                 ("bins", "coop-43-32"), ("bins", "coop-46-32"), ("bins", "coop-xts"),
