@@ -19,8 +19,8 @@
  *    caller's next synchronisation.
  *  - The library is thread-safe.  Its state, per device, is the fixed scratch
  *    array of sff_wht_features_noalloc and one helper stream with two events
- *    (sff_match_level_bins), created on first use and kept until the process
- *    ends.
+ *    (sff_match_level_bins, sff_cost_f32_bwd), created on first use and kept
+ *    until the process ends.
  *
  * Data layouts (row-major)
  *  - image  uint8  [n][H][W][C]                 C = 1..4 channels
@@ -480,7 +480,10 @@ size_t sff_cost_f32_bwd_workspace_bytes(int32_t batch, int32_t H, int32_t W);
  * fully overwritten.  Deterministic: the same inputs give the same bits.
  * Each gradient entry is gathered by cf / 4 lanes, four channels each;
  * SFF_COST_F32_EVAL=lane gathers with one lane per entry (same bits; testing
- * and timing).
+ * and timing).  The reference-map gradient runs on the library's helper
+ * stream beside the target-map gradients, joined to `stream` before the call
+ * returns as for sff_match_level_bins (SFF_COST_F32_SPLIT=0: all on `stream`;
+ * same bits).
  * workspace: device buffer, 256-byte aligned, at least
  *   sff_cost_f32_bwd_workspace_bytes(batch, H, W) bytes.
  * Errors: SFF_ERR_INVALID_ARG, SFF_ERR_WORKSPACE. */

@@ -1031,12 +1031,25 @@ extern "C" sff_status sff_cost_f32_bwd(int32_t batch, int32_t H, int32_t W, int3
     const dim3 grid((W + 63) / 64, (H + 3) / 4, batch);
     // maps below 2 GiB are read through 32-bit buffer offsets
     const bool buf = (size_t)H * W * cf * 4 <= (size_t)kSkipOff;
+    // The reference-map gradient and the target-map gradients (with the
+    // grouping they need) read the same inputs and write different maps, so
+    // the reference gradient runs on the library's helper stream beside them
+    // (SFF_COST_F32_SPLIT=0: one stream; identical results either way).
+    const char* sp = std::getenv("SFF_COST_F32_SPLIT");
+    std::unique_lock<std::mutex> lock(helper_lock(), std::defer_lock);
+    HelperStream* hs = nullptr;
+    if (!(sp && std::strcmp(sp, "0") == 0)) {
+        lock.lock();
+        hs = helper_for_current_device();
+        if (hs && !helper_fork(hs, st)) return SFF_ERR_HIP;
+    }
+    hipStream_t sr = hs ? hs->stream : st;
     if (lane_grad)
-        launch_cf<RefK>(cf, grid, st, a);
+        launch_cf<RefK>(cf, grid, sr, a);
     else if (buf)
-        launch_cf<RefTileK>(cf, dim3((unsigned)((size_t)batch * H * tiles_x)), st, a, tiles_x);
+        launch_cf<RefTileK>(cf, dim3((unsigned)((size_t)batch * H * tiles_x)), sr, a, tiles_x);
     else
-        launch_cf<RefTileWideK>(cf, dim3((unsigned)((size_t)batch * H * tiles_x)), st, a, tiles_x);
+        launch_cf<RefTileWideK>(cf, dim3((unsigned)((size_t)batch * H * tiles_x)), sr, a, tiles_x);
     // group the pixels by target centre: keys, then a stable radix sort
     const size_t N = L.N;
     hipLaunchKernelGGL(target_keys_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, hyp,
@@ -1068,5 +1081,7 @@ extern "C" sff_status sff_cost_f32_bwd(int32_t batch, int32_t H, int32_t W, int3
         launch_cf<TgtTileWideK>(cf, dim3((unsigned)((size_t)3 * batch * H * tiles_x)), st, a, tiles_x, n,
                                 (const uint32_t*)start, (const uint32_t*)kin, (const uint32_t*)vin);
     }
-    return launch_status();
+    const sff_status r = launch_status();
+    if (hs && !helper_join(hs, st)) return SFF_ERR_HIP;
+    return r;
 }

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 
 #include "sff.h"
 
@@ -135,5 +136,21 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
 __device__ __forceinline__ int uniform_offset(uint32_t x, int r) {
     return (int)(((uint64_t)x * (uint64_t)(2 * r + 1)) >> 32) - r;
 }
+
+// The library's helper stream of the current device (default priority, not
+// blocking on the null stream, created on first use and kept until the
+// process ends) with a fork and a join event, for a call that runs two
+// independent launch sequences concurrently: helper_fork makes the helper
+// wait for the work enqueued on st so far, helper_join makes st wait for the
+// helper's.  Callers hold helper_lock() from the fork to the join (the events
+// are shared); helper_for_current_device returns null on a runtime error.
+struct HelperStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex& helper_lock();
+HelperStream* helper_for_current_device();
+bool helper_fork(HelperStream* h, hipStream_t st);
+bool helper_join(HelperStream* h, hipStream_t st);
 
 }  // namespace sff

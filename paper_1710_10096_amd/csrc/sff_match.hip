@@ -26,7 +26,6 @@
 // and the gathers mostly hit the L2 instead of streaming records.
 #include <cstdlib>
 #include <cstring>
-#include <mutex>
 
 #include "sff_device.hpp"
 
@@ -959,39 +958,6 @@ sff_status launch_bin_pick(int pick, const MatchArgs& a, int iters, hipStream_t 
 // Identical fields either way.
 constexpr long kSplitMinUpdates = 100000;
 
-constexpr int kMaxSplitDevices = 64;
-struct SplitStreams {
-    hipStream_t helper = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-};
-std::mutex split_mutex;
-SplitStreams split_streams[kMaxSplitDevices];
-
-// The current device's helper stream and events, created on first use
-// (default priority, not blocking on the null stream); false on a runtime
-// error (the caller then runs both fields in one launch sequence).
-bool split_for_current_device(SplitStreams** out) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxSplitDevices) return false;
-    SplitStreams& s = split_streams[dev];
-    if (!s.helper) {
-        hipStream_t h = nullptr;
-        hipEvent_t f = nullptr, j = nullptr;
-        if (hipStreamCreateWithFlags(&h, hipStreamNonBlocking) != hipSuccess) return false;
-        if (hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
-            if (f) (void)hipEventDestroy(f);
-            (void)hipStreamDestroy(h);
-            return false;
-        }
-        s.helper = h;
-        s.fork = f;
-        s.join = j;
-    }
-    *out = &s;
-    return true;
-}
-
 // SFF_MATCH_SPLIT = "0" or "1" forces one launch sequence for both fields or
 // the two-stream split (identical results; the switch exists to test and time
 // both); anything else: by launch size.
@@ -1026,16 +992,14 @@ sff_status run_bin_level(const MatchArgs& a, int iters, hipStream_t st) {
     f1.hyp = a.hyp + 4 * fine;
     f1.cost = a.cost + fine;
     if (a.hyp_coarse) f1.hyp_coarse = a.hyp_coarse + 4 * coarse;
-    std::lock_guard<std::mutex> lock(split_mutex);  // the events are shared by callers
-    SplitStreams* ss = nullptr;
-    if (!split_for_current_device(&ss)) return launch_bin_pick<C>(pick, a, iters, st);
-    if (hipEventRecord(ss->fork, st) != hipSuccess || hipStreamWaitEvent(ss->helper, ss->fork, 0) != hipSuccess)
-        return SFF_ERR_HIP;
+    std::lock_guard<std::mutex> lock(helper_lock());
+    HelperStream* hs = helper_for_current_device();
+    if (!hs) return launch_bin_pick<C>(pick, a, iters, st);
+    if (!helper_fork(hs, st)) return SFF_ERR_HIP;
     const sff_status r0 = launch_bin_pick<C>(pick, f0, iters, st);
-    const sff_status r1 = launch_bin_pick<C>(pick, f1, iters, ss->helper);
+    const sff_status r1 = launch_bin_pick<C>(pick, f1, iters, hs->stream);
     // join even after a launch error, so the caller's stream never runs ahead
-    if (hipEventRecord(ss->join, ss->helper) != hipSuccess || hipStreamWaitEvent(st, ss->join, 0) != hipSuccess)
-        return SFF_ERR_HIP;
+    if (!helper_join(hs, st)) return SFF_ERR_HIP;
     return r0 != SFF_OK ? r0 : r1;
 }
 
