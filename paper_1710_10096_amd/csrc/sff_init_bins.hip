@@ -313,11 +313,16 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
                 constexpr bool kInterior = decltype(interior)::value;
                 constexpr bool kRowsIn = decltype(rows_in)::value;
                 bool ok[4] = {true, true, true, true};
+                // fp32 keys: a candidate outside the box or the image gets an
+                // infinite norm once per tile, so its keys come out infinite
+                // (the kNone of this form) in every row without a select each
+                float bq[4] = {cur.bsq[0], cur.bsq[1], cur.bsq[2], cur.bsq[3]};
                 if constexpr (!kInterior) {
     #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int jc = c0 + 4 * g + e;
                         ok[e] = (unsigned)(jc - jq + F) <= (unsigned)(2 * F) && (unsigned)jc < (unsigned)Wk;
+                        if constexpr (kFloat) bq[e] = ok[e] ? bq[e] : __builtin_huge_valf();
                     }
                 }
     #pragma unroll
@@ -337,11 +342,11 @@ __global__ void __launch_bounds__(256) init_bins_kernel(BinInitArgs a, OpPlanes 
                     for (int e = 0; e < 4; ++e) {
                         // |b'|^2 + (-2 a'.b'), the product exact in fp32
                         if constexpr (kFloat) {
-                            k[e] = cur.bsq[e] + acc[e];
+                            k[e] = bq[e] + acc[e];
                         } else {
                             k[e] = (int)cur.bsq[e] + (int)acc[e];
+                            if constexpr (!kInterior) k[e] = ok[e] ? k[e] : kNone;
                         }
-                        if constexpr (!kInterior) k[e] = ok[e] ? k[e] : kNone;
                     }
                     if constexpr (K == 1) {
                         // the running minimum folded in (two 3-input minima), the
