@@ -167,6 +167,25 @@ def test_many_tiles_identical_to_one_lane(sff, monkeypatch):
     assert np.array_equal(grad, lane)
 
 
+def test_backward_on_one_stream_identical(sff, monkeypatch):
+    """The backward with the reference map's gradient on the helper stream
+    (default) against everything on the caller's stream (SFF_COST_F32_SPLIT=0):
+    the maps' gradients are disjoint outputs of the same kernels, so the bits
+    agree; two pairs, C = 32, several tiles a row."""
+    F, hyp, g = _random_case(78, 2, 60, 200, 32, spread=12)
+    _say("cost_f32 backward split vs one stream")
+    monkeypatch.delenv("SFF_COST_F32_EVAL", raising=False)
+    monkeypatch.delenv("SFF_COST_F32_SPLIT", raising=False)
+    split = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), -1, _dev(g)).cpu().numpy()
+    monkeypatch.setenv("SFF_COST_F32_SPLIT", "0")
+    one = sff.sff_cost_f32_bwd(_dev(F), _dev(hyp), -1, _dev(g)).cpu().numpy()
+    assert np.array_equal(split, one)
+    Fb = [F[1, m].astype(np.float64) for m in range(4)]
+    G = ocf.window_cost_grad(Fb, hyp[1], -1, g[1])
+    for m in range(4):
+        assert _grad_close(split[1, m], G[m]).all(), m
+
+
 def test_crowded_centres_use_the_global_lists(sff, monkeypatch):
     """Vectors that send whole rows to one centre cell (u far to the left,
     clamped to column 0): the cells of the first tile of a row hold about
